@@ -1,0 +1,204 @@
+"""Benchmark: 3D Ising HOTRG, chi = 16, T = 4.5115 on one MI355X.
+
+One "step" is one whole coarse-graining step at saturated bond dimensions (Gram
+matrices, FP64 eigendecomposition, choice, prime chain, bottleneck contraction,
+non-prime chain, trace and normalisation), everything on the GPU through the C ABI.
+
+Prints one JSON line: contraction TFLOP/s (algorithmic flops of the new-tensor
+contraction / its measured time) for the headline precision form, RG steps/s, the
+roofline of the bottleneck GEMM (the dominant kernel), the free-energy error against
+the stored FP64 oracle fixture, the same figures for the FP64 form, and the oracle
+timed on a bounded sample on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form split_fp16] [--no-cpu]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "3D HOTRG chi=16 contraction TFLOP/s + RG steps/s, MFMA vs FP64 at |df|<1e-6"
+CHI, TEMP, STEPS_FIXTURE = 16, 4.5115, 25
+UNSATURATED = 3            # steps 1-3 have bond dims below chi (untruncated)
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6, "fp16": 2516.6,
+               "split_bf16": 2516.6, "split_fp16": 2516.6}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16 (f32 acc)", "fp16": "f16 (f32 acc)",
+         "split_bf16": "bf16x3 hi/lo split (f32 acc)", "split_fp16": "f16x3 hi/lo split (f32 acc)"}
+PRODUCTS = {"split_bf16": 3, "split_fp16": 3}
+
+
+def fixture_lnz():
+    path = os.path.join(ROOT, "tests", "golden", "config3.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        fx = json.load(f)
+    return [s["lnz_per_site"] for s in fx["runs"][0]["steps"]]
+
+
+def run_form(P, torch, form, steps, warmup):
+    """Full run in one precision form; times exactly `steps` saturated steps."""
+    beta = 1.0 / TEMP
+    total = max(STEPS_FIXTURE, UNSATURATED + warmup + steps)
+    r = P.HOTRG("ising", 3, beta, CHI, precision=form, max_steps=total)
+    lnz = []
+    for _ in range(UNSATURATED + warmup):
+        r.step()
+    lnz_hist = None
+    torch.cuda.synchronize()
+    r.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r.step()
+    r.log_z()                      # synchronises the library's stream
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = r.timings()
+    r.profile(False)
+    while r.steps < total:
+        r.step()
+    final = r.log_z()
+    # per-step lnZ/V from the step records
+    lnz = [r.info(p).lnz_per_site for p in range(1, total + 1)]
+    r.close()
+    return dict(wall=wall, timings=tm, lnz=lnz, final=final, total_steps=total)
+
+
+def cpu_baseline(sample_pairs=16):
+    """The FP64 oracle on the host: a bounded sample of one saturated chi = 16 step --
+    the new-tensor contraction restricted to `sample_pairs` of the 256 (n'_1, n'_2)
+    slices, on a seeded random tensor (the cost does not depend on the values)."""
+    import numpy as np
+    from oracle import hotrg as H
+    from tests import seeded_inputs as SI
+    T = SI.random_tensor((CHI,) * 6, seed=0)
+    U1 = SI.random_isometry(CHI * CHI, CHI, seed=1)
+    U2 = SI.random_isometry(CHI * CHI, CHI, seed=2)
+    picks = [(i // CHI, i % CHI) for i in range(0, CHI * CHI, (CHI * CHI) // sample_pairs)][:sample_pairs]
+    t0 = time.perf_counter()
+    H.new_tensor(T, {1: U1, 2: U2}, only=picks)
+    dt = time.perf_counter() - t0
+    frac = len(picks) / float(CHI * CHI)
+    flops = 2.0 * (CHI ** 11 + 2 * CHI ** 9 + 2 * CHI ** 8) * frac
+    threads = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        info = [x for x in threadpool_info() if x.get("user_api") == "blas"]
+        if info:
+            threads = info[0].get("num_threads", threads)
+    except Exception:
+        pass
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(picks)}/256 (n'_1, n'_2) slices of one saturated chi=16 new-tensor contraction "
+                      f"(FP64 NumPy, {dt:.1f} s); full-step estimate {dt / frac:.0f} s/step",
+            "seconds_per_step_estimate": dt / frac}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--form", default="split_fp16")
+    ap.add_argument("--reference-form", default="fp64")
+    ap.add_argument("--reference-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of the "
+              "contraction is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2110_03607_amd as P
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    P.lib()
+    ref_lnz = fixture_lnz()
+
+    head = run_form(P, torch, args.form, args.steps, args.warmup)
+    tm = head["timings"]
+    ms_per_step = head["wall"] * 1e3 / args.steps
+    contract_ms = tm["contract"]["ms"]
+    contract_tflops = tm["flops_contract"] / (contract_ms * 1e-3) / 1e12
+    bott_ms_avg = tm["bottleneck"]["ms"] / max(1, tm["bottleneck"]["count"])
+    bott_flops_per_launch = tm["flops_bottleneck"] / max(1, tm["bottleneck"]["count"])
+    bott_tflops = bott_flops_per_launch / (bott_ms_avg * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.form]
+    err = None
+    if ref_lnz is not None:
+        n = min(len(ref_lnz), len(head["lnz"]))
+        err = max(abs(head["lnz"][i] - ref_lnz[i]) / abs(ref_lnz[i]) for i in range(n))
+        err_final = abs(head["lnz"][n - 1] - ref_lnz[n - 1]) / abs(ref_lnz[n - 1])
+
+    ref = run_form(P, torch, args.reference_form, args.reference_steps, 0)
+    rtm = ref["timings"]
+    ref_ms_per_step = ref["wall"] * 1e3 / args.reference_steps
+    ref_contract_tflops = rtm["flops_contract"] / (rtm["contract"]["ms"] * 1e-3) / 1e12
+    ref_err = None
+    if ref_lnz is not None:
+        n = min(len(ref_lnz), len(ref["lnz"]))
+        ref_err = max(abs(ref["lnz"][i] - ref_lnz[i]) / abs(ref_lnz[i]) for i in range(n))
+
+    out = {
+        "metric": METRIC,
+        "value": round(contract_tflops, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.form],
+        "data": "synthetic",
+        "config": {"workload": "3D Ising HOTRG, chi=16, T=4.5115, J=1, h=0; steps 1-3 unsaturated, "
+                               f"timed steps {UNSATURATED + args.warmup + 1}-{UNSATURATED + args.warmup + args.steps}",
+                   "form": args.form, "chi": CHI, "d": 3},
+        "steps_per_s": round(1e3 / ms_per_step, 4),
+        "contract_flops_per_step": tm["flops_contract"] / args.steps,
+        "free_energy_rel_err_vs_oracle": err,
+        "free_energy_rel_err_final": err_final if ref_lnz is not None else None,
+        "phase_ms_per_step": {k: round(tm[k]["ms"] / args.steps, 3) for k in P.TIMING_PHASES},
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "k_gemm_tn (bottleneck, eq. BottleneckPart)",
+            "achieved": round(bott_tflops, 3),
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": round(bott_tflops / peak, 4),
+            "issued_frac": round(bott_tflops * PRODUCTS.get(args.form, 1) / peak, 4),
+            "avg_launch_ms": round(bott_ms_avg, 4),
+            "launches": tm["bottleneck"]["count"],
+            "traffic": None,
+        },
+        "fp64_reference": {
+            "form": args.reference_form,
+            "ms_per_step": round(ref_ms_per_step, 3),
+            "steps_per_s": round(1e3 / ref_ms_per_step, 4),
+            "contract_tflops": round(ref_contract_tflops, 3),
+            "free_energy_rel_err_vs_oracle": ref_err,
+            "speedup_of_headline_form": round(ref_ms_per_step / ms_per_step, 3),
+        },
+    }
+    if not args.no_cpu:
+        cb = cpu_baseline()
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"]["value"] = round(cb["value"], 5)
+        out["speedup_vs_oracle_steps"] = round(cb["seconds_per_step_estimate"] / (ms_per_step * 1e-3), 1)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * hotrg.h -- C ABI of the MI355X HOTRG coarse-graining library (libhotrg.so).
+ *
+ * The library runs the Higher Order Tensor Renormalization Group of
+ * Yamashita & Sakurai (arXiv 2110.03607) on one gfx950 GPU: the Gram matrices
+ * that decide the truncation (Sections 3.2 and 4.2.4), their eigendecomposition
+ * (Section 4.2.5), the choice and truncation of the isometries (Sections 2,
+ * 4.2.6-4.2.7), the new-tensor contraction in the prime chain / bottleneck /
+ * non-prime chain order (Section 4.2.8, eqs. TU1-TUNCD, BottleneckPart,
+ * AfterBNNCD-AfterBN1), the renaming of Section 3.1.3, and the lnZ/V
+ * bookkeeping of Section 4.1.1 (eqs. eq_lnZ, K_recurrence).
+ *
+ * Conventions
+ *  - Every pointer argument named *_dev is a device pointer (HIP device memory
+ *    of the current device); every other pointer is host memory.
+ *  - The caller owns all memory.  The library allocates no device memory: the
+ *    caller passes a workspace of at least hotrg_workspace_bytes() bytes, which
+ *    must stay valid until hotrg_destroy() returns.
+ *  - All work is enqueued on the HIP stream passed to hotrg_init (a hipStream_t
+ *    passed as void*; NULL means the default stream).  hotrg_step only enqueues
+ *    work; errors found on the device surface at the next synchronising call
+ *    (hotrg_log_z, hotrg_step_info, hotrg_spectrum, hotrg_grad) and are sticky.
+ *  - Functions return a status code (HOTRG_OK on success); nothing throws or
+ *    aborts across this interface.  hotrg_last_error() describes the last error.
+ *
+ * Local-tensor layout on the device (the "storage order")
+ *  For a d-dimensional lattice the local tensor with legs
+ *      c, n_1, ..., n_{d-1}   (unprimed half)   and   c', n'_1, ..., n'_{d-1}
+ *  is stored row-major as T[c][n_1]...[n_{d-1}][c'][n'_1]...[n'_{d-1}], i.e. as
+ *  an H x H matrix with H = chi_c * prod_j chi_{n_j}.  c/c' is the Current
+ *  direction, n_j/n'_j the direction Next j (Section 3.1.2-3.1.3).
+ */
+#ifndef HOTRG_H
+#define HOTRG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define HOTRG_OK         0
+#define HOTRG_E_ARG      1  /* invalid argument (NULL, out of range, unsupported) */
+#define HOTRG_E_STATE    2  /* call not allowed in the current state of the handle */
+#define HOTRG_E_NUMERIC  3  /* trace <= 0 or not finite, eigensolver did not converge */
+#define HOTRG_E_OOM      4  /* workspace smaller than hotrg_workspace_bytes() */
+#define HOTRG_E_DEVICE   5  /* HIP runtime error */
+#define HOTRG_E_NOT_PSD  6  /* the bond weight matrix W has a negative eigenvalue */
+
+/* ---- models (Section 2, eqs. 1-2) ------------------------------------- */
+#define HOTRG_ISING 0  /* s = +-1, f = beta J s s', g = beta h s               */
+#define HOTRG_POTTS 1  /* q states, f = beta J delta(s, s'), g = 0 (h must be 0) */
+
+/* ---- precision forms of the contraction ------------------------------ */
+#define HOTRG_FP64        0  /* FP64 operands, FP64 MFMA, FP64 master tensor        */
+#define HOTRG_FP32        1  /* FP32 operands, FP32 MFMA, FP32 master tensor        */
+#define HOTRG_BF16        2  /* BF16 operands (RNE), FP32 accumulate                */
+#define HOTRG_FP16        3  /* FP16 operands (RNE, power-of-two scaled), FP32 acc. */
+#define HOTRG_SPLIT_BF16  4  /* x = hi + lo in BF16; hi*hi + hi*lo + lo*hi, FP32 acc. */
+#define HOTRG_SPLIT_FP16  5  /* x = hi + lo in FP16 (scaled); 3 products, FP32 acc.   */
+
+typedef struct hotrg_model {
+    int kind;     /* HOTRG_ISING or HOTRG_POTTS                      */
+    int d;        /* lattice dimension: 2 or 3                       */
+    int q;        /* number of spin states (2 for Ising, >= 2 Potts) */
+    double J;     /* coupling (J >= 0; J < 0 gives HOTRG_E_NOT_PSD)  */
+    double h;     /* field (Ising only)                              */
+} hotrg_model;
+
+typedef struct hotrg_opts {
+    int precision;    /* HOTRG_FP64 .. HOTRG_SPLIT_FP16                          */
+    int max_steps;    /* capacity of the per-step record (diagnostics), >= 1      */
+    int chunk;        /* new-tensor columns per chunk in units of (n'_1..,c') groups;
+                         0 = automatic.  Bounds the memory of the prime-chain output
+                         (the paper's loop over n'_1, Section 4.2.8).            */
+    int record_grad;  /* reserved: must be 0                                     */
+} hotrg_opts;
+
+typedef struct hotrg_handle hotrg_handle;
+
+/* Per-step diagnostics (gauge-invariant quantities), see hotrg_step_info. */
+#define HOTRG_MAX_DIRS 3
+typedef struct hotrg_step_record {
+    int    p;                          /* step number, 1-based                          */
+    int    axis;                       /* lattice axis that was coarse-grained          */
+    int    dims_before[HOTRG_MAX_DIRS];/* chi_c, chi_{n_1}, .., chi_{n_{d-1}} before      */
+    double trace;                      /* Tr T^(p) of the new tensor (before f^(p))     */
+    double lnz_per_site;               /* ln Z^(p) / V^(p)                               */
+    double gu_wen;                     /* (tr Y)^2 / tr(Y^2), eq. ratio_X               */
+    int    chi_new[HOTRG_MAX_DIRS];    /* index j-1: chi_{n_j}^(new)                    */
+    double eps[HOTRG_MAX_DIRS];        /* epsilon^(j)  (0 when not truncated)           */
+    double eps_p[HOTRG_MAX_DIRS];      /* epsilon'^(j)                                  */
+    int    chose_prime[HOTRG_MAX_DIRS];/* 1 when U'^(j) was adopted                     */
+    int    truncated[HOTRG_MAX_DIRS];  /* 1 when chi_{n_j}^2 > chi (decomposition done) */
+    int    kept[HOTRG_MAX_DIRS];       /* leading columns kept; the rest of the chi_new
+                                          columns were zeroed because the cut split a
+                                          multiplet of equal eigenvalues             */
+} hotrg_step_record;
+
+/* Bytes of device workspace needed for (model, chi, opts).  Returns 0 for an
+ * invalid argument. */
+size_t hotrg_workspace_bytes(const hotrg_model* model, int chi, const hotrg_opts* opts);
+
+/* Build the initial tensor of eq. (4) on the device, normalise it by
+ * f^(0) = 1/Tr T (Section 3.1.3) and record lnZ/V at p = 0.  The first Current
+ * direction is lattice axis 0.  beta >= 0 and finite; 1 <= chi <= 16 for d = 3,
+ * chi <= 32 for d = 2, chi >= q.
+ * Errors: HOTRG_E_ARG, HOTRG_E_NOT_PSD, HOTRG_E_OOM, HOTRG_E_DEVICE. */
+int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts* opts,
+               void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+               hotrg_handle** out);
+
+/* Enqueue one coarse-graining step along lattice axis `axis` (0 <= axis < d).
+ * Any order is allowed; following the cycle 0, 1, .., d-1, 0, .. of the
+ * renaming in Section 3.1.3 needs no re-layout.  The lattice volume doubles.
+ * Errors: HOTRG_E_ARG, HOTRG_E_STATE (failed handle, or more than max_steps
+ * steps), HOTRG_E_DEVICE. */
+int hotrg_step(hotrg_handle* h, int axis);
+
+/* Synchronise and return ln Z^(p) / V^(p) (Section 4.1.1) after the steps so
+ * far, in FP64, and the number of steps done (either pointer may be NULL).
+ * Errors: HOTRG_E_NUMERIC (sticky), HOTRG_E_DEVICE. */
+int hotrg_log_z(hotrg_handle* h, double* lnz_per_site, int* steps_done);
+
+/* Synchronise and copy the diagnostics of step `step` (1-based). */
+int hotrg_step_info(hotrg_handle* h, int step, hotrg_step_record* out);
+
+/* Synchronise and copy the normalised eigenvalues lambda_l / lambda_1 (descending)
+ * of A^(dir) (side 0) or A'^(dir) (side 1) at step `step`; dir is 1-based.
+ * Writes min(cap, available) values and sets *n.  Untruncated steps have none. */
+int hotrg_spectrum(hotrg_handle* h, int step, int dir, int side, double* out, int cap, int* n);
+
+/* ---- live timing (HIP events on the library's stream) ----------------------
+ * Phases of hotrg_step, timed per launch while profiling is enabled. */
+#define HOTRG_T_DECOMP      0  /* Gram matrices + eigendecomposition + choice (4.2.4-4.2.7) */
+#define HOTRG_T_PRIME       1  /* prime chain into the B operand (eqs. TU1..TUNCD)          */
+#define HOTRG_T_BOTTLENECK  2  /* bottleneck GEMM (eq. BottleneckPart), one entry per chunk */
+#define HOTRG_T_NONPRIME    3  /* non-prime chain + renaming (eqs. AfterBNNCD..AfterBN1)    */
+#define HOTRG_T_TRACE       4  /* trace, lnZ/V, normalisation (4.2.11-4.2.14)                */
+#define HOTRG_T_CONTRACT    5  /* whole new-tensor contraction incl. the A operand          */
+#define HOTRG_T_STEP        6  /* whole hotrg_step                                          */
+#define HOTRG_T_COUNT       7
+typedef struct hotrg_timing {
+    double ms[HOTRG_T_COUNT];     /* summed duration of the phase                     */
+    long   count[HOTRG_T_COUNT];  /* number of timed launches (or steps) of the phase */
+    double flops_bottleneck;      /* algorithmic flops of the timed bottleneck GEMMs:
+                                     2 * M * N * K of the unpadded operands          */
+    double flops_contract;        /* algorithmic flops of the whole contraction:
+                                     bottleneck + prime chain + non-prime chain      */
+} hotrg_timing;
+
+/* Enable (1) or disable (0) timing; enabling clears the accumulators. */
+int hotrg_profile(hotrg_handle* h, int enable);
+
+/* Synchronise and return the accumulated timings since profiling was enabled. */
+int hotrg_timings(hotrg_handle* h, hotrg_timing* out);
+
+/* Reserved for the adjoint d(lnZ/V)/dbeta; returns HOTRG_E_STATE in this version. */
+int hotrg_grad(hotrg_handle* h, double* dlnz_dbeta_per_site);
+
+/* Release the handle (idempotent on NULL).  Does not free the workspace. */
+void hotrg_destroy(hotrg_handle* h);
+
+/* Message describing the last error on h (owned by h), or a static string
+ * for h == NULL. */
+const char* hotrg_last_error(const hotrg_handle* h);
+
+/* ---- kernel-level entry points (same kernels as hotrg_step) --------------
+ * They take FP64 device buffers in the storage order above, apply the given
+ * precision form inside, and use the caller's workspace (>= the value returned by
+ * hotrg_debug_workspace_bytes).  They synchronise the stream before returning. */
+
+/* Workspace bytes for the kernel-level entry points with local dims
+ * dims[0] = chi_c, dims[1..d-1] = chi_{n_j} and new dims kdims[0..d-2]. */
+size_t hotrg_debug_workspace_bytes(int d, const int* dims, const int* kdims, int precision);
+
+/* New tensor from T (dims as above) and isometries U_j (row-major
+ * chi_{n_j}^2 x kdims[j-1], row index (hat check) = hat + chi_{n_j} * check,
+ * Section 3.2).  Writes T^next in the storage order of the renamed tensor
+ * (Section 3.1.3: c^bar = n_1, n^bar_j = n_{j+1}, n^bar_{d-1} = c), not normalised. */
+int hotrg_debug_contract(int d, const int* dims, const int* kdims, int precision,
+                         const double* T_dev, const double* const* U_dev,
+                         double* Tnext_dev, void* workspace_dev, size_t workspace_bytes,
+                         void* hip_stream);
+
+/* Gram matrices A^(j) (side 0) and A'^(j) (side 1) of Section 3.2 for direction
+ * j = dir (1-based): A_dev receives chi_{n_j}^2 x chi_{n_j}^2 FP64, row-major. */
+int hotrg_debug_gram(int d, const int* dims, int dir, int side, const double* T_dev,
+                     double* A_dev, void* workspace_dev, size_t workspace_bytes,
+                     void* hip_stream);
+
+/* Workspace bytes for hotrg_debug_eigh. */
+size_t hotrg_debug_eigh_workspace_bytes(int n, int batch);
+
+/* Symmetric eigendecomposition (FP64 parallel Jacobi, the solver used for A and A'
+ * in Section 4.2.5) of `batch` row-major n x n matrices (1 <= n <= 1024):
+ * eigenvalues descending into w_dev[batch][n], eigenvectors as columns of
+ * V_dev[batch][n][n] (row-major).  A_dev is overwritten.
+ * Errors: HOTRG_E_ARG, HOTRG_E_OOM, HOTRG_E_NUMERIC (no convergence), HOTRG_E_DEVICE. */
+int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_dev,
+                     void* workspace_dev, size_t workspace_bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOTRG_H */

@@ -28,6 +28,12 @@ Readings of points the paper leaves open (each also listed in the design doc):
   R6  The Current direction starts at lattice axis 0 (x) and cycles x, y, z, ...
       through the renaming of Section 3.1.3.
   R7  After p steps the result is lnZ/V for a periodic torus of 2^p sites.
+  R8  "The first chi columns" is not unique when the cut splits a multiplet of
+      (numerically) equal eigenvalues.  Then the whole multiplet is dropped: its
+      columns of the adopted isometry are set to zero, which is the same as keeping
+      fewer columns.  Two eigenvalues belong to one multiplet when they differ by at
+      most MULTIPLET_RTOL times the larger one; eigenvalues below MULTIPLET_ATOL
+      times the largest are never examined (their weight is at rounding level).
 """
 
 from __future__ import annotations
@@ -207,6 +213,21 @@ def eig_descending(A: np.ndarray):
     return lam[order], U[:, order]
 
 
+MULTIPLET_RTOL = 1e-10
+MULTIPLET_ATOL = 1e-12
+
+
+def multiplet_safe_cut(lam_desc: np.ndarray, chi_new: int) -> int:
+    """Number of leading columns kept so that the cut splits no multiplet (R8)."""
+    k = chi_new
+    if k >= lam_desc.size:
+        return k
+    while (k > 1 and lam_desc[k - 1] >= MULTIPLET_ATOL * lam_desc[0]
+           and lam_desc[k - 1] - lam_desc[k] <= MULTIPLET_RTOL * lam_desc[k - 1]):
+        k -= 1
+    return k
+
+
 def judgement_value(lam_desc: np.ndarray, chi_new: int) -> float:
     """epsilon = sum of the eigenvalues beyond the first chi_new (Section 2, R2)."""
     return float(np.sum(np.clip(lam_desc[chi_new:], 0.0, None)))
@@ -221,13 +242,15 @@ class Truncation:
     lam: np.ndarray               # eigenvalues of A  (descending)
     lam_p: np.ndarray             # eigenvalues of A' (descending)
     chi_new: int
+    kept: int                     # columns not zeroed by the multiplet rule (R8)
 
 
-def choose_isometry(A: np.ndarray, Ap: np.ndarray, chi: int) -> Truncation:
+def choose_isometry(A: np.ndarray, Ap: np.ndarray, chi: int, multiplets: bool = True) -> Truncation:
     """Decompose A and A', compare epsilon and epsilon', keep the first chi_new columns.
 
     chi_new = min(chi_j^2, chi) (Section 2).  If epsilon < epsilon' then U is
-    adopted, otherwise U' (R3).
+    adopted, otherwise U' (R3).  With `multiplets`, columns of a multiplet split by
+    the cut are zeroed (R8).
     """
     n = A.shape[0]
     chi_new = min(n, chi)
@@ -236,10 +259,12 @@ def choose_isometry(A: np.ndarray, Ap: np.ndarray, chi: int) -> Truncation:
     eps = judgement_value(lam, chi_new)
     eps_p = judgement_value(lam_p, chi_new)
     if eps < eps_p:
-        Ut, prime = U[:, :chi_new], False
+        Ut, prime, lam_c = U[:, :chi_new].copy(), False, lam
     else:
-        Ut, prime = U_p[:, :chi_new], True
-    return Truncation(Ut.copy(), eps, eps_p, prime, lam, lam_p, chi_new)
+        Ut, prime, lam_c = U_p[:, :chi_new].copy(), True, lam_p
+    kept = multiplet_safe_cut(lam_c, chi_new) if multiplets else chi_new
+    Ut[:, kept:] = 0.0
+    return Truncation(Ut, eps, eps_p, prime, lam, lam_p, chi_new, kept)
 
 
 # ----------------------------------------------------------------------------
@@ -254,7 +279,7 @@ def _contract_leg(X: np.ndarray, axis: int, W: np.ndarray) -> np.ndarray:
     return np.moveaxis(Y, -1, axis)
 
 
-def new_tensor(T: np.ndarray, Ut: dict[int, np.ndarray]) -> np.ndarray:
+def new_tensor(T: np.ndarray, Ut: dict[int, np.ndarray], only=None) -> np.ndarray:
     """T^new[n_{d-1}..n_1, n'_{d-1}..n'_1, c, c'] from two copies of T (hat and check)
     and the isometries Ut[j] (chi_{n_j}^2 x chi_new_j), in the order of Section 4.2.8:
 
@@ -265,6 +290,9 @@ def new_tensor(T: np.ndarray, Ut: dict[int, np.ndarray]) -> np.ndarray:
     The loops run over n'_1 (outermost) .. n'_{d-1} (innermost) as in the paper,
     which bounds the intermediate size.  The hat copy supplies c, the check copy
     supplies c', and rho joins the hat copy's c' to the check copy's c.
+
+    only: optional list of tuples (n'_1, .., n'_{d-1}); when given, only those slices
+    of T^new are computed (the others stay zero) -- used to sample large cases.
     """
     d = T.ndim // 2
     chi_c = T.shape[axis_c(d)]
@@ -281,6 +309,9 @@ def new_tensor(T: np.ndarray, Ut: dict[int, np.ndarray]) -> np.ndarray:
             bottleneck_and_non_prime(C, fixed)
             return
         for nj in range(k[j]):
+            if only is not None and not any(
+                    t[j - 1] == nj and all(t[i - 1] == fixed[i] for i in fixed) for t in only):
+                continue
             # C^check(j) = sum_{n'^check_j} U^(j)[(n'^hat_j n'^check_j), n'_j] C^check(j-1)
             # the leg n'^check_j of C is replaced by n'^hat_j
             Uslice = Wm[j][:, :, nj]                     # [n'^check_j, n'^hat_j]
@@ -350,7 +381,7 @@ class StepRecord:
     truncations: dict = field(default_factory=dict)
 
 
-def coarse_grain(T: np.ndarray, chi: int):
+def coarse_grain(T: np.ndarray, chi: int, multiplets: bool = True):
     """One coarse-graining step along the Current direction of T (Sections 3-4).
 
     Returns (T^new before normalisation and before renaming, truncations).
@@ -361,7 +392,7 @@ def coarse_grain(T: np.ndarray, chi: int):
     for j in range(1, d):
         A = gram_matrix(T, axis_n(d, j))              # non-prime side
         Ap = gram_matrix(T, axis_np(d, j))            # prime side
-        tr[j] = choose_isometry(A, Ap, chi)
+        tr[j] = choose_isometry(A, Ap, chi, multiplets)
         Ut[j] = tr[j].U
     return new_tensor(T, Ut), tr
 
@@ -387,7 +418,7 @@ def normalisation_factor(T: np.ndarray, norm: str) -> float:
 
 
 def run(model: Model, beta: float, chi: int, steps: int, T0: np.ndarray | None = None,
-        on_step=None, norm: str = "trace"):
+        on_step=None, norm: str = "trace", multiplets: bool = True):
     """Full oracle run: initial tensor, normalisation, `steps` coarse-graining steps.
 
     lnZ bookkeeping follows eqs. (eq_lnZ) and (K_recurrence):
@@ -407,7 +438,7 @@ def run(model: Model, beta: float, chi: int, steps: int, T0: np.ndarray | None =
     records = []
     for p in range(1, steps + 1):
         dims = T.shape
-        Tnew, tr = coarse_grain(T, chi)
+        Tnew, tr = coarse_grain(T, chi, multiplets)
         t = trace(Tnew)
         if not (t > 0.0 and math.isfinite(t)):
             raise FloatingPointError(f"non-positive trace at step {p}: {t}")

@@ -1,0 +1,937 @@
+// Host engine and C ABI of libhotrg.so (declared in include/hotrg.h).
+//
+// One coarse-graining step along the Current direction (Sections 3-4 of the paper),
+// everything enqueued on the caller's stream:
+//   1. Gram matrices A^(j), A'^(j) in three steps (Section 3.2): permute T so that the
+//      (side leg, c') or (side leg, c) pair is the row index, FP64 MFMA GEMM X X^T with
+//      split-K and a fixed-order reduction, then the (rho, eta) contraction.
+//   2. FP64 Jacobi eigendecomposition of A and A' (Section 4.2.5).
+//   3. Judgement values, choice, truncation (Sections 2, 4.2.6-4.2.7).
+//   4. For each chunk of new-tensor columns (the paper's loop over n'_1, Section 4.2.8):
+//      prime chain -> B operand, bottleneck GEMM on MFMA in the precision form,
+//      non-prime chain + renaming into T^next.
+//   5. Trace, Gu-Wen ratio, lnZ/V, normalisation (Section 4.1.1, 4.2.12-4.2.14).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hotrg.h"
+#include "kernels.h"
+
+using namespace hk;
+
+namespace {
+
+constexpr long TILE_M = 128, TILE_N = 128, TILE_K = 64;
+constexpr int MAX_CHI_3D = 16, MAX_CHI_2D = 32;
+constexpr size_t ALIGN = 256;
+
+inline long roundup(long x, long m) { return (x + m - 1) / m * m; }
+
+bool form_valid(int f) { return f >= HOTRG_FP64 && f <= HOTRG_SPLIT_FP16; }
+size_t master_size(int form) { return form == HOTRG_FP64 ? 8 : 4; }
+size_t op_esize(int form) {
+  switch (form) {
+    case HOTRG_FP64: return 8;
+    case HOTRG_FP32: return 4;
+    default: return 2;
+  }
+}
+int op_planes(int form) { return (form == HOTRG_SPLIT_BF16 || form == HOTRG_SPLIT_FP16) ? 2 : 1; }
+size_t acc_size(int form) { return form == HOTRG_FP64 ? 8 : 4; }
+
+// Dimensions of the current tensor: slot 0 = c, slot j = n_j.
+struct LocalDims {
+  int d;
+  int chi[MAXD];
+};
+
+Dims make_dims(const LocalDims& ld, const int* k) {
+  Dims dm;
+  dm.d = ld.d;
+  dm.chic = ld.chi[0];
+  dm.chi1 = ld.chi[1];
+  dm.chi2 = ld.d == 3 ? ld.chi[2] : 1;
+  dm.k1 = k[0];
+  dm.k2 = ld.d == 3 ? k[1] : 1;
+  dm.b = dm.chi1 * dm.chi2;
+  dm.H = dm.chic * dm.b;
+  return dm;
+}
+
+// Gram GEMM geometry for one side of one direction.
+struct GramGeo {
+  long R, Rp, C, Cp, kchunk;
+  int Z;
+};
+GramGeo gram_geo(long H, long R) {
+  GramGeo g;
+  g.R = R;
+  g.Rp = roundup(R, TILE_M);
+  g.C = H * H / R;
+  const long tiles = (g.Rp / TILE_M) * (g.Rp / TILE_N);
+  long Z = std::max(1L, (512 + tiles - 1) / tiles);
+  Z = std::min(Z, std::max(1L, roundup(g.C, 16) / 16));
+  g.kchunk = roundup((g.C + Z - 1) / Z, 16);
+  g.Z = (int)((g.C + g.kchunk - 1) / g.kchunk);
+  g.Cp = (long)g.Z * g.kchunk;
+  return g;
+}
+
+// Byte sizes of every workspace region for given dims (max over the run is allocated).
+struct Need {
+  size_t T, Aop, Bop, Cc, X, part, G, Amat, w, Ut;
+};
+
+long chunk_pairs_for(const LocalDims& ld, const int* k, int form, int user_chunk) {
+  long total = 1;
+  for (int j = 1; j < ld.d; ++j) total *= k[j - 1];
+  if (user_chunk > 0) return std::min<long>(total, user_chunk);
+  const Dims dm = make_dims(ld, k);
+  const long Kp = roundup(dm.H, TILE_K), Mp = roundup(dm.H, TILE_M);
+  const double per_pair = (double)dm.chic * dm.b * (Kp * op_esize(form) * op_planes(form) + Mp * acc_size(form));
+  const double budget = 2.0 * 1024 * 1024 * 1024;
+  long c = (long)std::max(1.0, std::floor(budget / per_pair));
+  return std::min(total, c);
+}
+
+Need need_for(const LocalDims& ld, int chi, int form, int user_chunk) {
+  Need n{};
+  int k[MAXD];
+  for (int j = 1; j < ld.d; ++j) k[j - 1] = std::min(ld.chi[j] * ld.chi[j], chi);
+  const Dims dm = make_dims(ld, k);
+  const long H = dm.H;
+  const long Mp = roundup(H, TILE_M), Kp = roundup(H, TILE_K);
+  const long pairs = chunk_pairs_for(ld, k, form, user_chunk);
+  const long Np = roundup(pairs * dm.chic * dm.b, TILE_N);
+  long Hn = dm.chic;
+  for (int j = 0; j < ld.d - 1; ++j) Hn *= k[j];
+  n.T = (size_t)std::max(H * H, Hn * Hn) * master_size(form);
+  n.Aop = (size_t)Mp * Kp * op_esize(form) * op_planes(form);
+  n.Bop = (size_t)Np * Kp * op_esize(form) * op_planes(form);
+  n.Cc = (size_t)Mp * Np * acc_size(form);
+  size_t X = 0, part = 0, G = 0, Am = 0;
+  for (int j = 1; j < ld.d; ++j) {
+    const GramGeo g = gram_geo(H, (long)ld.chi[j] * ld.chi[0]);
+    X = std::max(X, (size_t)(g.Rp * g.Cp) * 8);
+    part = std::max(part, (size_t)g.Z * g.Rp * g.Rp * 8);
+    G = std::max(G, (size_t)g.R * g.R * 8);
+    const long nn = (long)ld.chi[j] * ld.chi[j];
+    Am = std::max(Am, (size_t)nn * nn * 8);
+  }
+  n.X = X;
+  n.part = part;
+  n.G = G;
+  n.Amat = Am;
+  n.w = (size_t)chi * chi * 8 + 64;
+  n.Ut = (size_t)chi * chi * chi * 8;
+  return n;
+}
+
+void need_max(Need& a, const Need& b) {
+  a.T = std::max(a.T, b.T); a.Aop = std::max(a.Aop, b.Aop); a.Bop = std::max(a.Bop, b.Bop);
+  a.Cc = std::max(a.Cc, b.Cc); a.X = std::max(a.X, b.X); a.part = std::max(a.part, b.part);
+  a.G = std::max(a.G, b.G); a.Amat = std::max(a.Amat, b.Amat); a.w = std::max(a.w, b.w);
+  a.Ut = std::max(a.Ut, b.Ut);
+}
+
+// All bond dimensions a run can reach: q, then min(x^2, chi) repeatedly.
+std::vector<int> reachable_dims(int q, int chi) {
+  std::vector<int> v{q};
+  int x = q;
+  while (x < chi) {
+    x = std::min(x * x, chi);
+    v.push_back(x);
+    if (x == 1) break;
+  }
+  return v;
+}
+
+struct Plan {
+  Need need;
+  size_t off_state, off_rec, off_T, off_Tn, off_Aop, off_Bop, off_Cc, off_X, off_part, off_Gh, off_Gc,
+      off_A, off_Vw, off_Vo, off_w, off_Ut, off_Ut32, total;
+  int max_steps;
+};
+
+Plan make_plan(int d, int q, int chi, int form, int user_chunk, int max_steps) {
+  Plan P{};
+  Need nd{};
+  const std::vector<int> vals = reachable_dims(q, chi);
+  LocalDims ld;
+  ld.d = d;
+  const int nv = (int)vals.size();
+  int combos = 1;
+  for (int i = 0; i < d; ++i) combos *= nv;
+  for (int cidx = 0; cidx < combos; ++cidx) {
+    int r = cidx;
+    for (int i = 0; i < d; ++i) { ld.chi[i] = vals[r % nv]; r /= nv; }
+    need_max(nd, need_for(ld, chi, form, user_chunk));
+  }
+  P.need = nd;
+  P.max_steps = max_steps;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = roundup(o + bytes, ALIGN); return r; };
+  P.off_state = take(sizeof(DevState));
+  P.off_rec = take(sizeof(StepRec) * (size_t)(max_steps + 1));
+  P.off_T = take(nd.T);
+  P.off_Tn = take(nd.T);
+  P.off_Aop = take(nd.Aop);
+  P.off_Bop = take(nd.Bop);
+  P.off_Cc = take(nd.Cc);
+  P.off_X = take(nd.X);
+  P.off_part = take(nd.part);
+  P.off_Gh = take(nd.G);
+  P.off_Gc = take(nd.G);
+  P.off_A = take(2 * nd.Amat);
+  P.off_Vw = take(2 * nd.Amat);
+  P.off_Vo = take(2 * nd.Amat);
+  P.off_w = take(2 * nd.w);
+  P.off_Ut = take(MAXD * nd.Ut);
+  P.off_Ut32 = take(MAXD * nd.Ut / 2 + 64);
+  P.total = o;
+  return P;
+}
+
+unsigned grid_for(long n, int block = 256) {
+  long g = (n + block - 1) / block;
+  return (unsigned)std::max(1L, std::min(g, 65536L));
+}
+
+}  // namespace
+
+struct hotrg_handle {
+  hotrg_model model{};
+  hotrg_opts opts{};
+  double beta = 0;
+  int chi = 0;
+  int form = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t s = nullptr;
+  Plan plan{};
+  LocalDims ld{};
+  int axes[MAXD]{};   // lattice axis of each slot (slot 0 = Current)
+  int p = 0;
+  bool failed = false;
+  std::string err;
+  // live timing: pairs of events recorded on the stream, resolved at hotrg_timings
+  bool profiling = false;
+  struct Pending { int cat; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> free_events;
+  hotrg_timing acc{};
+
+  template <class X> X* at(size_t off) { return reinterpret_cast<X*>(ws + off); }
+  DevState* st() { return at<DevState>(plan.off_state); }
+  StepRec* rec(int step) { return at<StepRec>(plan.off_rec) + step; }
+};
+
+namespace {
+
+thread_local std::string g_static_err;
+
+// Timing helpers: mark(h) records an event on the stream (or returns null when not
+// profiling); close(h, cat, start) records the end event and queues the pair.
+hipEvent_t tmark(hotrg_handle* h) {
+  if (!h->profiling) return nullptr;
+  hipEvent_t e;
+  if (!h->free_events.empty()) {
+    e = h->free_events.back();
+    h->free_events.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return nullptr;
+  }
+  hipEventRecord(e, h->s);
+  return e;
+}
+void tclose(hotrg_handle* h, int cat, hipEvent_t start) {
+  if (!h->profiling || !start) return;
+  hipEvent_t e = tmark(h);
+  if (!e) return;
+  h->pending.push_back({cat, start, e});
+}
+
+int fail(hotrg_handle* h, int code, const std::string& msg) {
+  if (h) {
+    h->err = msg;
+    if (code == HOTRG_E_DEVICE || code == HOTRG_E_NUMERIC) h->failed = true;
+  } else {
+    g_static_err = msg;
+  }
+  return code;
+}
+
+#define HIPCHK(h, expr)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) return fail((h), HOTRG_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Launch helpers (template dispatch on the precision form)
+// ---------------------------------------------------------------------------
+
+template <int F> struct GemmCfg;
+template <> struct GemmCfg<F_FP64> { static constexpr int BK = 16; };
+template <> struct GemmCfg<F_FP32> { static constexpr int BK = 32; };
+template <> struct GemmCfg<F_BF16> { static constexpr int BK = 64; };
+template <> struct GemmCfg<F_FP16> { static constexpr int BK = 64; };
+template <> struct GemmCfg<F_SPLIT_BF16> { static constexpr int BK = 64; };
+template <> struct GemmCfg<F_SPLIT_FP16> { static constexpr int BK = 64; };
+
+template <int F>
+void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, long bplane, void* C, long ldc,
+                 long czs, long Mp, long Np, long Kp, int Z, long kchunk, const double* scale_ptr, double smult,
+                 hipStream_t s) {
+  typedef typename OpOf<F>::type Op;
+  constexpr int PL = FormInfo<F>::planes;
+  dim3 grid((unsigned)(Mp / TILE_M), (unsigned)(Np / TILE_N), (unsigned)Z);
+  (void)Kp;
+  hipLaunchKernelGGL((k_gemm_tn<Op, PL, TILE_M, TILE_N, GemmCfg<F>::BK>), grid, dim3(256), 0, s,
+                     (const typename Op::T*)A, lda, aplane, (const typename Op::T*)B, ldb, bplane,
+                     (typename Op::Acc*)C, ldc, czs, (int)kchunk, scale_ptr, smult);
+}
+
+// Gram matrices for direction j (1-based) into A_out[side] (n x n each, n = chi_j^2).
+int enqueue_gram(hotrg_handle* h, const void* T, bool t_is_f64, const LocalDims& ld, int j, int side,
+                 double* A_out) {
+  const int d = ld.d;
+  long H = 1;
+  for (int i = 0; i < d; ++i) H *= ld.chi[i];
+  const long R = (long)ld.chi[j] * ld.chi[0];
+  const GramGeo g = gram_geo(H, R);
+  double* X = h->at<double>(h->plan.off_X);
+  double* part = h->at<double>(h->plan.off_part);
+  double* Gh = h->at<double>(h->plan.off_Gh);
+  double* Gc = h->at<double>(h->plan.off_Gc);
+  // storage legs: 0 = c, 1..d-1 = n_j, d = c', d+1.. = n'_j; strides row-major
+  int dims2[2 * MAXD];
+  long str[2 * MAXD];
+  for (int i = 0; i < d; ++i) { dims2[i] = ld.chi[i]; dims2[d + i] = ld.chi[i]; }
+  str[2 * d - 1] = 1;
+  for (int i = 2 * d - 2; i >= 0; --i) str[i] = str[i + 1] * dims2[i + 1];
+  const int sleg = side == 0 ? j : d + j;          // n_j or n'_j
+  for (int which = 0; which < 2; ++which) {
+    // which 0: hat, rows (side leg, c'); which 1: check, rows (side leg, c)
+    const int rleg = which == 0 ? d : 0;
+    PermSpec ps{};
+    ps.nd = 2 * d;
+    ps.nrow = 2;
+    int k = 0;
+    ps.od[k] = dims2[sleg]; ps.sstride[k++] = str[sleg];
+    ps.od[k] = dims2[rleg]; ps.sstride[k++] = str[rleg];
+    for (int l = 0; l < 2 * d; ++l) {
+      if (l == sleg || l == rleg) continue;
+      ps.od[k] = dims2[l]; ps.sstride[k++] = str[l];
+    }
+    ps.rows = R; ps.cols = g.C; ps.rows_p = g.Rp; ps.ldd = g.Cp;
+    if (t_is_f64)
+      hipLaunchKernelGGL((k_permute<double, double>), dim3(grid_for(g.Rp * g.Cp)), dim3(256), 0, h->s,
+                         (const double*)T, X, ps, 1.0);
+    else
+      hipLaunchKernelGGL((k_permute<float, double>), dim3(grid_for(g.Rp * g.Cp)), dim3(256), 0, h->s,
+                         (const float*)T, X, ps, 1.0);
+    launch_gemm<F_FP64>(X, g.Cp, 0, X, g.Cp, 0, part, g.Rp, g.Rp * g.Rp, g.Rp, g.Rp, g.Cp, g.Z, g.kchunk,
+                        nullptr, 1.0, h->s);
+    hipLaunchKernelGGL(k_reduce_z, dim3(grid_for(R * R)), dim3(256), 0, h->s, (const double*)part,
+                       g.Rp * g.Rp, g.Rp, g.Z, (int)R, which == 0 ? Gh : Gc);
+  }
+  const long n = (long)ld.chi[j] * ld.chi[j];
+  hipLaunchKernelGGL(k_gram_combine, dim3(grid_for(n * n)), dim3(256), 0, h->s, (const double*)Gh,
+                     (const double*)Gc, ld.chi[j], ld.chi[0], A_out);
+  HIPCHK(h, hipGetLastError());
+  return HOTRG_OK;
+}
+
+// Contraction (prime chain, bottleneck, non-prime chain + rename) for form F.
+template <int F>
+int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDims& ld, const int* k) {
+  typedef typename std::conditional<F == F_FP64, double, float>::type MT;
+  typedef typename Store<F>::T ST;
+  typedef typename OpOf<F>::type::Acc AT;
+  const MT* T = (const MT*)Tv;
+  MT* Tn = (MT*)Tnv;
+  const Dims dm = make_dims(ld, k);
+  const long H = dm.H, Mp = roundup(H, TILE_M), Kp = roundup(H, TILE_K);
+  const long pairs_total = (ld.d == 3) ? (long)k[0] * k[1] : k[0];
+  const long cp = chunk_pairs_for(ld, k, h->form, h->opts.chunk);
+  ST* Aop = h->at<ST>(h->plan.off_Aop);
+  ST* Bop = h->at<ST>(h->plan.off_Bop);
+  AT* Cc = h->at<AT>(h->plan.off_Cc);
+  DevState* st = h->st();
+  const void* U1 = F == F_FP64 ? (const void*)h->at<double>(h->plan.off_Ut)
+                               : (const void*)h->at<float>(h->plan.off_Ut32);
+  const size_t ut_stride = h->plan.need.Ut / 8;   // elements per direction
+  const void* U2 = F == F_FP64 ? (const void*)(h->at<double>(h->plan.off_Ut) + ut_stride)
+                               : (const void*)(h->at<float>(h->plan.off_Ut32) + ut_stride);
+  typedef typename std::conditional<F == F_FP64, double, float>::type UT;
+  const long aplane = Mp * Kp;
+  hipEvent_t t_all = tmark(h);
+  hipLaunchKernelGGL((k_make_a<MT, F>), dim3(grid_for(aplane)), dim3(256), 0, h->s, T, (int)H, Aop, Mp, Kp,
+                     (const DevState*)st);
+  for (long pr0 = 0; pr0 < pairs_total; pr0 += cp) {
+    const long pr1 = std::min(pairs_total, pr0 + cp);
+    const long ncols = (pr1 - pr0) * dm.chic * dm.b;
+    const long Np = roundup(ncols, TILE_N);
+    const long bplane = Np * Kp;
+    hipEvent_t t0 = tmark(h);
+    hipLaunchKernelGGL((k_zero_pad<ST>), dim3(grid_for((Np - ncols) * Kp + ncols * (Kp - H) + 1)), dim3(256), 0,
+                       h->s, Bop, ncols, Np, H, Kp, bplane, FormInfo<F>::planes);
+    hipLaunchKernelGGL((k_pstage<MT, UT, F>), dim3((unsigned)(H * dm.chic)), dim3(256), 0, h->s, T,
+                       (const UT*)U1, (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane,
+                       (const DevState*)st);
+    tclose(h, HOTRG_T_PRIME, t0);
+    const double* sp = nullptr;
+    if (FormInfo<F>::fp16) {
+      // the product is scaled back by 1 / (s_A s_B), a device scalar (no host round trip)
+      hipLaunchKernelGGL(k_inv_scale_fp16, dim3(1), dim3(1), 0, h->s, st, dm.b);
+      sp = &st->inv_scale;
+    }
+    hipEvent_t t1 = tmark(h);
+    launch_gemm<F>(Aop, Kp, aplane, Bop, Kp, bplane, Cc, Np, 0, Mp, Np, Kp, 1, Kp, sp, 1.0, h->s);
+    tclose(h, HOTRG_T_BOTTLENECK, t1);
+    if (h->profiling) h->acc.flops_bottleneck += 2.0 * (double)H * (double)ncols * (double)H;
+    hipEvent_t t2 = tmark(h);
+    const long ncell = (long)dm.chic * (pr1 - pr0) * dm.chic;   // (c, g) blocks
+    const int g0 = (int)(pr0 * dm.chic), gcount = (int)((pr1 - pr0) * dm.chic);
+    if (ld.d == 3)
+      hipLaunchKernelGGL((k_nstage3<AT, MT, UT>), dim3((unsigned)ncell), dim3(256), 0, h->s, (const AT*)Cc, Np,
+                         (const UT*)U1, (const UT*)U2, dm, g0, gcount, Tn);
+    else
+      hipLaunchKernelGGL((k_nstage2<AT, MT, UT>), dim3((unsigned)ncell), dim3(64), 0, h->s, (const AT*)Cc, Np,
+                         (const UT*)U1, dm, g0, gcount, Tn);
+    tclose(h, HOTRG_T_NONPRIME, t2);
+  }
+  tclose(h, HOTRG_T_CONTRACT, t_all);
+  if (h->profiling) {
+    // algorithmic MACs of the three stages as factorised here (all chunks of this step)
+    const double c = dm.chic, b = dm.b, k1 = dm.k1, k2 = dm.k2, x1 = dm.chi1, x2 = dm.chi2, Hd = (double)H;
+    double macs = Hd * Hd * (k1 * k2 * c * b);                 // bottleneck: M = K = H, N = k1 k2 c b
+    if (ld.d == 3) {
+      macs += Hd * c * k1 * b * x1 + Hd * c * k1 * k2 * b * x2; // prime chain: n'^check_1, then n'^check_2
+      macs += c * c * k1 * k2 * (x1 * x1 * k2 * x2 * x2 + x1 * x1 * k1 * k2);  // non-prime chain
+    } else {
+      macs += Hd * c * k1 * x1 * x1;                            // prime chain
+      macs += c * c * k1 * k1 * x1 * x1;                        // non-prime chain
+    }
+    h->acc.flops_contract += 2.0 * macs;
+  }
+  HIPCHK(h, hipGetLastError());
+  return HOTRG_OK;
+}
+
+int enqueue_contract(hotrg_handle* h, const void* T, void* Tn, const LocalDims& ld, const int* k) {
+  switch (h->form) {
+    case HOTRG_FP64: return enqueue_contract_f<F_FP64>(h, T, Tn, ld, k);
+    case HOTRG_FP32: return enqueue_contract_f<F_FP32>(h, T, Tn, ld, k);
+    case HOTRG_BF16: return enqueue_contract_f<F_BF16>(h, T, Tn, ld, k);
+    case HOTRG_FP16: return enqueue_contract_f<F_FP16>(h, T, Tn, ld, k);
+    case HOTRG_SPLIT_BF16: return enqueue_contract_f<F_SPLIT_BF16>(h, T, Tn, ld, k);
+    case HOTRG_SPLIT_FP16: return enqueue_contract_f<F_SPLIT_FP16>(h, T, Tn, ld, k);
+  }
+  return fail(h, HOTRG_E_ARG, "bad precision form");
+}
+
+// Decompose A^(j), A'^(j) and choose/truncate U^(j) into the isometry slot of direction j.
+int enqueue_isometry(hotrg_handle* h, const void* T, const LocalDims& ld, int j, int kj, StepRec* rec) {
+  const int n = ld.chi[j] * ld.chi[j];
+  double* Ut = h->at<double>(h->plan.off_Ut) + (size_t)(j - 1) * (h->plan.need.Ut / 8);
+  float* Ut32 = h->at<float>(h->plan.off_Ut32) + (size_t)(j - 1) * (h->plan.need.Ut / 8);
+  double* Am = h->at<double>(h->plan.off_A);
+  double* Vw = h->at<double>(h->plan.off_Vw);
+  double* Vo = h->at<double>(h->plan.off_Vo);
+  double* w = h->at<double>(h->plan.off_w);
+  if (n <= h->chi) {   // untruncated: all columns kept, identity basis
+    hipLaunchKernelGGL(k_choose, dim3(1), dim3(256), 0, h->s, (const double*)w, (const double*)Vo, n, n, 1, Ut,
+                       Ut32, rec, j - 1);
+    HIPCHK(h, hipGetLastError());
+    return HOTRG_OK;
+  }
+  const size_t nn = (size_t)n * n;
+  for (int side = 0; side < 2; ++side) {
+    int rc = enqueue_gram(h, T, h->form == HOTRG_FP64, ld, j, side, Am + side * nn);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_jacobi, dim3(2), dim3(JAC_THREADS), 0, h->s, Am, Vw, w, Vo, n, 60, h->st());
+  hipLaunchKernelGGL(k_choose, dim3(1), dim3(256), 0, h->s, (const double*)w, (const double*)Vo, n, kj, 0, Ut,
+                     Ut32, rec, j - 1);
+  HIPCHK(h, hipGetLastError());
+  return HOTRG_OK;
+}
+
+// Rotate the storage legs so that slot 0 holds lattice axis `axis`.
+int enqueue_relayout(hotrg_handle* h, int axis) {
+  const int d = h->ld.d;
+  int shift = 0;
+  while (h->axes[shift] != axis) ++shift;
+  if (shift == 0) return HOTRG_OK;
+  int dims2[2 * MAXD];
+  long str[2 * MAXD];
+  for (int i = 0; i < d; ++i) { dims2[i] = h->ld.chi[i]; dims2[d + i] = h->ld.chi[i]; }
+  str[2 * d - 1] = 1;
+  for (int i = 2 * d - 2; i >= 0; --i) str[i] = str[i + 1] * dims2[i + 1];
+  PermSpec ps{};
+  ps.nd = 2 * d;
+  ps.nrow = d;
+  long H = 1;
+  for (int i = 0; i < d; ++i) {
+    const int src = (i + shift) % d;
+    ps.od[i] = dims2[src]; ps.sstride[i] = str[src];
+    ps.od[d + i] = dims2[d + src]; ps.sstride[d + i] = str[d + src];
+    H *= dims2[src];
+  }
+  ps.rows = H; ps.cols = H; ps.rows_p = H; ps.ldd = H;
+  void* T = h->at<void>(h->plan.off_T);
+  void* Tn = h->at<void>(h->plan.off_Tn);
+  if (h->form == HOTRG_FP64)
+    hipLaunchKernelGGL((k_permute<double, double>), dim3(grid_for(H * H)), dim3(256), 0, h->s, (const double*)T,
+                       (double*)Tn, ps, 1.0);
+  else
+    hipLaunchKernelGGL((k_permute<float, float>), dim3(grid_for(H * H)), dim3(256), 0, h->s, (const float*)T,
+                       (float*)Tn, ps, 1.0);
+  HIPCHK(h, hipGetLastError());
+  std::swap(h->plan.off_T, h->plan.off_Tn);
+  LocalDims nl = h->ld;
+  int na[MAXD];
+  for (int i = 0; i < d; ++i) { nl.chi[i] = h->ld.chi[(i + shift) % d]; na[i] = h->axes[(i + shift) % d]; }
+  h->ld = nl;
+  for (int i = 0; i < d; ++i) h->axes[i] = na[i];
+  return HOTRG_OK;
+}
+
+int sync_state(hotrg_handle* h, DevState* out) {
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  HIPCHK(h, hipMemcpy(out, h->st(), sizeof(DevState), hipMemcpyDeviceToHost));
+  if (out->err) {
+    h->failed = true;
+    return fail(h, HOTRG_E_NUMERIC, "numeric failure on the device (non-positive or non-finite trace, "
+                                    "or eigensolver without convergence)");
+  }
+  return HOTRG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+static int check_model(const hotrg_model* m, int chi) {
+  if (!m) return HOTRG_E_ARG;
+  if (m->d != 2 && m->d != 3) return HOTRG_E_ARG;
+  if (m->kind == HOTRG_ISING) {
+    if (m->q != 2) return HOTRG_E_ARG;
+  } else if (m->kind == HOTRG_POTTS) {
+    if (m->q < 2 || m->q > 8 || m->h != 0.0) return HOTRG_E_ARG;
+  } else {
+    return HOTRG_E_ARG;
+  }
+  if (!std::isfinite(m->J) || !std::isfinite(m->h)) return HOTRG_E_ARG;
+  const int maxchi = m->d == 3 ? MAX_CHI_3D : MAX_CHI_2D;
+  if (chi < m->q || chi > maxchi) return HOTRG_E_ARG;
+  return HOTRG_OK;
+}
+
+size_t hotrg_workspace_bytes(const hotrg_model* model, int chi, const hotrg_opts* opts) {
+  if (!opts || check_model(model, chi) != HOTRG_OK || !form_valid(opts->precision) || opts->max_steps < 1)
+    return 0;
+  return make_plan(model->d, model->q, chi, opts->precision, opts->chunk, opts->max_steps).total;
+}
+
+int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts* opts, void* workspace,
+               size_t ws_bytes, void* stream, hotrg_handle** out) {
+  if (!out) return fail(nullptr, HOTRG_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!opts || !model) return fail(nullptr, HOTRG_E_ARG, "model or opts is NULL");
+  if (check_model(model, chi) != HOTRG_OK) return fail(nullptr, HOTRG_E_ARG, "invalid model or chi");
+  if (!form_valid(opts->precision) || opts->max_steps < 1 || opts->chunk < 0 || opts->record_grad != 0)
+    return fail(nullptr, HOTRG_E_ARG, "invalid options");
+  if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(nullptr, HOTRG_E_ARG, "beta must be finite and >= 0");
+  // W must be positive semi-definite: Ising needs sinh(beta J) >= 0, Potts e^{beta J} - 1 >= 0
+  if (beta * model->J < 0.0) return fail(nullptr, HOTRG_E_NOT_PSD, "bond weight matrix is not PSD (J < 0)");
+  if (!workspace) return fail(nullptr, HOTRG_E_ARG, "workspace is NULL");
+  Plan P = make_plan(model->d, model->q, chi, opts->precision, opts->chunk, opts->max_steps);
+  if (ws_bytes < P.total) return fail(nullptr, HOTRG_E_OOM, "workspace too small");
+  if (((uintptr_t)workspace) % ALIGN) return fail(nullptr, HOTRG_E_ARG, "workspace must be 256-byte aligned");
+  hotrg_handle* h = new hotrg_handle();
+  h->model = *model;
+  h->opts = *opts;
+  h->beta = beta;
+  h->chi = chi;
+  h->form = opts->precision;
+  h->ws = (char*)workspace;
+  h->ws_bytes = ws_bytes;
+  h->s = (hipStream_t)stream;
+  h->plan = P;
+  h->ld.d = model->d;
+  for (int i = 0; i < model->d; ++i) { h->ld.chi[i] = model->q; h->axes[i] = i; }
+  hipError_t e = hipMemsetAsync(h->ws, 0, P.off_T, h->s);   // state + records
+  if (e == hipSuccess) {
+    if (h->form == HOTRG_FP64)
+      hipLaunchKernelGGL((k_init_tensor<double>), dim3(1), dim3(256), 0, h->s, h->at<double>(P.off_T),
+                         model->kind, model->d, model->q, beta, model->J, model->h, h->st());
+    else
+      hipLaunchKernelGGL((k_init_tensor<float>), dim3(1), dim3(256), 0, h->s, h->at<float>(P.off_T),
+                         model->kind, model->d, model->q, beta, model->J, model->h, h->st());
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    g_static_err = std::string("device error in hotrg_init: ") + hipGetErrorString(e);
+    delete h;
+    return HOTRG_E_DEVICE;
+  }
+  *out = h;
+  return HOTRG_OK;
+}
+
+int hotrg_step(hotrg_handle* h, int axis) {
+  if (!h) return fail(nullptr, HOTRG_E_ARG, "handle is NULL");
+  if (h->failed) return fail(h, HOTRG_E_STATE, "handle is in the failed state");
+  if (axis < 0 || axis >= h->ld.d) return fail(h, HOTRG_E_ARG, "axis out of range");
+  if (h->p >= h->plan.max_steps) return fail(h, HOTRG_E_STATE, "max_steps reached");
+  hipEvent_t t_step = tmark(h);
+  int rc = enqueue_relayout(h, axis);
+  if (rc) return rc;
+  const int d = h->ld.d;
+  const LocalDims ld = h->ld;
+  int k[MAXD];
+  for (int j = 1; j < d; ++j) k[j - 1] = std::min(ld.chi[j] * ld.chi[j], h->chi);
+  const int p = h->p + 1;
+  StepRec* rec = h->rec(p - 1);
+  hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(256), 0, h->s, rec, p, axis, d, ld.chi[0], ld.chi[1],
+                     d == 3 ? ld.chi[2] : 0);
+  void* T = h->at<void>(h->plan.off_T);
+  void* Tn = h->at<void>(h->plan.off_Tn);
+  hipEvent_t t_dec = tmark(h);
+  for (int j = 1; j < d; ++j) {
+    rc = enqueue_isometry(h, T, ld, j, k[j - 1], rec);
+    if (rc) return rc;
+  }
+  tclose(h, HOTRG_T_DECOMP, t_dec);
+  rc = enqueue_contract(h, T, Tn, ld, k);
+  if (rc) return rc;
+  // new dims after renaming: c^bar = n_1, n^bar_j = n_{j+1}, n^bar_{d-1} = c
+  LocalDims nl;
+  nl.d = d;
+  for (int j = 1; j < d; ++j) nl.chi[j - 1] = k[j - 1];
+  nl.chi[d - 1] = ld.chi[0];
+  long Hn = 1;
+  for (int i = 0; i < d; ++i) Hn *= nl.chi[i];
+  DevState* st = h->st();
+  hipEvent_t t_tr = tmark(h);
+  if (h->form == HOTRG_FP64) {
+    hipLaunchKernelGGL((k_trace_lnz<double>), dim3(1), dim3(256), 0, h->s, (const double*)Tn, (int)Hn, ld.chi[0],
+                       st, rec, p);
+    hipLaunchKernelGGL(k_reset_maxabs, dim3(1), dim3(1), 0, h->s, st);
+    hipLaunchKernelGGL((k_scale<double>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (double*)Tn, Hn * Hn, st);
+  } else {
+    hipLaunchKernelGGL((k_trace_lnz<float>), dim3(1), dim3(256), 0, h->s, (const float*)Tn, (int)Hn, ld.chi[0],
+                       st, rec, p);
+    hipLaunchKernelGGL(k_reset_maxabs, dim3(1), dim3(1), 0, h->s, st);
+    hipLaunchKernelGGL((k_scale<float>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (float*)Tn, Hn * Hn, st);
+  }
+  tclose(h, HOTRG_T_TRACE, t_tr);
+  tclose(h, HOTRG_T_STEP, t_step);
+  HIPCHK(h, hipGetLastError());
+  std::swap(h->plan.off_T, h->plan.off_Tn);
+  int na[MAXD];
+  for (int i = 0; i < d; ++i) na[i] = h->axes[(i + 1) % d];
+  for (int i = 0; i < d; ++i) h->axes[i] = na[i];
+  h->ld = nl;
+  h->p = p;
+  return HOTRG_OK;
+}
+
+int hotrg_log_z(hotrg_handle* h, double* lnz, int* steps) {
+  if (!h) return fail(nullptr, HOTRG_E_ARG, "handle is NULL");
+  DevState s;
+  int rc = sync_state(h, &s);
+  if (rc) return rc;
+  if (lnz) *lnz = s.lnz;
+  if (steps) *steps = h->p;
+  return HOTRG_OK;
+}
+
+int hotrg_step_info(hotrg_handle* h, int step, hotrg_step_record* out) {
+  if (!h || !out) return fail(h, HOTRG_E_ARG, "NULL argument");
+  if (step < 1 || step > h->p) return fail(h, HOTRG_E_ARG, "step out of range");
+  DevState s;
+  int rc = sync_state(h, &s);
+  if (rc) return rc;
+  StepRec r;
+  HIPCHK(h, hipMemcpy(&r, h->rec(step - 1), sizeof(StepRec), hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  out->p = r.p;
+  out->axis = r.axis;
+  out->trace = r.trace;
+  out->lnz_per_site = r.lnz;
+  out->gu_wen = r.gu_wen;
+  for (int i = 0; i < MAXD; ++i) {
+    out->dims_before[i] = r.dims_before[i];
+    out->chi_new[i] = r.chi_new[i];
+    out->eps[i] = r.eps[i];
+    out->eps_p[i] = r.eps_p[i];
+    out->chose_prime[i] = r.chose_prime[i];
+    out->truncated[i] = r.truncated[i];
+    out->kept[i] = r.kept[i];
+  }
+  return HOTRG_OK;
+}
+
+int hotrg_spectrum(hotrg_handle* h, int step, int dir, int side, double* outv, int cap, int* n) {
+  if (!h || !n || (cap > 0 && !outv)) return fail(h, HOTRG_E_ARG, "NULL argument");
+  if (step < 1 || step > h->p || dir < 1 || dir >= h->ld.d || side < 0 || side > 1)
+    return fail(h, HOTRG_E_ARG, "argument out of range");
+  DevState s;
+  int rc = sync_state(h, &s);
+  if (rc) return rc;
+  StepRec r;
+  HIPCHK(h, hipMemcpy(&r, h->rec(step - 1), sizeof(StepRec), hipMemcpyDeviceToHost));
+  const int avail = r.nspec[dir - 1][side];
+  const int m = std::min(cap, avail);
+  for (int i = 0; i < m; ++i) outv[i] = r.spec[dir - 1][side][i];
+  *n = m;
+  return HOTRG_OK;
+}
+
+int hotrg_grad(hotrg_handle* h, double* outv) {
+  (void)outv;
+  if (!h) return fail(nullptr, HOTRG_E_ARG, "handle is NULL");
+  return fail(h, HOTRG_E_STATE, "gradient recording is not enabled in this version");
+}
+
+int hotrg_profile(hotrg_handle* h, int enable) {
+  if (!h) return fail(nullptr, HOTRG_E_ARG, "handle is NULL");
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  for (auto& pe : h->pending) { h->free_events.push_back(pe.a); h->free_events.push_back(pe.b); }
+  h->pending.clear();
+  h->acc = hotrg_timing{};
+  h->profiling = enable != 0;
+  return HOTRG_OK;
+}
+
+int hotrg_timings(hotrg_handle* h, hotrg_timing* out) {
+  if (!h || !out) return fail(h, HOTRG_E_ARG, "NULL argument");
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  for (auto& pe : h->pending) {
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, pe.a, pe.b));
+    h->acc.ms[pe.cat] += ms;
+    h->acc.count[pe.cat] += 1;
+    h->free_events.push_back(pe.a);
+    h->free_events.push_back(pe.b);
+  }
+  h->pending.clear();
+  *out = h->acc;
+  return HOTRG_OK;
+}
+
+void hotrg_destroy(hotrg_handle* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->s);
+  for (auto& pe : h->pending) { h->free_events.push_back(pe.a); h->free_events.push_back(pe.b); }
+  for (hipEvent_t e : h->free_events) (void)hipEventDestroy(e);
+  delete h;
+}
+
+const char* hotrg_last_error(const hotrg_handle* h) {
+  if (!h) return g_static_err.c_str();
+  return h->err.c_str();
+}
+
+// ---------------------------------------------------------------------------
+// Kernel-level entry points
+// ---------------------------------------------------------------------------
+
+static bool debug_dims_ok(int d, const int* dims, const int* kdims) {
+  if ((d != 2 && d != 3) || !dims) return false;
+  const int maxchi = d == 3 ? MAX_CHI_3D : MAX_CHI_2D;
+  for (int i = 0; i < d; ++i)
+    if (dims[i] < 1 || dims[i] > maxchi) return false;
+  if (kdims)
+    for (int j = 0; j < d - 1; ++j)
+      if (kdims[j] < 1 || kdims[j] > maxchi || kdims[j] > dims[j + 1] * dims[j + 1]) return false;
+  return true;
+}
+
+static Plan debug_plan(int d, const int* dims, const int* kdims, int form) {
+  LocalDims ld;
+  ld.d = d;
+  for (int i = 0; i < d; ++i) ld.chi[i] = dims[i];
+  int chi = 1;
+  for (int i = 0; i < d; ++i) chi = std::max(chi, dims[i]);
+  if (kdims)
+    for (int j = 0; j < d - 1; ++j) chi = std::max(chi, kdims[j]);
+  Plan P{};
+  P.need = need_for(ld, chi, form, 0);
+  // kdims may be smaller than min(chi^2, chi): need_for used the larger value -> still enough
+  P.max_steps = 1;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = roundup(o + bytes, ALIGN); return r; };
+  const Need& nd = P.need;
+  long H = 1;
+  for (int i = 0; i < d; ++i) H *= dims[i];
+  const size_t tb = std::max(nd.T, (size_t)H * H * 8);
+  P.off_state = take(sizeof(DevState));
+  P.off_rec = take(sizeof(StepRec) * 2);
+  P.off_T = take(tb);
+  P.off_Tn = take(tb);
+  P.off_Aop = take(nd.Aop);
+  P.off_Bop = take(nd.Bop);
+  P.off_Cc = take(nd.Cc);
+  P.off_X = take(nd.X);
+  P.off_part = take(nd.part);
+  P.off_Gh = take(nd.G);
+  P.off_Gc = take(nd.G);
+  P.off_A = take(2 * nd.Amat);
+  P.off_Vw = take(2 * nd.Amat);
+  P.off_Vo = take(2 * nd.Amat);
+  P.off_w = take(2 * nd.w);
+  P.off_Ut = take(MAXD * nd.Ut);
+  P.off_Ut32 = take(MAXD * nd.Ut / 2 + 64);
+  P.total = o;
+  return P;
+}
+
+size_t hotrg_debug_workspace_bytes(int d, const int* dims, const int* kdims, int precision) {
+  if (!debug_dims_ok(d, dims, kdims) || !form_valid(precision)) return 0;
+  return debug_plan(d, dims, kdims, precision).total;
+}
+
+// Copy a double matrix into a float buffer or keep it (device).
+__global__ void k_f64_to_mt_f32(const double* src, float* dst, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+__global__ void k_mt_f32_to_f64(const float* src, double* dst, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = (double)src[i];
+}
+__global__ void k_copy_f64(const double* src, double* dst, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+__global__ void k_maxabs_f64(const double* src, long n, DevState* st) {
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    mx = fmax(mx, fabs(src[i]));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax((unsigned long long*)&st->maxabs, __double_as_longlong(red[0]));
+}
+
+int hotrg_debug_contract(int d, const int* dims, const int* kdims, int precision, const double* T_dev,
+                         const double* const* U_dev, double* Tnext_dev, void* workspace, size_t ws_bytes,
+                         void* stream) {
+  if (!debug_dims_ok(d, dims, kdims) || !kdims || !form_valid(precision) || !T_dev || !U_dev || !Tnext_dev ||
+      !workspace)
+    return fail(nullptr, HOTRG_E_ARG, "invalid argument");
+  for (int j = 0; j < d - 1; ++j)
+    if (!U_dev[j]) return fail(nullptr, HOTRG_E_ARG, "U is NULL");
+  Plan P = debug_plan(d, dims, kdims, precision);
+  if (ws_bytes < P.total) return fail(nullptr, HOTRG_E_OOM, "workspace too small");
+  hotrg_handle hh;
+  hotrg_handle* h = &hh;
+  h->form = precision;
+  h->ws = (char*)workspace;
+  h->ws_bytes = ws_bytes;
+  h->s = (hipStream_t)stream;
+  h->plan = P;
+  h->opts.chunk = 0;
+  h->ld.d = d;
+  for (int i = 0; i < d; ++i) h->ld.chi[i] = dims[i];
+  long H = 1, Hn = dims[0];
+  for (int i = 0; i < d; ++i) H *= dims[i];
+  for (int j = 0; j < d - 1; ++j) Hn *= kdims[j];
+  const long ut_stride = P.need.Ut / 8;
+  HIPCHK(h, hipMemsetAsync(h->ws, 0, P.off_T, h->s));
+  for (int j = 0; j < d - 1; ++j) {
+    const long nu = (long)dims[j + 1] * dims[j + 1] * kdims[j];
+    double* U = h->at<double>(P.off_Ut) + j * ut_stride;
+    float* U32 = h->at<float>(P.off_Ut32) + j * ut_stride;
+    hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(nu)), dim3(256), 0, h->s, U_dev[j], U, nu);
+    hipLaunchKernelGGL(k_f64_to_mt_f32, dim3(grid_for(nu)), dim3(256), 0, h->s, U_dev[j], U32, nu);
+  }
+  void* T = h->at<void>(P.off_T);
+  void* Tn = h->at<void>(P.off_Tn);
+  hipLaunchKernelGGL(k_maxabs_f64, dim3(grid_for(H * H)), dim3(256), 0, h->s, T_dev, H * H, h->st());
+  if (precision == HOTRG_FP64) {
+    hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(H * H)), dim3(256), 0, h->s, T_dev, (double*)T, H * H);
+  } else {
+    hipLaunchKernelGGL(k_f64_to_mt_f32, dim3(grid_for(H * H)), dim3(256), 0, h->s, T_dev, (float*)T, H * H);
+  }
+  int rc = enqueue_contract(h, T, Tn, h->ld, kdims);
+  if (rc) return rc;
+  if (precision == HOTRG_FP64)
+    hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (const double*)Tn, Tnext_dev,
+                       Hn * Hn);
+  else
+    hipLaunchKernelGGL(k_mt_f32_to_f64, dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (const float*)Tn, Tnext_dev,
+                       Hn * Hn);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  return HOTRG_OK;
+}
+
+int hotrg_debug_gram(int d, const int* dims, int dir, int side, const double* T_dev, double* A_dev,
+                     void* workspace, size_t ws_bytes, void* stream) {
+  if (!debug_dims_ok(d, dims, nullptr) || dir < 1 || dir >= d || side < 0 || side > 1 || !T_dev || !A_dev ||
+      !workspace)
+    return fail(nullptr, HOTRG_E_ARG, "invalid argument");
+  Plan P = debug_plan(d, dims, nullptr, HOTRG_FP64);
+  if (ws_bytes < P.total) return fail(nullptr, HOTRG_E_OOM, "workspace too small");
+  hotrg_handle hh;
+  hotrg_handle* h = &hh;
+  h->form = HOTRG_FP64;
+  h->ws = (char*)workspace;
+  h->s = (hipStream_t)stream;
+  h->plan = P;
+  h->ld.d = d;
+  for (int i = 0; i < d; ++i) h->ld.chi[i] = dims[i];
+  int rc = enqueue_gram(h, T_dev, true, h->ld, dir, side, A_dev);
+  if (rc) return rc;
+  HIPCHK(h, hipStreamSynchronize(h->s));
+  return HOTRG_OK;
+}
+
+size_t hotrg_debug_eigh_workspace_bytes(int n, int batch) {
+  if (n < 1 || n > 2 * JAC_MAXPAIR || batch < 1) return 0;
+  return roundup(sizeof(DevState), ALIGN) + (size_t)batch * n * n * 8;
+}
+
+int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_dev, void* workspace,
+                     size_t ws_bytes, void* stream) {
+  if (n < 1 || n > 2 * JAC_MAXPAIR || batch < 1 || !A_dev || !w_dev || !V_dev || !workspace)
+    return fail(nullptr, HOTRG_E_ARG, "invalid argument");
+  if (ws_bytes < hotrg_debug_eigh_workspace_bytes(n, batch)) return fail(nullptr, HOTRG_E_OOM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  DevState* dst = (DevState*)workspace;
+  double* work = (double*)((char*)workspace + roundup(sizeof(DevState), ALIGN));
+  hipError_t e = hipMemsetAsync(dst, 0, sizeof(DevState), s);
+  if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
+  hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(JAC_THREADS), 0, s, A_dev, work, w_dev, V_dev, n, 60, dst);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
+  DevState hs;
+  e = hipMemcpy(&hs, dst, sizeof(DevState), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
+  if (hs.eig_fail) return fail(nullptr, HOTRG_E_NUMERIC, "Jacobi did not converge");
+  return HOTRG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,837 @@
+// Device kernels of the HOTRG step for gfx950 (CDNA4).
+//
+// Storage order of a local tensor (d = 2 or 3): T[c][n_1]..[n_{d-1}][c'][n'_1]..[n'_{d-1}],
+// i.e. an H x H row-major matrix with H = chi_c * b, b = prod_j chi_{n_j}.  A "half index"
+// h = c * b + nb where nb = n_1 * chi_2 + n_2 (3D) or n_1 (2D).
+//
+// Hat and check copies (Section 3.2): the hat copy supplies the new c, the check copy the
+// new c'; rho joins the hat copy's c' to the check copy's c.  Merged indices of the
+// isometries are (hat check) = hat + chi_{n_j} * check.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+
+constexpr int NSPEC = 24;       // normalised eigenvalues kept per decomposition
+constexpr int MAXD = 3;
+
+// Device-resident state of one run: lnZ/V bookkeeping of Section 4.1.1.
+struct DevState {
+  double lnz;          // ln Z^(p) / V^(p)
+  double lnz0;         // ln Z^(0) / V^(0) = ln Tr T^(init)
+  double f;            // f^(p) = 1 / Tr T^(p), applied to the new tensor
+  double maxabs;       // max |T| of the current (normalised) tensor
+  double inv_scale;    // 1 / (s_A s_B) applied to the FP16-form products
+  int err;             // sticky error code (HOTRG_E_*)
+  int p;               // steps done
+  int eig_fail;        // eigensolver did not converge
+  int pad;
+};
+
+struct StepRec {
+  double trace, lnz, gu_wen;
+  double eps[MAXD], eps_p[MAXD];
+  int chose_prime[MAXD], truncated[MAXD], chi_new[MAXD], kept[MAXD], dims_before[MAXD];
+  int axis, p, nspec[MAXD][2], pad;
+  double spec[MAXD][2][NSPEC];
+};
+
+// ---------------------------------------------------------------------------
+// Precision forms: operand storage and conversion (IEEE round to nearest even)
+// ---------------------------------------------------------------------------
+
+__device__ inline uint16_t f32_to_bf16_rne(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  uint32_t r = 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)((u + r) >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t b) {
+  return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+// Power-of-two scale for FP16 operands: the largest 2^e with bound * 2^e <= 2^14.
+__device__ inline double fp16_scale_for(double bound) {
+  if (!(bound > 0.0)) return 1.0;
+  int e;
+  frexp(bound, &e);                 // bound = m 2^e, 0.5 <= m < 1  ->  bound < 2^e
+  return ldexp(1.0, 14 - e);        // bound * scale < 2^14
+}
+
+enum Form { F_FP64 = 0, F_FP32 = 1, F_BF16 = 2, F_FP16 = 3, F_SPLIT_BF16 = 4, F_SPLIT_FP16 = 5 };
+
+// Write value x (already scaled) in form F at position i of plane 0 (and plane 1 at +plane).
+template <int F> struct Store;
+template <> struct Store<F_FP64> {
+  typedef double T;
+  __device__ static void put(T* p, long i, long, double x) { p[i] = x; }
+};
+template <> struct Store<F_FP32> {
+  typedef float T;
+  __device__ static void put(T* p, long i, long, double x) { p[i] = (float)x; }
+};
+template <> struct Store<F_BF16> {
+  typedef uint16_t T;
+  __device__ static void put(T* p, long i, long, double x) { p[i] = f32_to_bf16_rne((float)x); }
+};
+template <> struct Store<F_FP16> {
+  typedef _Float16 T;
+  __device__ static void put(T* p, long i, long, double x) { p[i] = (_Float16)(float)x; }
+};
+template <> struct Store<F_SPLIT_BF16> {
+  typedef uint16_t T;
+  __device__ static void put(T* p, long i, long plane, double x) {
+    float xf = (float)x;
+    uint16_t hi = f32_to_bf16_rne(xf);
+    float lo = xf - bf16_to_f32(hi);
+    p[i] = hi;
+    p[i + plane] = f32_to_bf16_rne(lo);
+  }
+};
+template <> struct Store<F_SPLIT_FP16> {
+  typedef _Float16 T;
+  __device__ static void put(T* p, long i, long plane, double x) {
+    float xf = (float)x;
+    _Float16 hi = (_Float16)xf;
+    float lo = xf - (float)hi;
+    p[i] = hi;
+    p[i + plane] = (_Float16)lo;
+  }
+};
+
+template <int F> struct FormInfo {
+  static constexpr bool fp16 = (F == F_FP16 || F == F_SPLIT_FP16);
+  static constexpr int planes = (F == F_SPLIT_BF16 || F == F_SPLIT_FP16) ? 2 : 1;
+};
+
+// ---------------------------------------------------------------------------
+// MFMA operand traits.  For all instructions used here, lane l of a wave supplies
+// row (l % 16) and the KL consecutive k-elements starting at KL * (l / 16) of both
+// operands (A as M x K, B^T as N x K).  Accumulator register i (< 4) of lane l holds
+// D[out_row(l, i)][l % 16]: rows 4 (l / 16) + i for the FP32-accumulating instructions,
+// rows 4 i + l / 16 for the FP64 one (its 16 x 16 result is split in single-row groups).
+// ---------------------------------------------------------------------------
+
+struct OpF64 {
+  typedef double T; typedef double Acc; typedef d4 AccV; typedef double Frag;
+  static constexpr int KL = 1, KP = 4;
+  __device__ static AccV mma(Frag a, Frag b, AccV c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static Frag ld(const T* p) { return *p; }
+  __device__ static int out_row(int lane, int i) { return 4 * i + (lane >> 4); }
+};
+struct OpF32 {
+  typedef float T; typedef float Acc; typedef f4 AccV; typedef float Frag;
+  static constexpr int KL = 1, KP = 4;
+  __device__ static AccV mma(Frag a, Frag b, AccV c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static Frag ld(const T* p) { return *p; }
+  __device__ static int out_row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+struct OpF16 {
+  typedef _Float16 T; typedef float Acc; typedef f4 AccV; typedef h8 Frag;
+  static constexpr int KL = 8, KP = 32;
+  __device__ static AccV mma(Frag a, Frag b, AccV c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  __device__ static Frag ld(const T* p) { return *(const Frag*)p; }
+  __device__ static int out_row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+struct OpBF16 {
+  typedef uint16_t T; typedef float Acc; typedef f4 AccV; typedef b8 Frag;
+  static constexpr int KL = 8, KP = 32;
+  __device__ static AccV mma(Frag a, Frag b, AccV c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ static Frag ld(const T* p) { return *(const Frag*)p; }
+  __device__ static int out_row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
+template <int F> struct OpOf;
+template <> struct OpOf<F_FP64> { typedef OpF64 type; };
+template <> struct OpOf<F_FP32> { typedef OpF32 type; };
+template <> struct OpOf<F_BF16> { typedef OpBF16 type; };
+template <> struct OpOf<F_FP16> { typedef OpF16 type; };
+template <> struct OpOf<F_SPLIT_BF16> { typedef OpBF16 type; };
+template <> struct OpOf<F_SPLIT_FP16> { typedef OpF16 type; };
+
+// ---------------------------------------------------------------------------
+// TN GEMM on MFMA:  C[z][m][n] = scale * sum_{k in chunk z} A[m][k] * B[n][k]
+// A: Mp x Kp (lda), B: Np x Kp (ldb), both K-contiguous and zero-padded to the tile
+// sizes; C: row-major (ldc), one slice per K-chunk z (split-K, reduced elsewhere in a
+// fixed order).  Split forms add hi*hi + hi*lo + lo*hi, the lo planes at +a_plane/+b_plane.
+// 256 threads = 4 waves in a 2 x 2 grid; each wave owns a (BM/2) x (BN/2) sub-tile.
+// ---------------------------------------------------------------------------
+
+template <class Op, int PLANES, int BM, int BN, int BK>
+__global__ __launch_bounds__(256) void k_gemm_tn(
+    const typename Op::T* __restrict__ A, long lda, long a_plane,
+    const typename Op::T* __restrict__ B, long ldb, long b_plane,
+    typename Op::Acc* __restrict__ C, long ldc, long c_zstride, int kchunk,
+    const double* __restrict__ scale_ptr, double scale_mult) {
+  typedef typename Op::T T;
+  typedef typename Op::AccV AccV;
+  typedef typename Op::Frag Frag;
+  constexpr int VE = 16 / sizeof(T);          // elements per 16-byte vector
+  constexpr int LDSW = BK + VE;               // padded LDS row (elements)
+  constexpr int WM = BM / 2, WN = BN / 2, MI = WM / 16, NI = WN / 16;
+  constexpr int AV = BM * BK / VE, BV = BN * BK / VE, RV = BK / VE;
+  __shared__ __attribute__((aligned(16))) T sA[PLANES][BM * LDSW];
+  __shared__ __attribute__((aligned(16))) T sB[PLANES][BN * LDSW];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long m0 = (long)blockIdx.x * BM, n0 = (long)blockIdx.y * BN;
+  const long kbeg = (long)blockIdx.z * kchunk, kend = kbeg + kchunk;
+
+  AccV acc[MI][NI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = AccV{0, 0, 0, 0};
+
+  for (long k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int p = 0; p < PLANES; ++p) {
+      for (int v = tid; v < AV; v += 256) {
+        const int r = v / RV, cv = v % RV;
+        *(uint4*)&sA[p][r * LDSW + cv * VE] =
+            *(const uint4*)(A + p * a_plane + (m0 + r) * lda + k0 + cv * VE);
+      }
+      for (int v = tid; v < BV; v += 256) {
+        const int r = v / RV, cv = v % RV;
+        *(uint4*)&sB[p][r * LDSW + cv * VE] =
+            *(const uint4*)(B + p * b_plane + (n0 + r) * ldb + k0 + cv * VE);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += Op::KP) {
+      Frag a[PLANES][MI], b[PLANES][NI];
+#pragma unroll
+      for (int p = 0; p < PLANES; ++p) {
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+          a[p][i] = Op::ld(&sA[p][(wm * WM + i * 16 + (lane & 15)) * LDSW + kk + Op::KL * (lane >> 4)]);
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          b[p][j] = Op::ld(&sB[p][(wn * WN + j * 16 + (lane & 15)) * LDSW + kk + Op::KL * (lane >> 4)]);
+      }
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+          if constexpr (PLANES == 2) {
+            acc[i][j] = Op::mma(a[0][i], b[PLANES - 1][j], acc[i][j]);
+            acc[i][j] = Op::mma(a[PLANES - 1][i], b[0][j], acc[i][j]);
+          }
+          acc[i][j] = Op::mma(a[0][i], b[0][j], acc[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+
+  const double s = (scale_ptr ? *scale_ptr : 1.0) * scale_mult;
+  typename Op::Acc* Cz = C + (long)blockIdx.z * c_zstride;
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long row = m0 + wm * WM + i * 16 + Op::out_row(lane, r);
+        const long col = n0 + wn * WN + j * 16 + (lane & 15);
+        Cz[row * ldc + col] = (typename Op::Acc)(acc[i][j][r] * s);
+      }
+}
+
+// Fixed-order reduction of split-K slices: out[r][c] = sum_z part[z][r][c] for r < R, c < R.
+__global__ void k_reduce_z(const double* __restrict__ part, long zstride, long ldp, int Z, int R,
+                           double* __restrict__ out) {
+  const long n = (long)R * R;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long r = i / R, c = i % R;
+    double s = 0.0;
+    for (int z = 0; z < Z; ++z) s += part[z * zstride + r * ldp + c];
+    out[i] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Generic leg permutation into a padded 2-D matrix:
+//   dst[row * ldd + col] = scale * src[sum_i idx_i * sstride_i]
+// where (row, col) decomposes row-major over out-dims od[0..nrow-1] | od[nrow..nd-1].
+// Padding (row >= rows or col >= cols) is written as zero.
+// ---------------------------------------------------------------------------
+struct PermSpec {
+  int nd, nrow;
+  int od[8];
+  long sstride[8];
+  long rows, cols, rows_p, ldd;
+};
+
+template <class S, class D>
+__global__ void k_permute(const S* __restrict__ src, D* __restrict__ dst, PermSpec ps, double scale) {
+  const long total = ps.rows_p * ps.ldd;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long row = i / ps.ldd, col = i % ps.ldd;
+    if (row >= ps.rows || col >= ps.cols) { dst[i] = (D)0; continue; }
+    long off = 0, rr = row, cc = col;
+    for (int k = ps.nd - 1; k >= ps.nrow; --k) { off += (cc % ps.od[k]) * ps.sstride[k]; cc /= ps.od[k]; }
+    for (int k = ps.nrow - 1; k >= 0; --k) { off += (rr % ps.od[k]) * ps.sstride[k]; rr /= ps.od[k]; }
+    dst[i] = (D)((double)src[off] * scale);
+  }
+}
+
+// A operand of the bottleneck in form F: A[m][k] = s_A * T[m][k] for m, k < H, zero padded
+// to Mp x Kp.  s_A = 1 except for the FP16 forms (power of two from max|T|).
+template <class MT, int F>
+__global__ void k_make_a(const MT* __restrict__ T, int H, typename Store<F>::T* __restrict__ A, long Mp,
+                         long Kp, const DevState* __restrict__ st) {
+  const double sA = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs) : 1.0;
+  const long plane = Mp * Kp;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < plane; i += (long)gridDim.x * blockDim.x) {
+    const long m = i / Kp, k = i % Kp;
+    const double x = (m < H && k < H) ? (double)T[m * H + k] * sA : 0.0;
+    Store<F>::put(A, i, plane, x);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Three-step Gram matrices (Section 3.2, eqs. Aux_Tensor_hat_S / Aux_Tensor_check_S):
+// the GEMM above gives G = X X^T with X rows (f, rho), f the side leg and rho the
+// c' leg (hat) or the c leg (check).  Then
+//   A[(fh + chi_s fc), (gh + chi_s gc)] = sum_{rho, eta} Gh[fh, rho; gh, eta] Gc[fc, rho; gc, eta].
+// ---------------------------------------------------------------------------
+__global__ void k_gram_combine(const double* __restrict__ Gh, const double* __restrict__ Gc, int chis,
+                               int chic, double* __restrict__ A) {
+  const int n = chis * chis, R = chis * chic;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (long)n * n; i += (long)gridDim.x * blockDim.x) {
+    const int row = (int)(i / n), col = (int)(i % n);
+    const int fh = row % chis, fc = row / chis, gh = col % chis, gc = col / chis;
+    double s = 0.0;
+    for (int r = 0; r < chic; ++r)
+      for (int e = 0; e < chic; ++e)
+        s += Gh[(long)(fh * chic + r) * R + gh * chic + e] * Gc[(long)(fc * chic + r) * R + gc * chic + e];
+    A[i] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric eigendecomposition: parallel cyclic Jacobi (round-robin ordering), one
+// workgroup per matrix, FP64.  Rotations skip |a_pq| <= 1e-16 sqrt(|a_pp a_qq|) and
+// entries below 1e-18 max|a_ii|; converged when a sweep performs no rotation.
+// Output: eigenvalues descending in w, eigenvectors as the matching columns of Vout.
+// ---------------------------------------------------------------------------
+constexpr int JAC_THREADS = 1024;
+constexpr int JAC_MAXPAIR = 512;     // n <= 1024
+
+__device__ inline void rr_pair(int r, int k, int m, int& p, int& q) {
+  // circle method: player 0 fixed, players 1..m-1 rotate
+  if (k == 0) { p = 0; q = 1 + r % (m - 1); }
+  else { p = 1 + (r + k) % (m - 1); q = 1 + (r - k + (m - 1)) % (m - 1); }
+  if (p > q) { int t = p; p = q; q = t; }
+}
+
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ Ab, double* __restrict__ Vb,
+                                                        double* __restrict__ wb, double* __restrict__ Vout,
+                                                        int n, int max_sweeps, DevState* st) {
+  __shared__ double cs[JAC_MAXPAIR], sn[JAC_MAXPAIR];
+  __shared__ int pp[JAC_MAXPAIR], qq[JAC_MAXPAIR];
+  __shared__ int rot_count;
+  __shared__ double dmax_s;
+  __shared__ double red[JAC_THREADS / 64];
+  double* A = Ab + (long)blockIdx.x * n * n;
+  double* V = Vb + (long)blockIdx.x * n * n;
+  double* w = wb + (long)blockIdx.x * n;
+  double* Vo = Vout + (long)blockIdx.x * n * n;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int m = n + (n & 1), half = m / 2;
+
+  for (long i = tid; i < (long)n * n; i += nt) V[i] = (i / n == i % n) ? 1.0 : 0.0;
+  // absolute floor from the largest diagonal entry
+  double dm = 0.0;
+  for (int i = tid; i < n; i += nt) dm = fmax(dm, fabs(A[(long)i * n + i]));
+  for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o));
+  if ((tid & 63) == 0) red[tid >> 6] = dm;
+  __syncthreads();
+  if (tid == 0) {
+    double x = 0.0;
+    for (int i = 0; i < nt / 64; ++i) x = fmax(x, red[i]);
+    dmax_s = x;
+  }
+  __syncthreads();
+  const double floor_abs = 1e-18 * dmax_s;
+
+  int sweep = 0;
+  bool done = (n <= 1);
+  for (; sweep < max_sweeps && !done; ++sweep) {
+    if (tid == 0) rot_count = 0;
+    __syncthreads();
+    for (int r = 0; r < m - 1; ++r) {
+      for (int k = tid; k < half; k += nt) {
+        int p, q;
+        rr_pair(r, k, m, p, q);
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[(long)p * n + q];
+          const double app = A[(long)p * n + p], aqq = A[(long)q * n + q];
+          if (fabs(apq) > floor_abs && fabs(apq) > 1e-16 * sqrt(fabs(app * aqq))) {
+            const double th = (aqq - app) / (2.0 * apq);
+            const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+            atomicAdd(&rot_count, 1);
+          }
+        }
+        cs[k] = c; sn[k] = s; pp[k] = p; qq[k] = q;
+      }
+      __syncthreads();
+      // A <- J^T A J on the 2x2 blocks (P, Q), P <= Q; the (Q, P) block is its transpose.
+      const long nblk = (long)half * (half + 1) / 2;
+      for (long bidx = tid; bidx < nblk; bidx += nt) {
+        // map bidx -> (P, Q) with P <= Q
+        int P = (int)((sqrt(8.0 * (double)bidx + 1.0) - 1.0) / 2.0);
+        while ((long)(P + 1) * (P + 2) / 2 <= bidx) ++P;
+        while ((long)P * (P + 1) / 2 > bidx) --P;
+        const int Q2 = (int)(bidx - (long)P * (P + 1) / 2);   // Q2 <= P
+        const int Pa = Q2, Qa = P;                              // Pa <= Qa
+        const double cP = cs[Pa], sP = sn[Pa], cQ = cs[Qa], sQ = sn[Qa];
+        const int p1 = pp[Pa], q1 = qq[Pa], p2 = pp[Qa], q2 = qq[Qa];
+        const bool vq1 = q1 < n, vq2 = q2 < n;
+        const double a = A[(long)p1 * n + p2];
+        const double b = vq2 ? A[(long)p1 * n + q2] : 0.0;
+        const double c_ = vq1 ? A[(long)q1 * n + p2] : 0.0;
+        const double d = (vq1 && vq2) ? A[(long)q1 * n + q2] : 0.0;
+        // rows: row_p' = cP row_p - sP row_q, row_q' = sP row_p + cP row_q
+        const double rpp = cP * a - sP * c_, rpq = cP * b - sP * d;
+        const double rqp = sP * a + cP * c_, rqq = sP * b + cP * d;
+        // cols: col_p' = cQ col_p - sQ col_q, col_q' = sQ col_p + cQ col_q
+        double npp = cQ * rpp - sQ * rpq, npq = sQ * rpp + cQ * rpq;
+        double nqp = cQ * rqp - sQ * rqq, nqq = sQ * rqp + cQ * rqq;
+        if (Pa == Qa) {           // diagonal block: keep it exactly symmetric
+          const double off = 0.5 * (npq + nqp);
+          npq = off; nqp = off;
+        }
+        A[(long)p1 * n + p2] = npp;
+        if (vq2) A[(long)p1 * n + q2] = npq;
+        if (vq1) A[(long)q1 * n + p2] = nqp;
+        if (vq1 && vq2) A[(long)q1 * n + q2] = nqq;
+        if (Pa != Qa) {
+          A[(long)p2 * n + p1] = npp;
+          if (vq2) A[(long)q2 * n + p1] = npq;
+          if (vq1) A[(long)p2 * n + q1] = nqp;
+          if (vq1 && vq2) A[(long)q2 * n + q1] = nqq;
+        }
+      }
+      // V <- V J
+      for (long idx = tid; idx < (long)n * half; idx += nt) {
+        const int i = (int)(idx / half), Q = (int)(idx % half);
+        const int p = pp[Q], q = qq[Q];
+        if (q >= n) continue;
+        const double c = cs[Q], s = sn[Q];
+        const double vp = V[(long)i * n + p], vq = V[(long)i * n + q];
+        V[(long)i * n + p] = c * vp - s * vq;
+        V[(long)i * n + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    done = (rot_count == 0);
+    __syncthreads();
+  }
+  if (!done && tid == 0) atomicOr(&st->eig_fail, 1);
+  // sort eigenvalues descending (ties by index) and permute the eigenvector columns
+  for (int i = tid; i < n; i += nt) {
+    const double wi = A[(long)i * n + i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double wj = A[(long)j * n + j];
+      rank += (wj > wi) || (wj == wi && j < i);
+    }
+    w[rank] = wi;
+    for (int r = 0; r < n; ++r) Vo[(long)r * n + rank] = V[(long)r * n + i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Judgement values, choice and truncation (Sections 2, 4.2.6-4.2.7):
+//   epsilon = sum_{l >= chi_new} max(lambda_l, 0),  U if epsilon < epsilon' else U'.
+// When the cut splits a multiplet of equal eigenvalues (relative difference at most
+// MULT_RTOL, eigenvalue at least MULT_ATOL of the largest) the whole multiplet is
+// dropped by zeroing its columns: "the first chi columns" are not unique there.
+// w: [2][n] (side 0 = A, side 1 = A'), V: [2][n][n].  identity != 0: untruncated, the
+// isometry is the identity (any orthonormal basis is exact when chi_new = n).
+// ---------------------------------------------------------------------------
+constexpr double MULT_RTOL = 1e-10, MULT_ATOL = 1e-12;
+
+__global__ void k_choose(const double* __restrict__ w, const double* __restrict__ V, int n, int chi_new,
+                         int identity, double* __restrict__ Ut, float* __restrict__ Ut32, StepRec* rec,
+                         int dir_index) {
+  __shared__ double eps_s[2];
+  __shared__ int prime_s, kept_s;
+  const int tid = threadIdx.x;
+  if (identity) {
+    for (int i = tid; i < n * n; i += blockDim.x) {
+      const double v = (i / n == i % n) ? 1.0 : 0.0;
+      Ut[i] = v;
+      Ut32[i] = (float)v;
+    }
+    if (tid == 0) {
+      rec->eps[dir_index] = 0.0; rec->eps_p[dir_index] = 0.0;
+      rec->chose_prime[dir_index] = 1; rec->truncated[dir_index] = 0;
+      rec->chi_new[dir_index] = n; rec->kept[dir_index] = n;
+      rec->nspec[dir_index][0] = 0; rec->nspec[dir_index][1] = 0;
+    }
+    return;
+  }
+  if (tid < 2) {
+    double e = 0.0;
+    for (int l = chi_new; l < n; ++l) e += fmax(w[tid * n + l], 0.0);
+    eps_s[tid] = e;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int side = !(eps_s[0] < eps_s[1]);
+    const double* lam = w + side * n;
+    int k = chi_new;
+    if (k < n)
+      while (k > 1 && lam[k - 1] >= MULT_ATOL * lam[0] && lam[k - 1] - lam[k] <= MULT_RTOL * lam[k - 1]) --k;
+    prime_s = side;
+    kept_s = k;
+  }
+  __syncthreads();
+  const int side = prime_s, kept = kept_s;
+  const double* Vs = V + (long)side * n * n;
+  for (int i = tid; i < n * chi_new; i += blockDim.x) {
+    const int r = i / chi_new, c = i % chi_new;
+    const double v = c < kept ? Vs[(long)r * n + c] : 0.0;
+    Ut[i] = v;
+    Ut32[i] = (float)v;
+  }
+  if (tid == 0) {
+    rec->eps[dir_index] = eps_s[0]; rec->eps_p[dir_index] = eps_s[1];
+    rec->chose_prime[dir_index] = side; rec->truncated[dir_index] = 1;
+    rec->chi_new[dir_index] = chi_new; rec->kept[dir_index] = kept;
+    for (int s = 0; s < 2; ++s) {
+      const int ns = n < NSPEC ? n : NSPEC;
+      rec->nspec[dir_index][s] = ns;
+      const double w0 = w[s * n];
+      for (int l = 0; l < ns; ++l) rec->spec[dir_index][s][l] = w[s * n + l] / w0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Prime chain (Section 4.2.8, eqs. TU1..TUNCD) written straight into the B operand
+// of the bottleneck GEMM (B^T rows n, K-contiguous):
+//   3D:  B[(g - g0) b + nc][rho b + (nh1' chi2 + nh2')] =
+//          sum_{nc1', nc2'} U1[nh1' + chi1 nc1', n1'] U2[nh2' + chi2 nc2', n2'] T[rho, nc][c', nc1', nc2']
+//   2D:  B[(g - g0) b + nc][rho b + nh1'] = sum_{nc1'} U1[nh1' + chi1 nc1', n1'] T[rho, nc][c', nc1']
+// with g = (n1' chi2n + n2') chi_c + c' (3D) or n1' chi_c + c' (2D): the column index of
+// the renamed new tensor.  One workgroup per (check row h = (rho, nc), c'); the chunk
+// covers pair groups pr in [pr0, pr1) (pr = n1' chi2n + n2' or n1').
+// ---------------------------------------------------------------------------
+struct Dims {
+  int d, chic, chi1, chi2, k1, k2, b, H;   // chi2 = k2 = 1 for d = 2
+};
+
+template <class MT, class UT, int F>
+__global__ __launch_bounds__(256) void k_pstage(const MT* __restrict__ T, const UT* __restrict__ U1,
+                                                const UT* __restrict__ U2, Dims dm, int pr0, int pr1,
+                                                typename Store<F>::T* __restrict__ B, long ldb, long bplane,
+                                                const DevState* __restrict__ st) {
+  __shared__ MT X[256];
+  __shared__ MT Z[16 * 256];
+  const int tid = threadIdx.x;
+  const int h = blockIdx.x / dm.chic, cp = blockIdx.x % dm.chic;
+  const int b = dm.b, chi1 = dm.chi1, chi2 = dm.chi2;
+  const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * sqrt((double)b)) : 1.0;
+  const int rho = h / b, nc = h % b;
+  for (int i = tid; i < b; i += blockDim.x) X[i] = T[(long)h * dm.H + (long)cp * b + i];
+  __syncthreads();
+  const int npairs = pr1 - pr0;
+  if (dm.d == 3) {
+    const int n1lo = pr0 / dm.k2, n1hi = (pr1 - 1) / dm.k2;
+    const int nn1 = n1hi - n1lo + 1;
+    // Z[n1'][nh1'][nc2'] = sum_{nc1'} U1[nh1' + chi1 nc1', n1'] X[nc1'][nc2']
+    for (int i = tid; i < nn1 * b; i += blockDim.x) {
+      const int n1 = n1lo + i / b, r = i % b, nh1 = r / chi2, nc2 = r % chi2;
+      MT s = 0;
+      for (int nc1 = 0; nc1 < chi1; ++nc1) s += (MT)U1[(nh1 + chi1 * nc1) * dm.k1 + n1] * X[nc1 * chi2 + nc2];
+      Z[i] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < npairs * b; i += blockDim.x) {
+      const int pr = pr0 + i / b, r = i % b, nh1 = r / chi2, nh2 = r % chi2;
+      const int n1 = pr / dm.k2, n2 = pr % dm.k2;
+      const MT* z = &Z[(n1 - n1lo) * b + nh1 * chi2];
+      MT s = 0;
+      for (int nc2 = 0; nc2 < chi2; ++nc2) s += z[nc2] * (MT)U2[(nh2 + chi2 * nc2) * dm.k2 + n2];
+      const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
+      Store<F>::put(B, row * ldb + (long)rho * b + r, bplane, (double)s * sB);
+    }
+  } else {
+    for (int i = tid; i < npairs * b; i += blockDim.x) {
+      const int pr = pr0 + i / b, nh1 = i % b;
+      MT s = 0;
+      for (int nc1 = 0; nc1 < chi1; ++nc1) s += (MT)U1[(nh1 + chi1 * nc1) * dm.k1 + pr] * X[nc1];
+      const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
+      Store<F>::put(B, row * ldb + (long)rho * b + nh1, bplane, (double)s * sB);
+    }
+  }
+}
+
+// Zero the padding of a B operand: columns [K, Kp) of rows [0, N) and all of rows [N, Np).
+template <class ST>
+__global__ void k_zero_pad(ST* __restrict__ B, long N, long Np, long K, long Kp, long plane, int planes) {
+  const long padc = Kp - K;
+  const long n1 = N * padc, n2 = (Np - N) * Kp;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n1 + n2; i += (long)gridDim.x * blockDim.x) {
+    long off;
+    if (i < n1) off = (i / padc) * Kp + K + (i % padc);
+    else off = N * Kp + (i - n1);
+    for (int p = 0; p < planes; ++p) B[off + p * plane] = (ST)0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Non-prime chain (eqs. AfterBNNCD..AfterBN1) on the bottleneck output
+//   C[c b + nh][(g - g0) b + nc]   (nh = (nh1, nh2), nc = (nc1, nc2))
+// and the renaming of Section 3.1.3: the result goes to T^next[hbar][g] with
+// hbar = (n1 chi2n + n2) chi_c + c (3D) or n1 chi_c + c (2D).  One workgroup per (c, g).
+// ---------------------------------------------------------------------------
+template <class AT, class MT, class UT>
+__global__ __launch_bounds__(256) void k_nstage3(const AT* __restrict__ C, long ldc, const UT* __restrict__ U1,
+                                                 const UT* __restrict__ U2, Dims dm, int g0, int gcount,
+                                                 MT* __restrict__ Tn) {
+  __shared__ MT tile[16 * 256];
+  __shared__ MT Q[256];
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x / gcount, gl = blockIdx.x % gcount, g = g0 + gl;
+  const int b = dm.b, chi1 = dm.chi1, chi2 = dm.chi2, k1 = dm.k1, k2 = dm.k2;
+  const int Hn = k1 * k2 * dm.chic;
+  // thread roles
+  const int qa = tid / k2, qn2 = tid % k2;          // Q[nc1][n2]: nc1 = qa < chi1
+  const int on1 = tid / k2, on2 = tid % k2;         // out[n1][n2]: n1 = on1 < k1
+  MT acc = 0;
+  for (int nh1 = 0; nh1 < chi1; ++nh1) {
+    // rows c b + nh1 chi2 + nh2 (nh2 < chi2), all b columns of block g
+    for (int i = tid; i < chi2 * b; i += blockDim.x) {
+      const int nh2 = i / b, col = i % b;
+      tile[i] = (MT)C[(long)(c * b + nh1 * chi2 + nh2) * ldc + (long)gl * b + col];
+    }
+    __syncthreads();
+    if (qa < chi1) {
+      MT s = 0;
+      for (int nh2 = 0; nh2 < chi2; ++nh2)
+        for (int nc2 = 0; nc2 < chi2; ++nc2)
+          s += (MT)U2[(nh2 + chi2 * nc2) * k2 + qn2] * tile[nh2 * b + qa * chi2 + nc2];
+      Q[qa * k2 + qn2] = s;
+    }
+    __syncthreads();
+    if (on1 < k1) {
+      for (int nc1 = 0; nc1 < chi1; ++nc1) acc += (MT)U1[(nh1 + chi1 * nc1) * k1 + on1] * Q[nc1 * k2 + on2];
+    }
+    __syncthreads();
+  }
+  if (on1 < k1) Tn[(long)((on1 * k2 + on2) * dm.chic + c) * Hn + g] = acc;
+}
+
+template <class AT, class MT, class UT>
+__global__ __launch_bounds__(64) void k_nstage2(const AT* __restrict__ C, long ldc, const UT* __restrict__ U1,
+                                                Dims dm, int g0, int gcount, MT* __restrict__ Tn) {
+  __shared__ MT tile[32 * 32];
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x / gcount, gl = blockIdx.x % gcount, g = g0 + gl;
+  const int chi1 = dm.chi1, k1 = dm.k1;
+  const int Hn = k1 * dm.chic;
+  for (int i = tid; i < chi1 * chi1; i += blockDim.x) {
+    const int nh1 = i / chi1, nc1 = i % chi1;
+    tile[i] = (MT)C[(long)(c * chi1 + nh1) * ldc + (long)gl * chi1 + nc1];
+  }
+  __syncthreads();
+  for (int n1 = tid; n1 < k1; n1 += blockDim.x) {
+    MT s = 0;
+    for (int nh1 = 0; nh1 < chi1; ++nh1)
+      for (int nc1 = 0; nc1 < chi1; ++nc1) s += (MT)U1[(nh1 + chi1 * nc1) * k1 + n1] * tile[nh1 * chi1 + nc1];
+    Tn[(long)(n1 * dm.chic + c) * Hn + g] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Trace, Gu-Wen ratio and lnZ/V (eqs. Trace_LocalTensor, ratio_X, eq_lnZ, K_recurrence):
+// t_p = Tr T^new = sum_h T[h][h];  lnZ^(p)/V^(p) = lnZ^(p-1)/V^(p-1) + ln(t_p) / 2^p;
+// f^(p) = 1/t_p.  Y[c][c'] = sum_n T^new[n.., n.., c, c'] where, in the renamed storage,
+// the old Current leg is the last slot: T^next[nb * chi_c + c][nb * chi_c + c'].
+// One workgroup of 256 threads; fixed-order reductions.
+// ---------------------------------------------------------------------------
+template <class MT>
+__global__ __launch_bounds__(256) void k_trace_lnz(const MT* __restrict__ Tn, int Hn, int chic_old,
+                                                   DevState* st, StepRec* rec, int p) {
+  __shared__ double red[256];
+  __shared__ double Y[32 * 32];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int h = tid; h < Hn; h += 256) s += (double)Tn[(long)h * Hn + h];
+  red[tid] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  const double t = red[0];
+  __syncthreads();
+  const int cc = chic_old, nb = Hn / cc;
+  for (int i = tid; i < cc * cc; i += 256) {
+    const int c = i / cc, c2 = i % cc;
+    double y = 0.0;
+    for (int n = 0; n < nb; ++n) y += (double)Tn[(long)(n * cc + c) * Hn + n * cc + c2];
+    Y[i] = y;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double ty = 0.0, ty2 = 0.0;
+    for (int c = 0; c < cc; ++c) {
+      ty += Y[c * cc + c];
+      for (int c2 = 0; c2 < cc; ++c2) ty2 += Y[c * cc + c2] * Y[c2 * cc + c];
+    }
+    const bool ok = (t > 0.0) && isfinite(t);
+    if (!ok && st->err == 0) st->err = 3;   // HOTRG_E_NUMERIC
+    if (st->eig_fail && st->err == 0) st->err = 3;
+    const double lnz = st->lnz + (ok ? log(t) : 0.0) / ldexp(1.0, p);
+    st->lnz = lnz;
+    st->f = ok ? 1.0 / t : 1.0;
+    st->p = p;
+    rec->trace = t;
+    rec->lnz = lnz;
+    rec->gu_wen = ty * ty / ty2;
+    rec->p = p;
+  }
+}
+
+// T <- f T over n elements, and max |f T| into st->maxabs (for the FP16 scaling).
+template <class MT>
+__global__ void k_scale(MT* __restrict__ T, long n, DevState* st) {
+  __shared__ double red[256];
+  const double f = st->f;
+  double mx = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const MT v = (MT)((double)T[i] * f);
+    T[i] = v;
+    mx = fmax(mx, fabs((double)v));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax((unsigned long long*)&st->maxabs, __double_as_longlong(red[0]));
+}
+
+__global__ void k_reset_maxabs(DevState* st) { st->maxabs = 0.0; }
+
+// 1 / (s_A s_B) for the FP16 forms: s_A from max|T|, s_B from the bound |B| <= sqrt(b) max|T|
+// (each prime-chain output is an isometry applied to a b-vector of T).
+__global__ void k_inv_scale_fp16(DevState* st, int b) {
+  const double sA = fp16_scale_for(st->maxabs);
+  const double sB = fp16_scale_for(st->maxabs * sqrt((double)b));
+  st->inv_scale = 1.0 / (sA * sB);
+}
+
+// Fresh step record.
+__global__ void k_rec_init(StepRec* rec, int p, int axis, int d, int c0, int c1, int c2) {
+  int* w = (int*)rec;
+  for (int i = threadIdx.x; i < (int)(sizeof(StepRec) / sizeof(int)); i += blockDim.x) w[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    rec->p = p;
+    rec->axis = axis;
+    rec->dims_before[0] = c0;
+    rec->dims_before[1] = c1;
+    rec->dims_before[2] = d == 3 ? c2 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial tensor (Section 2, eq. 4) with the bond factor X = U sqrt(Lambda) in closed
+// form.  Ising: W = [[e^{bJ}, e^{-bJ}], [e^{-bJ}, e^{bJ}]] has eigenvectors (1, 1)/sqrt2
+// (2 cosh bJ) and (1, -1)/sqrt2 (2 sinh bJ).  Potts: W = (e^{bJ} - 1) I + 1 1^T has
+// (1, .., 1)/sqrt q (e^{bJ} + q - 1) and the Helmert vectors (e^{bJ} - 1).
+// T0[h][h'] = sum_s V_s prod_legs X[s][k_leg], normalised by f^(0) = 1/Tr T0.
+// ---------------------------------------------------------------------------
+template <class MT>
+__global__ void k_init_tensor(MT* __restrict__ T, int kind, int d, int q, double beta, double J, double hfield,
+                              DevState* st) {
+  __shared__ double X[8 * 8];
+  __shared__ double V[8];
+  __shared__ double tr_s;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    if (kind == 0) {
+      const double ch = sqrt(cosh(beta * J)), sh = sqrt(sinh(beta * J));
+      X[0 * q + 0] = ch; X[0 * q + 1] = sh;
+      X[1 * q + 0] = ch; X[1 * q + 1] = -sh;
+      V[0] = exp(beta * hfield); V[1] = exp(-beta * hfield);
+    } else {
+      const double l0 = exp(beta * J) + q - 1, l1 = exp(beta * J) - 1;
+      for (int s = 0; s < q; ++s) {
+        X[s * q + 0] = sqrt(l0 / q);
+        for (int k = 1; k < q; ++k) {
+          const double nk = 1.0 / sqrt((double)k * (k + 1));
+          const double u = (s < k) ? nk : (s == k ? -k * nk : 0.0);
+          X[s * q + k] = u * sqrt(l1);
+        }
+        V[s] = 1.0;
+      }
+    }
+    // Tr T0 = sum_s V_s (sum_k X[s][k]^2)^d
+    double tr = 0.0;
+    for (int s = 0; s < q; ++s) {
+      double wss = 0.0;
+      for (int k = 0; k < q; ++k) wss += X[s * q + k] * X[s * q + k];
+      tr += V[s] * pow(wss, (double)d);
+    }
+    tr_s = tr;
+    st->lnz0 = log(tr);
+    st->lnz = log(tr);
+    st->f = 1.0 / tr;
+    st->p = 0;
+    st->err = 0;
+    st->eig_fail = 0;
+  }
+  __syncthreads();
+  int H = 1;
+  for (int i = 0; i < d; ++i) H *= q;
+  const double f = 1.0 / tr_s;
+  double mx = 0.0;
+  for (int i = tid; i < H * H; i += blockDim.x) {
+    double v = 0.0;
+    for (int s = 0; s < q; ++s) {
+      double prod = V[s];
+      int rem = i;
+      for (int l = 0; l < 2 * d; ++l) { prod *= X[s * q + rem % q]; rem /= q; }
+      v += prod;
+    }
+    T[i] = (MT)(v * f);
+    mx = fmax(mx, fabs(v * f));
+  }
+  // maxabs (single block)
+  __shared__ double red[256];
+  red[tid] = mx;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (tid < o) red[tid] = fmax(red[tid], red[tid + o]);
+    __syncthreads();
+  }
+  if (tid == 0) st->maxabs = red[0];
+}
+
+}  // namespace hk

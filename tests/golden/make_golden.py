@@ -1,0 +1,102 @@
+"""Write oracle fixtures for the physics configurations (calls only oracle/).
+
+Usage:  python tests/golden/make_golden.py config1 config2 [config3 ...]
+
+Each fixture is JSON: the configuration, per-run lnZ/V after every step, the
+trace t_p, the Gu-Wen ratio, the judgement values and the leading normalised
+spectrum of every decomposed Gram matrix, plus provenance (oracle commit, host,
+cores, wall time).  Stored values come from the FP64 oracle and nothing else.
+"""
+
+import json
+import math
+import os
+import platform
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import hotrg as H  # noqa: E402
+from tests import seeded_inputs as SI  # noqa: E402
+
+N_SPEC = 24
+
+
+def _record(rec):
+    out = dict(p=rec.p, lnz_per_site=rec.lnz_per_site, trace=rec.trace, gu_wen=rec.gu_wen,
+               dims_before=list(rec.dims_before), dirs={})
+    for j, t in rec.truncations.items():
+        lam, lam_p = t.lam, t.lam_p
+        out["dirs"][str(j)] = dict(
+            chi_new=t.chi_new, kept=t.kept, eps=t.eps, eps_p=t.eps_p, chose_prime=bool(t.chose_prime),
+            spec=[float(x / lam[0]) for x in lam[:N_SPEC]],
+            spec_p=[float(x / lam_p[0]) for x in lam_p[:N_SPEC]],
+            gap=float((lam[t.chi_new - 1] - lam[t.chi_new]) / lam[0]) if t.chi_new < lam.size else None,
+        )
+    return out
+
+
+def run_config(name, cfg, betas):
+    runs = []
+    for beta in betas:
+        t0 = time.time()
+        step_times = []
+        last = [time.time()]
+
+        def on_step(rec):
+            now = time.time()
+            step_times.append(now - last[0])
+            last[0] = now
+            print(f"  {name} beta={beta:.6f} step {rec.p} lnz/V={rec.lnz_per_site:.15f} "
+                  f"({step_times[-1]:.1f}s)", flush=True)
+
+        model = H.Model(cfg["kind"], cfg["d"], cfg["q"])
+        lnz0, recs = H.run(model, beta, cfg["chi"], cfg["steps"], on_step=on_step)
+        runs.append(dict(beta=beta, lnz0=lnz0, steps=[_record(r) for r in recs],
+                         step_seconds=step_times, wall_seconds=time.time() - t0))
+    return runs
+
+
+def provenance():
+    try:
+        rev = subprocess.check_output(["git", "-C", ROOT, "rev-parse", "HEAD"], text=True).strip()
+    except Exception:
+        rev = "unknown"
+    cpu = platform.processor()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(oracle_commit=rev, host_cpu=cpu, cores=os.cpu_count(),
+                numpy_blas_threads=os.environ.get("OMP_NUM_THREADS", "default"))
+
+
+def main(names):
+    table = {
+        "config1": (SI.CONFIG1, [1.0 / T for T in SI.CONFIG1["temps"]]),
+        "config2": (SI.CONFIG2, [1.0 / T for T in SI.CONFIG2["temps"]]),
+        "config3": (SI.CONFIG3, [1.0 / T for T in SI.CONFIG3["temps"]]),
+        "config5": (SI.CONFIG5, list(SI.CONFIG5["betas"])),
+    }
+    for name in names:
+        cfg, betas = table[name]
+        runs = run_config(name, cfg, betas)
+        doc = dict(config=name, kind=cfg["kind"], d=cfg["d"], q=cfg["q"], chi=cfg["chi"],
+                   steps=cfg["steps"], runs=runs, provenance=provenance(),
+                   source="oracle/hotrg.py (FP64 NumPy), written by tests/golden/make_golden.py")
+        path = os.path.join(HERE, f"{name}.json")
+        with open(path, "w") as f:
+            json.dump(doc, f, indent=1)
+        print("wrote", path, flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["config1", "config2"])

@@ -1,0 +1,95 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared symbol,
+and its host-side argument validation and workspace planning behave."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2110_03607_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hotrg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hotrg_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 14
+    L = P.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    # the binding covers the same set
+    assert sorted(P.exported_symbols()) == names
+
+
+def test_struct_layouts_match_header():
+    # hotrg_model: int, int, int, (pad), double, double
+    assert ctypes.sizeof(P.hotrg_model) == 32
+    assert ctypes.sizeof(P.hotrg_opts) == 16
+
+
+def _model(kind=P.HOTRG_ISING, d=3, q=2, J=1.0, h=0.0):
+    return P.hotrg_model(kind, d, q, J, h)
+
+
+def test_workspace_bytes_validation():
+    o = P.hotrg_opts(P.HOTRG_FP64, 32, 0, 0)
+    assert P.hotrg_workspace_bytes(_model(), 16, o) > 0
+    assert P.hotrg_workspace_bytes(_model(d=4), 16, o) == 0            # d not supported
+    assert P.hotrg_workspace_bytes(_model(), 17, o) == 0               # chi above the 3D maximum
+    assert P.hotrg_workspace_bytes(_model(d=2), 32, o) > 0
+    assert P.hotrg_workspace_bytes(_model(q=3), 16, o) == 0            # Ising needs q = 2
+    assert P.hotrg_workspace_bytes(_model(P.HOTRG_POTTS, 3, 3), 16, o) > 0
+    assert P.hotrg_workspace_bytes(_model(P.HOTRG_POTTS, 3, 3), 2, o) == 0   # chi < q
+    bad = P.hotrg_opts(9, 32, 0, 0)
+    assert P.hotrg_workspace_bytes(_model(), 16, bad) == 0
+
+
+def test_workspace_grows_with_chi_and_form():
+    o64 = P.hotrg_opts(P.HOTRG_FP64, 32, 0, 0)
+    o32 = P.hotrg_opts(P.HOTRG_FP32, 32, 0, 0)
+    sizes = [P.hotrg_workspace_bytes(_model(), c, o64) for c in (4, 8, 12, 16)]
+    assert sizes == sorted(sizes)
+    assert P.hotrg_workspace_bytes(_model(), 16, o32) < P.hotrg_workspace_bytes(_model(), 16, o64)
+    # chi = 16, FP64: two copies of the chi^6 tensor at least
+    assert sizes[-1] > 2 * 16 ** 6 * 8
+
+
+def test_init_argument_errors_without_device():
+    o = P.hotrg_opts(P.HOTRG_FP64, 8, 0, 0)
+    h = ctypes.c_void_p()
+    L = P.lib()
+    # NULL out pointer
+    assert L.hotrg_init(ctypes.byref(_model()), 0.2, 8, ctypes.byref(o), None, 0, None, None) == P.HOTRG_E_ARG
+    # invalid beta
+    rc = L.hotrg_init(ctypes.byref(_model()), float("nan"), 8, ctypes.byref(o), ctypes.c_void_p(256), 1 << 40,
+                      None, ctypes.byref(h))
+    assert rc == P.HOTRG_E_ARG and not h.value
+    # antiferromagnet: W not PSD
+    rc = L.hotrg_init(ctypes.byref(_model(J=-1.0)), 0.2, 8, ctypes.byref(o), ctypes.c_void_p(256), 1 << 40,
+                      None, ctypes.byref(h))
+    assert rc == P.HOTRG_E_NOT_PSD
+    # workspace too small
+    rc = L.hotrg_init(ctypes.byref(_model()), 0.2, 8, ctypes.byref(o), ctypes.c_void_p(256), 16, None,
+                      ctypes.byref(h))
+    assert rc == P.HOTRG_E_OOM
+    assert "workspace" in P.hotrg_last_error(None)
+    # NULL handle
+    assert L.hotrg_step(None, 0) == P.HOTRG_E_ARG
+    assert L.hotrg_log_z(None, None, None) == P.HOTRG_E_ARG
+    L.hotrg_destroy(None)
+
+
+def test_debug_workspace_bytes():
+    assert P.hotrg_debug_workspace_bytes(3, [4, 4, 4], [8, 8], P.HOTRG_FP64) > 0
+    assert P.hotrg_debug_workspace_bytes(3, [4, 4, 4], [17, 8], P.HOTRG_FP64) == 0   # k > chi^2
+    assert P.hotrg_debug_workspace_bytes(2, [8, 8], [16], P.HOTRG_SPLIT_FP16) > 0
+    assert P.hotrg_debug_eigh_workspace_bytes(256, 2) >= 2 * 256 * 256 * 8
+    assert P.hotrg_debug_eigh_workspace_bytes(2000, 1) == 0

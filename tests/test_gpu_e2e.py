@@ -1,0 +1,150 @@
+"""End-to-end parity of whole HOTRG runs on the GPU (through the C ABI) against the
+FP64 oracle: exact tori while nothing is truncated, then the oracle fixtures of the
+physics configurations (gauge-invariant quantities only: lnZ/V after every step,
+normalised Gram spectra, judgement values)."""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import exact as E
+from oracle import hotrg as H
+
+pytestmark = pytest.mark.gpu
+
+gu = pytest.importorskip("tests.gpu_util")
+P = gu.P
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    gu.require_gpu()
+
+
+def run_gpu(kind, d, beta, chi, steps, precision="fp64", q=None, axes=None, chunk=0):
+    r = P.HOTRG(kind, d, beta, chi, q=q, precision=precision, max_steps=max(steps, 1), chunk=chunk)
+    out = []
+    for p in range(steps):
+        r.step(None if axes is None else axes[p])
+        out.append(r.log_z())
+    return r, out
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------------------
+# Exact tori (untruncated steps) -- brute force, independent of the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,d,q,beta,chi,steps", [
+    ("ising", 2, 2, 0.44, 16, 4),
+    ("ising", 3, 2, 0.2216544, 16, 3),
+    ("potts", 3, 3, 0.55, 9, 1),
+    ("potts", 2, 3, 0.9, 9, 1),
+])
+def test_untruncated_steps_equal_brute_force(kind, d, q, beta, chi, steps):
+    r, lnz = run_gpu(kind, d, beta, chi, steps, q=q)
+    for p in range(1, steps + 1):
+        L = H.lattice_shape(d, p)
+        z, _ = E.torus_log_z(kind, beta, L, q=q)
+        assert lnz[p - 1] == pytest.approx(z / np.prod(L), abs=1e-13), (p, L)
+
+
+def test_initial_lnz_closed_form():
+    for d in (2, 3):
+        r = P.HOTRG("ising", d, 0.3, 8)
+        assert r.log_z() == pytest.approx(math.log(2) + d * 0.3, abs=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Physics configurations against the oracle fixtures
+# ---------------------------------------------------------------------------
+
+def _compare_run(run_fix, lnz_gpu, rtol):
+    errs = []
+    for rec, g in zip(run_fix["steps"], lnz_gpu):
+        errs.append(abs(g - rec["lnz_per_site"]) / abs(rec["lnz_per_site"]))
+    return max(errs), errs[-1]
+
+
+def test_config1_fp64_2d_ising_chi8():
+    fx = load("config1.json")
+    for run in fx["runs"]:
+        _, lnz = run_gpu("ising", 2, run["beta"], fx["chi"], fx["steps"])
+        emax, elast = _compare_run(run, lnz, 1e-10)
+        print(f"config1 beta={run['beta']:.6f} max|df|/|f|={emax:.2e} final={elast:.2e}")
+        assert emax < 1e-10
+
+
+@pytest.mark.parametrize("precision,bound", [("fp64", 1e-10), ("fp32", 1e-6)])
+def test_config2_3d_ising_chi8(precision, bound):
+    fx = load("config2.json")
+    for run in fx["runs"]:
+        r, lnz = run_gpu("ising", 3, run["beta"], fx["chi"], fx["steps"], precision=precision)
+        emax, elast = _compare_run(run, lnz, bound)
+        print(f"config2 {precision} beta={run['beta']:.6f} max rel err={emax:.2e} final={elast:.2e}")
+        assert emax < bound
+
+
+def test_config2_spectra_and_judgement_values():
+    fx = load("config2.json")
+    run = fx["runs"][1]
+    r, _ = run_gpu("ising", 3, run["beta"], fx["chi"], 12)
+    for p in range(1, 13):
+        rec = run["steps"][p - 1]
+        info = r.info(p)
+        for j in (1, 2):
+            dref = rec["dirs"][str(j)]
+            assert info.chi_new[j - 1] == dref["chi_new"]
+            if not info.truncated[j - 1]:
+                continue
+            for side, key in ((0, "spec"), (1, "spec_p")):
+                spec = r.spectrum(p, j, side, cap=dref["chi_new"])
+                ref = dref[key][: len(spec)]
+                np.testing.assert_allclose(spec, ref, rtol=0, atol=1e-9)
+            # judgement values relative to the leading eigenvalue are gauge invariant
+            assert info.eps[j - 1] == pytest.approx(dref["eps"], rel=1e-5, abs=1e-13)
+
+
+def test_fp64_run_is_bitwise_deterministic():
+    _, a = run_gpu("ising", 3, 1 / 4.5115, 8, 10)
+    _, b = run_gpu("ising", 3, 1 / 4.5115, 8, 10)
+    assert a == b
+
+
+def test_axis_relabelling_invariance():
+    # isotropic model: the order x, z, y is the mirror image of x, y, z
+    beta = 1 / 4.5115
+    _, a = run_gpu("ising", 3, beta, 8, 9, axes=[0, 1, 2] * 3)
+    _, b = run_gpu("ising", 3, beta, 8, 9, axes=[0, 2, 1] * 3)
+    np.testing.assert_allclose(b, a, rtol=1e-12)
+
+
+def test_chunking_does_not_change_results():
+    beta = 1 / 4.5115
+    _, a = run_gpu("ising", 3, beta, 8, 8, chunk=0)
+    _, b = run_gpu("ising", 3, beta, 8, 8, chunk=5)
+    np.testing.assert_allclose(b, a, rtol=1e-13)
+
+
+def test_state_errors():
+    r = P.HOTRG("ising", 2, 0.4, 4, max_steps=2)
+    r.step()
+    r.step()
+    with pytest.raises(P.HotrgError) as e:
+        r.step()
+    assert e.value.code == P.HOTRG_E_STATE
+    with pytest.raises(P.HotrgError) as e:
+        P.hotrg_step(r.handle, 5)
+    assert e.value.code == P.HOTRG_E_ARG
+    with pytest.raises(P.HotrgError) as e:
+        P.hotrg_grad(r.handle)
+    assert e.value.code == P.HOTRG_E_STATE

@@ -219,6 +219,25 @@ def test_choice_rule_and_judgement_values():
     assert t4.chi_new == 4 and t4.eps == 0.0 and t4.eps_p == 0.0
 
 
+def test_multiplet_rule():
+    # a cut that splits a degenerate pair drops the pair; a clean cut keeps chi_new;
+    # eigenvalues at rounding level (here exact zeros) are not examined
+    assert H.multiplet_safe_cut(np.array([5.0, 2.0, 1.0, 1.0, 0.1]), 3) == 2
+    assert H.multiplet_safe_cut(np.array([5.0, 1.0, 1.0, 1.0, 0.1]), 3) == 1
+    assert H.multiplet_safe_cut(np.array([5.0, 2.0, 1.0, 0.5]), 3) == 3
+    assert H.multiplet_safe_cut(np.array([1.0, 0.0, 0.0, 0.0]), 2) == 2
+    assert H.multiplet_safe_cut(np.array([1.0, 0.5]), 2) == 2
+    Q = SI.random_isometry(5, 5, seed=9)
+    A = Q @ np.diag([5.0, 2.0, 1.0, 1.0, 0.1]) @ Q.T
+    t = H.choose_isometry(A, A, chi=3)
+    assert t.kept == 2 and t.U.shape == (5, 3)
+    assert np.all(t.U[:, 2] == 0.0)
+    # the kept columns span the top-2 eigenvectors exactly
+    np.testing.assert_allclose(t.U[:, :2] @ t.U[:, :2].T, Q[:, :2] @ Q[:, :2].T, atol=1e-12)
+    # the literal rule keeps chi_new columns
+    assert H.choose_isometry(A, A, chi=3, multiplets=False).kept == 3
+
+
 # --------------------------------------------------------------------------
 # Truncated regime
 # --------------------------------------------------------------------------
