@@ -193,11 +193,11 @@ int hotrg_debug_gram(int d, const int* dims, int dir, int side, const double* T_
 /* Workspace bytes for hotrg_debug_eigh. */
 size_t hotrg_debug_eigh_workspace_bytes(int n, int batch);
 
-/* Symmetric eigendecomposition (FP64 parallel Jacobi, the solver used for A and A'
- * in Section 4.2.5) of `batch` row-major n x n matrices (1 <= n <= 1024):
- * eigenvalues descending into w_dev[batch][n], eigenvectors as columns of
- * V_dev[batch][n][n] (row-major).  A_dev is overwritten.
- * Errors: HOTRG_E_ARG, HOTRG_E_OOM, HOTRG_E_NUMERIC (no convergence), HOTRG_E_DEVICE. */
+/* Symmetric eigendecomposition (FP64; Householder tridiagonalisation, bisection,
+ * inverse iteration -- the solver used for A and A' in Section 4.2.5) of `batch`
+ * (1..4) row-major n x n matrices (1 <= n <= 1024): eigenvalues descending into
+ * w_dev[batch][n], eigenvectors as columns of V_dev[batch][n][n] (row-major).
+ * A_dev is overwritten.  Errors: HOTRG_E_ARG, HOTRG_E_OOM, HOTRG_E_DEVICE. */
 int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_dev,
                      void* workspace_dev, size_t workspace_bytes, void* hip_stream);
 

@@ -27,9 +27,11 @@ using namespace hk;
 
 namespace {
 
-constexpr long TILE_M = 128, TILE_N = 128, TILE_K = 64;
+constexpr long TILE_M = 256, TILE_N = 256, TILE_K = 64;   // operand padding (multiple of every tile)
+constexpr long GRAM_TILE = 128;                             // tile of the FP64 Gram GEMM
 constexpr int MAX_CHI_3D = 16, MAX_CHI_2D = 32;
 constexpr size_t ALIGN = 256;
+constexpr int EIG_SLOTS = 4;    // (direction, side) matrices decomposed per step
 
 inline long roundup(long x, long m) { return (x + m - 1) / m * m; }
 
@@ -72,9 +74,9 @@ struct GramGeo {
 GramGeo gram_geo(long H, long R) {
   GramGeo g;
   g.R = R;
-  g.Rp = roundup(R, TILE_M);
+  g.Rp = roundup(R, GRAM_TILE);
   g.C = H * H / R;
-  const long tiles = (g.Rp / TILE_M) * (g.Rp / TILE_N);
+  const long tiles = (g.Rp / GRAM_TILE) * (g.Rp / GRAM_TILE);
   long Z = std::max(1L, (512 + tiles - 1) / tiles);
   Z = std::min(Z, std::max(1L, roundup(g.C, 16) / 16));
   g.kchunk = roundup((g.C + Z - 1) / Z, 16);
@@ -188,14 +190,27 @@ Plan make_plan(int d, int q, int chi, int form, int user_chunk, int max_steps) {
   P.off_part = take(nd.part);
   P.off_Gh = take(nd.G);
   P.off_Gc = take(nd.G);
-  P.off_A = take(2 * nd.Amat);
-  P.off_Vw = take(2 * nd.Amat);
-  P.off_Vo = take(2 * nd.Amat);
-  P.off_w = take(2 * nd.w);
+  P.off_A = take(EIG_SLOTS * nd.Amat);
+  P.off_Vw = take(EIG_SLOTS * 2 * nd.Amat);
+  P.off_Vo = take(EIG_SLOTS * nd.Amat);
+  P.off_w = take(EIG_SLOTS * nd.w);
   P.off_Ut = take(MAXD * nd.Ut);
   P.off_Ut32 = take(MAXD * nd.Ut / 2 + 64);
   P.total = o;
   return P;
+}
+
+// Noise floor of the Gram spectrum relative to its largest eigenvalue in each form:
+// 16 unit roundoffs of the form (0 for FP64: the exact multiplet rule of the oracle).
+double multiplet_tau(int form) {
+  switch (form) {
+    case HOTRG_FP64: return 0.0;
+    case HOTRG_FP32: return 16.0 * 0x1p-24;
+    case HOTRG_SPLIT_FP16: return 16.0 * 0x1p-21;
+    case HOTRG_SPLIT_BF16: return 16.0 * 0x1p-16;
+    case HOTRG_FP16: return 16.0 * 0x1p-11;
+    default: return 16.0 * 0x1p-8;
+  }
 }
 
 unsigned grid_for(long n, int block = 256) {
@@ -219,6 +234,7 @@ struct hotrg_handle {
   int axes[MAXD]{};   // lattice axis of each slot (slot 0 = Current)
   int p = 0;
   bool failed = false;
+  bool no_fuse = false;   // force the separate non-prime kernel (tests of the fused epilogue)
   std::string err;
   // live timing: pairs of events recorded on the stream, resolved at hotrg_timings
   bool profiling = false;
@@ -247,7 +263,10 @@ hipEvent_t tmark(hotrg_handle* h) {
   } else if (hipEventCreate(&e) != hipSuccess) {
     return nullptr;
   }
-  hipEventRecord(e, h->s);
+  if (hipEventRecord(e, h->s) != hipSuccess) {
+    h->free_events.push_back(e);
+    return nullptr;
+  }
   return e;
 }
 void tclose(hotrg_handle* h, int cat, hipEvent_t start) {
@@ -288,12 +307,27 @@ template <> struct GemmCfg<F_SPLIT_FP16> { static constexpr int BK = 64; };
 template <int F>
 void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, long bplane, void* C, long ldc,
                  long czs, long Mp, long Np, long Kp, int Z, long kchunk, const double* scale_ptr, double smult,
-                 hipStream_t s) {
+                 hipStream_t s, const FuseArgs* fuse = nullptr) {
   typedef typename OpOf<F>::type Op;
   constexpr int PL = FormInfo<F>::planes;
-  dim3 grid((unsigned)(Mp / TILE_M), (unsigned)(Np / TILE_N), (unsigned)Z);
-  (void)Kp;
-  hipLaunchKernelGGL((k_gemm_tn<Op, PL, TILE_M, TILE_N, GemmCfg<F>::BK>), grid, dim3(256), 0, s,
+  if constexpr (F != F_FP64 && F != F_FP32) {
+    if (Z == 1 && smult == 1.0 && Mp % GB_BM == 0 && Np % GB_BN == 0 && Kp % GB_BK == 0) {
+      const int mt = (int)(Mp / GB_BM), nt = (int)(Np / GB_BN);
+      constexpr int WAVES = PL == 2 ? 4 : 8;
+      if (fuse)
+        hipLaunchKernelGGL((k_gemm_big<Op, PL, WAVES, true>), dim3((unsigned)(mt * nt)), dim3(64 * WAVES), 0, s,
+                           (const typename Op::T*)A, lda, aplane, (const typename Op::T*)B, ldb, bplane,
+                           (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, *fuse);
+      else
+        hipLaunchKernelGGL((k_gemm_big<Op, PL, WAVES, false>), dim3((unsigned)(mt * nt)), dim3(64 * WAVES), 0, s,
+                           (const typename Op::T*)A, lda, aplane, (const typename Op::T*)B, ldb, bplane,
+                           (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, FuseArgs{});
+      return;
+    }
+  }
+  constexpr long T = 128;
+  dim3 grid((unsigned)(Mp / T), (unsigned)(Np / T), (unsigned)Z);
+  hipLaunchKernelGGL((k_gemm_tn<Op, PL, T, T, GemmCfg<F>::BK>), grid, dim3(256), 0, s,
                      (const typename Op::T*)A, lda, aplane, (const typename Op::T*)B, ldb, bplane,
                      (typename Op::Acc*)C, ldc, czs, (int)kchunk, scale_ptr, smult);
 }
@@ -383,9 +417,13 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     hipEvent_t t0 = tmark(h);
     hipLaunchKernelGGL((k_zero_pad<ST>), dim3(grid_for((Np - ncols) * Kp + ncols * (Kp - H) + 1)), dim3(256), 0,
                        h->s, Bop, ncols, Np, H, Kp, bplane, FormInfo<F>::planes);
-    hipLaunchKernelGGL((k_pstage<MT, UT, F>), dim3((unsigned)(H * dm.chic)), dim3(256), 0, h->s, T,
-                       (const UT*)U1, (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane,
-                       (const DevState*)st);
+    if (ld.d == 3)
+      hipLaunchKernelGGL((k_pstage3<MT, UT, F>), dim3((unsigned)H), dim3(256), 0, h->s, T, (const UT*)U1,
+                         (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane, (const DevState*)st);
+    else
+      hipLaunchKernelGGL((k_pstage<MT, UT, F>), dim3((unsigned)(H * dm.chic)), dim3(256), 0, h->s, T,
+                         (const UT*)U1, (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane,
+                         (const DevState*)st);
     tclose(h, HOTRG_T_PRIME, t0);
     const double* sp = nullptr;
     if (FormInfo<F>::fp16) {
@@ -393,16 +431,30 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
       hipLaunchKernelGGL(k_inv_scale_fp16, dim3(1), dim3(1), 0, h->s, st, dm.b);
       sp = &st->inv_scale;
     }
+    // the non-prime chain runs in the GEMM epilogue when one 256 x 256 tile is one (c, g) block
+    const bool fused = FormInfo<F>::fused_ok && ld.d == 3 && dm.chi1 == 16 && dm.chi2 == 16 && dm.k1 == 16 &&
+                       dm.k2 == 16 && h->opts.chunk >= 0 && !h->no_fuse;
+    FuseArgs fa{};
+    if (fused) {
+      fa.U1 = (const float*)U1;
+      fa.U2 = (const float*)U2;
+      fa.Tn = (float*)Tn;
+      fa.Hn = (long)dm.k1 * dm.k2 * dm.chic;
+      fa.chic = dm.chic;
+      fa.g0 = (int)(pr0 * dm.chic);
+    }
     hipEvent_t t1 = tmark(h);
-    launch_gemm<F>(Aop, Kp, aplane, Bop, Kp, bplane, Cc, Np, 0, Mp, Np, Kp, 1, Kp, sp, 1.0, h->s);
+    launch_gemm<F>(Aop, Kp, aplane, Bop, Kp, bplane, Cc, Np, 0, Mp, Np, Kp, 1, Kp, sp, 1.0, h->s,
+                   fused ? &fa : nullptr);
     tclose(h, HOTRG_T_BOTTLENECK, t1);
     if (h->profiling) h->acc.flops_bottleneck += 2.0 * (double)H * (double)ncols * (double)H;
+    if (fused) continue;
     hipEvent_t t2 = tmark(h);
     const long ncell = (long)dm.chic * (pr1 - pr0) * dm.chic;   // (c, g) blocks
     const int g0 = (int)(pr0 * dm.chic), gcount = (int)((pr1 - pr0) * dm.chic);
     if (ld.d == 3)
-      hipLaunchKernelGGL((k_nstage3<AT, MT, UT>), dim3((unsigned)ncell), dim3(256), 0, h->s, (const AT*)Cc, Np,
-                         (const UT*)U1, (const UT*)U2, dm, g0, gcount, Tn);
+      hipLaunchKernelGGL((k_nstage3b<AT, MT, UT>), dim3((unsigned)(dm.chic * ((gcount + 7) / 8))), dim3(256), 0,
+                         h->s, (const AT*)Cc, Np, (const UT*)U1, (const UT*)U2, dm, g0, gcount, Tn);
     else
       hipLaunchKernelGGL((k_nstage2<AT, MT, UT>), dim3((unsigned)ncell), dim3(64), 0, h->s, (const AT*)Cc, Np,
                          (const UT*)U1, dm, g0, gcount, Tn);
@@ -438,29 +490,44 @@ int enqueue_contract(hotrg_handle* h, const void* T, void* Tn, const LocalDims& 
   return fail(h, HOTRG_E_ARG, "bad precision form");
 }
 
-// Decompose A^(j), A'^(j) and choose/truncate U^(j) into the isometry slot of direction j.
-int enqueue_isometry(hotrg_handle* h, const void* T, const LocalDims& ld, int j, int kj, StepRec* rec) {
-  const int n = ld.chi[j] * ld.chi[j];
-  double* Ut = h->at<double>(h->plan.off_Ut) + (size_t)(j - 1) * (h->plan.need.Ut / 8);
-  float* Ut32 = h->at<float>(h->plan.off_Ut32) + (size_t)(j - 1) * (h->plan.need.Ut / 8);
+// Gram matrices of every truncated direction, one eigensolver launch over all of them,
+// then the choice / truncation of U^(j) per direction (untruncated: identity).
+int enqueue_decomposition(hotrg_handle* h, const void* T, const LocalDims& ld, const int* k, StepRec* rec) {
+  const int d = ld.d;
+  const size_t ut_stride = h->plan.need.Ut / 8;
+  const size_t am = h->plan.need.Amat / 8, wn = h->plan.need.w / 8;
   double* Am = h->at<double>(h->plan.off_A);
   double* Vw = h->at<double>(h->plan.off_Vw);
   double* Vo = h->at<double>(h->plan.off_Vo);
   double* w = h->at<double>(h->plan.off_w);
-  if (n <= h->chi) {   // untruncated: all columns kept, identity basis
-    hipLaunchKernelGGL(k_choose, dim3(1), dim3(256), 0, h->s, (const double*)w, (const double*)Vo, n, n, 1, Ut,
-                       Ut32, rec, j - 1);
-    HIPCHK(h, hipGetLastError());
-    return HOTRG_OK;
+  EigBatch eb{};
+  for (int j = 1; j < d; ++j) {
+    const int n = ld.chi[j] * ld.chi[j];
+    if (n <= h->chi) continue;
+    for (int side = 0; side < 2; ++side) {
+      const int slot = (j - 1) * 2 + side;
+      int rc = enqueue_gram(h, T, h->form == HOTRG_FP64, ld, j, side, Am + slot * am);
+      if (rc) return rc;
+      const int b = eb.count++;
+      eb.n[b] = n;
+      eb.kvec[b] = k[j - 1];
+      eb.A[b] = Am + slot * am;
+      eb.w[b] = w + slot * wn;
+      eb.V[b] = Vo + slot * am;
+      eb.scratch[b] = Vw + slot * 2 * am;
+    }
   }
-  const size_t nn = (size_t)n * n;
-  for (int side = 0; side < 2; ++side) {
-    int rc = enqueue_gram(h, T, h->form == HOTRG_FP64, ld, j, side, Am + side * nn);
-    if (rc) return rc;
+  if (eb.count > 0)
+    hipLaunchKernelGGL(k_eigh_tri, dim3(eb.count), dim3(EIG_THREADS), 0, h->s, eb);
+  for (int j = 1; j < d; ++j) {
+    const int n = ld.chi[j] * ld.chi[j];
+    double* Ut = h->at<double>(h->plan.off_Ut) + (size_t)(j - 1) * ut_stride;
+    float* Ut32 = h->at<float>(h->plan.off_Ut32) + (size_t)(j - 1) * ut_stride;
+    const int s0 = (j - 1) * 2, s1 = s0 + 1;
+    hipLaunchKernelGGL(k_choose, dim3(1), dim3(256), 0, h->s, (const double*)(w + s0 * wn),
+                       (const double*)(w + s1 * wn), (const double*)(Vo + s0 * am), (const double*)(Vo + s1 * am),
+                       n, k[j - 1], n <= h->chi ? 1 : 0, multiplet_tau(h->form), Ut, Ut32, rec, j - 1);
   }
-  hipLaunchKernelGGL(k_jacobi, dim3(2), dim3(JAC_THREADS), 0, h->s, Am, Vw, w, Vo, n, 60, h->st());
-  hipLaunchKernelGGL(k_choose, dim3(1), dim3(256), 0, h->s, (const double*)w, (const double*)Vo, n, kj, 0, Ut,
-                     Ut32, rec, j - 1);
   HIPCHK(h, hipGetLastError());
   return HOTRG_OK;
 }
@@ -611,10 +678,8 @@ int hotrg_step(hotrg_handle* h, int axis) {
   void* T = h->at<void>(h->plan.off_T);
   void* Tn = h->at<void>(h->plan.off_Tn);
   hipEvent_t t_dec = tmark(h);
-  for (int j = 1; j < d; ++j) {
-    rc = enqueue_isometry(h, T, ld, j, k[j - 1], rec);
-    if (rc) return rc;
-  }
+  rc = enqueue_decomposition(h, T, ld, k, rec);
+  if (rc) return rc;
   tclose(h, HOTRG_T_DECOMP, t_dec);
   rc = enqueue_contract(h, T, Tn, ld, k);
   if (rc) return rc;
@@ -791,10 +856,10 @@ static Plan debug_plan(int d, const int* dims, const int* kdims, int form) {
   P.off_part = take(nd.part);
   P.off_Gh = take(nd.G);
   P.off_Gc = take(nd.G);
-  P.off_A = take(2 * nd.Amat);
-  P.off_Vw = take(2 * nd.Amat);
-  P.off_Vo = take(2 * nd.Amat);
-  P.off_w = take(2 * nd.w);
+  P.off_A = take(EIG_SLOTS * nd.Amat);
+  P.off_Vw = take(EIG_SLOTS * 2 * nd.Amat);
+  P.off_Vo = take(EIG_SLOTS * nd.Amat);
+  P.off_w = take(EIG_SLOTS * nd.w);
   P.off_Ut = take(MAXD * nd.Ut);
   P.off_Ut32 = take(MAXD * nd.Ut / 2 + 64);
   P.total = o;
@@ -908,29 +973,31 @@ int hotrg_debug_gram(int d, const int* dims, int dir, int side, const double* T_
 }
 
 size_t hotrg_debug_eigh_workspace_bytes(int n, int batch) {
-  if (n < 1 || n > 2 * JAC_MAXPAIR || batch < 1) return 0;
-  return roundup(sizeof(DevState), ALIGN) + (size_t)batch * n * n * 8;
+  if (n < 1 || n > EIG_MAXN || batch < 1 || batch > 4) return 0;
+  return (size_t)batch * 2 * n * n * 8;
 }
 
 int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_dev, void* workspace,
                      size_t ws_bytes, void* stream) {
-  if (n < 1 || n > 2 * JAC_MAXPAIR || batch < 1 || !A_dev || !w_dev || !V_dev || !workspace)
+  if (n < 1 || n > EIG_MAXN || batch < 1 || batch > 4 || !A_dev || !w_dev || !V_dev || !workspace)
     return fail(nullptr, HOTRG_E_ARG, "invalid argument");
   if (ws_bytes < hotrg_debug_eigh_workspace_bytes(n, batch)) return fail(nullptr, HOTRG_E_OOM, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
-  DevState* dst = (DevState*)workspace;
-  double* work = (double*)((char*)workspace + roundup(sizeof(DevState), ALIGN));
-  hipError_t e = hipMemsetAsync(dst, 0, sizeof(DevState), s);
-  if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
-  hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(JAC_THREADS), 0, s, A_dev, work, w_dev, V_dev, n, 60, dst);
-  e = hipGetLastError();
+  EigBatch eb{};
+  eb.count = batch;
+  for (int b = 0; b < batch; ++b) {
+    eb.n[b] = n;
+    eb.kvec[b] = n;
+    eb.A[b] = A_dev + (size_t)b * n * n;
+    eb.w[b] = w_dev + (size_t)b * n;
+    eb.V[b] = V_dev + (size_t)b * n * n;
+    eb.scratch[b] = (double*)workspace + (size_t)b * 2 * n * n;
+  }
+  hipLaunchKernelGGL(k_eigh_tri, dim3(batch), dim3(EIG_THREADS), 0, s, eb);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
-  DevState hs;
-  e = hipMemcpy(&hs, dst, sizeof(DevState), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
-  if (hs.eig_fail) return fail(nullptr, HOTRG_E_NUMERIC, "Jacobi did not converge");
   return HOTRG_OK;
 }
 

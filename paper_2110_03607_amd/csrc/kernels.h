@@ -107,6 +107,7 @@ template <> struct Store<F_SPLIT_FP16> {
 template <int F> struct FormInfo {
   static constexpr bool fp16 = (F == F_FP16 || F == F_SPLIT_FP16);
   static constexpr int planes = (F == F_SPLIT_BF16 || F == F_SPLIT_FP16) ? 2 : 1;
+  static constexpr bool fused_ok = (F != F_FP64 && F != F_FP32);   // 16-bit forms: large-tile GEMM
 };
 
 // ---------------------------------------------------------------------------
@@ -252,6 +253,195 @@ __global__ __launch_bounds__(256) void k_gemm_tn(
       }
 }
 
+// ---------------------------------------------------------------------------
+// Large-tile GEMM for the 16-bit forms (single plane or hi/lo split):
+//   C[m][n] = scale * sum_k A[m][k] B[n][k],  tile 256 x 256, BK = 32, 512 threads.
+// 8 waves in a 2 (M) x 4 (N) grid, 128 x 64 per wave (8 x 4 blocks of 16 x 16).
+// Global -> registers -> LDS, double-buffered; the next K-slice is fetched while the
+// current one feeds the MFMAs.  LDS rows are 64 bytes (four 16-byte k-chunks); chunk c of
+// row r sits at slot c ^ ((r >> 2) & 3), so the 16 rows x 1 chunk read by a quarter-wave
+// for an MFMA fragment cover all 64 banks once.
+// Tiles are ordered so that the workgroups resident on one XCD at a time (consecutive
+// workgroups go to consecutive XCDs) form compact 4 x 8 groups of tiles sharing A and B
+// panels in that XCD's L2.
+// ---------------------------------------------------------------------------
+constexpr int GB_BM = 256, GB_BN = 256, GB_BK = 32;
+
+__device__ inline int swz(int r, int c) { return r * 64 + ((c ^ ((r >> 2) & 3)) << 4); }
+
+__device__ inline void tile_of(int b, int mt, int nt, int& tm, int& tn) {
+  if (mt % 4 == 0 && nt % 8 == 0 && (mt / 4) * (nt / 8) % 8 == 0) {
+    const int xcd = b & 7, j = b >> 3;
+    const int round = j >> 5, q = j & 31;
+    const int st = round * 8 + xcd;              // super-tile of 4 x 8 tiles
+    const int sm = st % (mt / 4), sn = st / (mt / 4);
+    tm = sm * 4 + (q & 3);
+    tn = sn * 8 + (q >> 2);
+  } else {
+    tm = b % mt;
+    tn = b / mt;
+  }
+}
+
+// WAVES = 8: 2 x 4 waves of 128 x 64 (2 waves per SIMD); WAVES = 4: 2 x 2 waves of
+// 128 x 128 (one wave per SIMD, accumulators in the AGPR half of the register file).
+// FUSE: the non-prime chain is done in the epilogue (3D, chi_1 = chi_2 = k_1 = k_2 = 16, so a
+// 256 x 256 tile is exactly one (c, g) block: rows (nh1, nh2), columns (nc1, nc2)).  Each
+// 16 x 16 accumulator block is one (nh1, nc1) pair; its (nh2, nc2) contraction with U2 is
+// done in registers (64 multiply-adds per lane, then a 17-shuffle reduce-scatter), the
+// (nh1, nc1) contraction with U1 through LDS.  The result goes to T^next[hbar][g] and C is
+// not written.
+struct FuseArgs {
+  const float* U1;     // [(nh1 + 16 nc1) * 16 + n1]
+  const float* U2;     // [(nh2 + 16 nc2) * 16 + n2]
+  float* Tn;           // renamed new tensor, row length Hn
+  long Hn;
+  int chic, g0;
+};
+
+template <class Op, int PLANES, int WAVES, bool FUSE>
+__global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
+    const typename Op::T* __restrict__ A, long lda, long a_plane,
+    const typename Op::T* __restrict__ B, long ldb, long b_plane,
+    float* __restrict__ C, long ldc, int Kp, int mtiles, int ntiles, const double* __restrict__ scale_ptr,
+    FuseArgs fa) {
+  typedef typename Op::Frag Frag;
+  typedef typename Op::AccV AccV;
+  constexpr int THREADS = 64 * WAVES, WNC = WAVES / 2, NB = GB_BN / 16 / WNC, WTN = GB_BN / WNC;
+  constexpr int CH = 1024 / THREADS;                        // 16-byte chunks per thread, plane, operand
+  constexpr int STAGE = PLANES * (GB_BM + GB_BN) * 64;     // bytes per stage
+  __shared__ __attribute__((aligned(16))) char lds[2 * STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WNC, wn = wave % WNC;
+  int tm, tn;
+  tile_of(blockIdx.x, mtiles, ntiles, tm, tn);
+  const long m0 = (long)tm * GB_BM, n0 = (long)tn * GB_BN;
+  const char* Ab = (const char*)A;
+  const char* Bb = (const char*)B;
+
+  // staging registers: slot k = p * CH + i holds chunk i of plane p (named scalars, so they
+  // can only live in registers)
+  uint4 sa0, sa1, sa2, sa3, sa4, sa5, sa6, sa7, sb0, sb1, sb2, sb3, sb4, sb5, sb6, sb7;
+#define GB_LD1(k, k0)                                                                                  \
+  if constexpr ((k) < PLANES * CH) {                                                                   \
+    const int p_ = (k) / CH, q_ = tid + ((k) % CH) * THREADS, r_ = q_ >> 2, c_ = q_ & 3;               \
+    sa##k = *(const uint4*)(Ab + 2 * (p_ * a_plane + (m0 + r_) * lda + (k0) + c_ * 8));               \
+    sb##k = *(const uint4*)(Bb + 2 * (p_ * b_plane + (n0 + r_) * ldb + (k0) + c_ * 8));               \
+  }
+#define GB_ST1(k, stage)                                                                               \
+  if constexpr ((k) < PLANES * CH) {                                                                   \
+    const int p_ = (k) / CH, q_ = tid + ((k) % CH) * THREADS, r_ = q_ >> 2, c_ = q_ & 3;               \
+    char* base_ = lds + (stage) * STAGE + p_ * (GB_BM + GB_BN) * 64;                                   \
+    *(uint4*)(base_ + swz(r_, c_)) = sa##k;                                                            \
+    *(uint4*)(base_ + GB_BM * 64 + swz(r_, c_)) = sb##k;                                               \
+  }
+#define GB_GLOAD(k0) { GB_LD1(0, k0) GB_LD1(1, k0) GB_LD1(2, k0) GB_LD1(3, k0) \
+                       GB_LD1(4, k0) GB_LD1(5, k0) GB_LD1(6, k0) GB_LD1(7, k0) }
+#define GB_LSTORE(st) { GB_ST1(0, st) GB_ST1(1, st) GB_ST1(2, st) GB_ST1(3, st) \
+                        GB_ST1(4, st) GB_ST1(5, st) GB_ST1(6, st) GB_ST1(7, st) }
+  static_assert(PLANES * CH <= 8, "staging slots");
+
+  AccV acc[8][NB];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = AccV{0, 0, 0, 0};
+
+  const int nk = Kp / GB_BK;
+  GB_GLOAD(0);
+  GB_LSTORE(0);
+  __syncthreads();
+  const int fr = lane & 15, fc = lane >> 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) { GB_GLOAD((long)(kt + 1) * GB_BK); }
+    const char* base = lds + (kt & 1) * STAGE;
+    Frag b[PLANES][NB];
+#pragma unroll
+    for (int p = 0; p < PLANES; ++p)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        b[p][j] = *(const Frag*)(base + p * (GB_BM + GB_BN) * 64 + GB_BM * 64 + swz(wn * WTN + j * 16 + fr, fc));
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      Frag a[PLANES];
+#pragma unroll
+      for (int p = 0; p < PLANES; ++p)
+        a[p] = *(const Frag*)(base + p * (GB_BM + GB_BN) * 64 + swz(wm * 128 + i * 16 + fr, fc));
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if constexpr (PLANES == 2) {
+          acc[i][j] = Op::mma(a[0], b[PLANES - 1][j], acc[i][j]);
+          acc[i][j] = Op::mma(a[PLANES - 1], b[0][j], acc[i][j]);
+        }
+        acc[i][j] = Op::mma(a[0], b[0][j], acc[i][j]);
+      }
+    }
+    if (kt + 1 < nk) { GB_LSTORE((kt + 1) & 1); }
+    __syncthreads();
+  }
+#undef GB_GLOAD
+#undef GB_LSTORE
+#undef GB_LD1
+#undef GB_ST1
+  const float sc = (float)(scale_ptr ? *scale_ptr : 1.0);
+  if constexpr (FUSE) {
+    float* qs = (float*)lds;                 // Q[(nh1 * 16 + nc1) * 16 + n2]
+    float* u1s = (float*)(lds + 16384);      // U1
+    for (int i = tid; i < 4096; i += THREADS) u1s[i] = fa.U1[i];
+    // this lane's accumulator entries are rows nh2 = 4 (lane / 16) + r, column nc2 = lane % 16
+    float w2[4][16];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int n2 = 0; n2 < 16; ++n2) w2[r][n2] = fa.U2[((4 * (lane >> 4) + r) + 16 * fr) * 16 + n2];
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        float P[16];
+#pragma unroll
+        for (int n2 = 0; n2 < 16; ++n2)
+          P[n2] = w2[0][n2] * acc[i][j][0] + w2[1][n2] * acc[i][j][1] + w2[2][n2] * acc[i][j][2] +
+                  w2[3][n2] * acc[i][j][3];
+        float R[8], S[4], U[2], v;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) R[t] = (b5 ? P[t + 8] : P[t]) + __shfl_xor(b5 ? P[t] : P[t + 8], 32);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) S[t] = (b4 ? R[t + 4] : R[t]) + __shfl_xor(b4 ? R[t] : R[t + 4], 16);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) U[t] = (b3 ? S[t + 2] : S[t]) + __shfl_xor(b3 ? S[t] : S[t + 2], 8);
+        v = (b2 ? U[1] : U[0]) + __shfl_xor(b2 ? U[0] : U[1], 4);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 1);
+        const int nh1 = wm * 8 + i, nc1 = wn * (WTN / 16) + j;
+        if ((lane & 3) == 0) qs[(nh1 * 16 + nc1) * 16 + (lane >> 2)] = v;   // n2 = lane / 4
+      }
+    __syncthreads();
+    const int c = tm, g = fa.g0 + tn;
+    for (int o = tid; o < 256; o += THREADS) {
+      const int n1 = o >> 4, n2 = o & 15;
+      float acc2 = 0.f;
+      for (int nh1 = 0; nh1 < 16; ++nh1)
+#pragma unroll 4
+        for (int nc1 = 0; nc1 < 16; ++nc1)
+          acc2 += u1s[(nh1 + 16 * nc1) * 16 + n1] * qs[(nh1 * 16 + nc1) * 16 + n2];
+      fa.Tn[(long)((n1 * 16 + n2) * fa.chic + c) * fa.Hn + g] = acc2 * sc;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const long row = m0 + wm * 128 + i * 16 + Op::out_row(lane, r);
+          const long col = n0 + wn * WTN + j * 16 + fr;
+          C[row * ldc + col] = acc[i][j][r] * sc;
+        }
+  }
+}
+
 // Fixed-order reduction of split-K slices: out[r][c] = sum_z part[z][r][c] for r < R, c < R.
 __global__ void k_reduce_z(const double* __restrict__ part, long zstride, long ldp, int Z, int R,
                            double* __restrict__ out) {
@@ -325,155 +515,266 @@ __global__ void k_gram_combine(const double* __restrict__ Gh, const double* __re
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric eigendecomposition: parallel cyclic Jacobi (round-robin ordering), one
-// workgroup per matrix, FP64.  Rotations skip |a_pq| <= 1e-16 sqrt(|a_pp a_qq|) and
-// entries below 1e-18 max|a_ii|; converged when a sweep performs no rotation.
-// Output: eigenvalues descending in w, eigenvectors as the matching columns of Vout.
+// Symmetric eigendecomposition, FP64, one 1024-thread workgroup per matrix:
+//   1. Householder reduction to tridiagonal form, H_k = I - 2 v v^T (|v| = 1);
+//   2. all eigenvalues by bisection on Sturm counts (needed for epsilon);
+//   3. the leading `kvec` eigenvectors of the tridiagonal matrix by inverse
+//      iteration (partial-pivoting LU, two iterations), re-orthogonalised against
+//      earlier vectors of the same cluster (|lambda_i - lambda_j| <= 1e-3 |T|);
+//   4. back-transformation with the stored reflectors.
+// Output: eigenvalues descending in w[n]; eigenvector i (< kvec) in column i of the
+// row-major V[n][n].  scratch: 2 n^2 doubles per matrix (reflectors, tridiagonal vectors).
 // ---------------------------------------------------------------------------
-constexpr int JAC_THREADS = 1024;
-constexpr int JAC_MAXPAIR = 512;     // n <= 1024
+constexpr int EIG_THREADS = 1024;
+constexpr int EIG_MAXN = 1024;
 
-__device__ inline void rr_pair(int r, int k, int m, int& p, int& q) {
-  // circle method: player 0 fixed, players 1..m-1 rotate
-  if (k == 0) { p = 0; q = 1 + r % (m - 1); }
-  else { p = 1 + (r + k) % (m - 1); q = 1 + (r - k + (m - 1)) % (m - 1); }
-  if (p > q) { int t = p; p = q; q = t; }
+__device__ inline double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  return s;
 }
 
-__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ Ab, double* __restrict__ Vb,
-                                                        double* __restrict__ wb, double* __restrict__ Vout,
-                                                        int n, int max_sweeps, DevState* st) {
-  __shared__ double cs[JAC_MAXPAIR], sn[JAC_MAXPAIR];
-  __shared__ int pp[JAC_MAXPAIR], qq[JAC_MAXPAIR];
-  __shared__ int rot_count;
-  __shared__ double dmax_s;
-  __shared__ double red[JAC_THREADS / 64];
-  double* A = Ab + (long)blockIdx.x * n * n;
-  double* V = Vb + (long)blockIdx.x * n * n;
-  double* w = wb + (long)blockIdx.x * n;
-  double* Vo = Vout + (long)blockIdx.x * n * n;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int m = n + (n & 1), half = m / 2;
+struct EigBatch {
+  int count;
+  int n[4], kvec[4];
+  double* A[4];
+  double* w[4];
+  double* V[4];
+  double* scratch[4];
+};
 
-  for (long i = tid; i < (long)n * n; i += nt) V[i] = (i / n == i % n) ? 1.0 : 0.0;
-  // absolute floor from the largest diagonal entry
-  double dm = 0.0;
-  for (int i = tid; i < n; i += nt) dm = fmax(dm, fabs(A[(long)i * n + i]));
-  for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o));
-  if ((tid & 63) == 0) red[tid >> 6] = dm;
-  __syncthreads();
+__global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
+  __shared__ double d[EIG_MAXN], e[EIG_MAXN], vv[EIG_MAXN], qv[EIG_MAXN];
+  __shared__ double red[EIG_THREADS / 64];
+  const int n = eb.n[blockIdx.x], kvec = eb.kvec[blockIdx.x];
+  double* A = eb.A[blockIdx.x];
+  double* w = eb.w[blockIdx.x];
+  double* V = eb.V[blockIdx.x];
+  double* R = eb.scratch[blockIdx.x];                   // reflector k at R[k * n .. k * n + n)
+  double* Z = R + (long)n * n;                          // tridiagonal eigenvector i at Z[i * n ..)
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+
+  // ---- 1. tridiagonalisation --------------------------------------------------
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    double x = 0.0, ss = 0.0;
+    for (int i = tid; i < m; i += nt) {
+      x = A[(long)(k + 1 + i) * n + k];
+      vv[i] = x;
+      ss += x * x;
+    }
+    const double sigma = block_sum(ss, red);          // includes a barrier: vv visible
+    const double x0 = vv[0];
+    const double tail = sigma - x0 * x0;
+    if (tid == 0) d[k] = A[(long)k * n + k];
+    if (!(tail > 0.0)) {                              // already tridiagonal in this column
+      if (tid == 0) e[k] = x0;
+      for (int i = tid; i < n; i += nt) R[(long)k * n + i] = 0.0;
+      __syncthreads();
+      continue;
+    }
+    const double alpha = (x0 >= 0.0 ? -1.0 : 1.0) * sqrt(sigma);
+    const double vnorm = sqrt(2.0 * (sigma - x0 * alpha));
+    __syncthreads();
+    for (int i = tid; i < m; i += nt) vv[i] = (i == 0 ? (x0 - alpha) : vv[i]) / vnorm;
+    if (tid == 0) e[k] = alpha;
+    __syncthreads();
+    for (int i = tid; i < n; i += nt) R[(long)k * n + i] = (i >= k + 1) ? vv[i - k - 1] : 0.0;
+    // w = A_sub v: wave per row, lanes over columns
+    for (int i = wv; i < m; i += nw) {
+      const double* row = A + (long)(k + 1 + i) * n + (k + 1);
+      double acc = 0.0;
+      for (int j = lane; j < m; j += 64) acc += row[j] * vv[j];
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (lane == 0) qv[i] = acc;
+    }
+    __syncthreads();
+    double cp = 0.0;
+    for (int i = tid; i < m; i += nt) cp += vv[i] * qv[i];
+    const double c = block_sum(cp, red);
+    for (int i = tid; i < m; i += nt) qv[i] -= c * vv[i];
+    __syncthreads();
+    // A_sub -= 2 (v q^T + q v^T)
+    for (long idx = tid; idx < (long)m * m; idx += nt) {
+      const int i = (int)(idx / m), j = (int)(idx % m);
+      A[(long)(k + 1 + i) * n + (k + 1 + j)] -= 2.0 * (vv[i] * qv[j] + qv[i] * vv[j]);
+    }
+    __syncthreads();
+  }
   if (tid == 0) {
-    double x = 0.0;
-    for (int i = 0; i < nt / 64; ++i) x = fmax(x, red[i]);
-    dmax_s = x;
+    if (n >= 2) {
+      d[n - 2] = A[(long)(n - 2) * n + (n - 2)];
+      e[n - 2] = A[(long)(n - 1) * n + (n - 2)];
+    }
+    d[n - 1] = A[(long)(n - 1) * n + (n - 1)];
+    e[n - 1] = 0.0;
+  }
+  for (int k = (n >= 2 ? n - 2 : 0); k < n; ++k)
+    for (int i = tid; i < n; i += nt) R[(long)k * n + i] = 0.0;   // no reflector for the last two
+  __syncthreads();
+
+  // ---- 2. eigenvalues by bisection (descending) -------------------------------
+  double tnorm = 0.0, lo = 0.0, hi = 0.0;
+  {
+    double gl = 1e300, gu = -1e300, emax = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+      gl = fmin(gl, d[i] - r);
+      gu = fmax(gu, d[i] + r);
+      if (i + 1 < n) emax = fmax(emax, fabs(e[i]));
+    }
+    tnorm = fmax(fabs(gl), fabs(gu));
+    const double pad = 2.0 * 2.2e-16 * tnorm + 1e-300;
+    lo = gl - pad;
+    hi = gu + pad;
+    (void)emax;
+  }
+  const double pivmin = fmax(1e-290, 2.2e-16 * 2.2e-16 * tnorm * tnorm);
+  for (int i = tid; i < n; i += nt) {
+    const int target = n - 1 - i;     // 0-based index in ascending order
+    double a = lo, b = hi;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (!(mid > a && mid < b)) break;
+      if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
+      int cnt = 0;
+      double q = d[0] - mid;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+      for (int r = 1; r < n; ++r) {
+        q = d[r] - mid - e[r - 1] * e[r - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+      }
+      if (cnt > target) b = mid; else a = mid;
+    }
+    w[i] = 0.5 * (a + b);
   }
   __syncthreads();
-  const double floor_abs = 1e-18 * dmax_s;
 
-  int sweep = 0;
-  bool done = (n <= 1);
-  for (; sweep < max_sweeps && !done; ++sweep) {
-    if (tid == 0) rot_count = 0;
-    __syncthreads();
-    for (int r = 0; r < m - 1; ++r) {
-      for (int k = tid; k < half; k += nt) {
-        int p, q;
-        rr_pair(r, k, m, p, q);
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double apq = A[(long)p * n + q];
-          const double app = A[(long)p * n + p], aqq = A[(long)q * n + q];
-          if (fabs(apq) > floor_abs && fabs(apq) > 1e-16 * sqrt(fabs(app * aqq))) {
-            const double th = (aqq - app) / (2.0 * apq);
-            const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-            atomicAdd(&rot_count, 1);
+  // ---- 3. inverse iteration for the leading kvec eigenvectors -----------------
+  // LU of (T - lambda I) with partial pivoting (rows r, r+1 may swap); U has three
+  // diagonals, stored as reciprocal pivot, first and second superdiagonal.
+  __shared__ double lu_ri[EIG_MAXN], lu_u1[EIG_MAXN], lu_u2[EIG_MAXN], lu_l[EIG_MAXN];
+  __shared__ int lu_p[EIG_MAXN];
+  const double ortol = 1e-3 * tnorm;
+  const double pivlu = fmax(1e-290, 2.2e-16 * tnorm);   // pivot floor: bounded growth, no overflow
+  double* zs = vv;                                       // LDS copy of the current vector
+  for (int iv = 0; iv < kvec; ++iv) {
+    const double lam = w[iv];
+    if (tid == 0) {
+      double a0 = d[0] - lam, b0 = n > 1 ? e[0] : 0.0, c0 = 0.0;   // current row: diag, super, super2
+      for (int r = 0; r < n; ++r) {
+        if (r + 1 < n) {
+          const double sub = e[r];
+          const double dn = d[r + 1] - lam, en = r + 2 < n ? e[r + 1] : 0.0;
+          if (fabs(sub) > fabs(a0)) {
+            const double l = a0 / sub;
+            lu_p[r] = 1; lu_l[r] = l;
+            lu_ri[r] = 1.0 / sub; lu_u1[r] = dn; lu_u2[r] = en;
+            a0 = b0 - l * dn;
+            b0 = c0 - l * en;
+          } else {
+            const double piv = fabs(a0) < pivlu ? (a0 < 0.0 ? -pivlu : pivlu) : a0;
+            const double l = sub / piv;
+            lu_p[r] = 0; lu_l[r] = l;
+            lu_ri[r] = 1.0 / piv; lu_u1[r] = b0; lu_u2[r] = c0;
+            a0 = dn - l * b0;
+            b0 = en - l * c0;
           }
+          c0 = 0.0;
+        } else {
+          const double piv = fabs(a0) < pivlu ? (a0 < 0.0 ? -pivlu : pivlu) : a0;
+          lu_p[r] = 0; lu_l[r] = 0.0;
+          lu_ri[r] = 1.0 / piv; lu_u1[r] = 0.0; lu_u2[r] = 0.0;
         }
-        cs[k] = c; sn[k] = s; pp[k] = p; qq[k] = q;
+      }
+    }
+    for (int i = tid; i < n; i += nt) {      // deterministic start vector
+      const unsigned hsh = (unsigned)(i + 1) * 2654435761u ^ (unsigned)(iv + 7) * 40503u;
+      zs[i] = 0.5 + (double)(hsh & 0xFFFFu) / 65536.0;
+    }
+    __syncthreads();
+    for (int it = 0; it < 2; ++it) {
+      if (tid == 0) {
+        double cur = zs[0];
+        for (int r = 0; r + 1 < n; ++r) {        // row operations, value of row r carried in cur
+          const double nxt = zs[r + 1], l = lu_l[r];
+          if (lu_p[r]) { zs[r] = nxt; cur = cur - l * nxt; }
+          else { zs[r] = cur; cur = nxt - l * cur; }
+        }
+        zs[n - 1] = cur;
+        double x1 = 0.0, x2 = 0.0;               // x_{r+1}, x_{r+2}
+        for (int r = n - 1; r >= 0; --r) {
+          const double x = (zs[r] - lu_u1[r] * x1 - lu_u2[r] * x2) * lu_ri[r];
+          zs[r] = x;
+          x2 = x1;
+          x1 = x;
+        }
       }
       __syncthreads();
-      // A <- J^T A J on the 2x2 blocks (P, Q), P <= Q; the (Q, P) block is its transpose.
-      const long nblk = (long)half * (half + 1) / 2;
-      for (long bidx = tid; bidx < nblk; bidx += nt) {
-        // map bidx -> (P, Q) with P <= Q
-        int P = (int)((sqrt(8.0 * (double)bidx + 1.0) - 1.0) / 2.0);
-        while ((long)(P + 1) * (P + 2) / 2 <= bidx) ++P;
-        while ((long)P * (P + 1) / 2 > bidx) --P;
-        const int Q2 = (int)(bidx - (long)P * (P + 1) / 2);   // Q2 <= P
-        const int Pa = Q2, Qa = P;                              // Pa <= Qa
-        const double cP = cs[Pa], sP = sn[Pa], cQ = cs[Qa], sQ = sn[Qa];
-        const int p1 = pp[Pa], q1 = qq[Pa], p2 = pp[Qa], q2 = qq[Qa];
-        const bool vq1 = q1 < n, vq2 = q2 < n;
-        const double a = A[(long)p1 * n + p2];
-        const double b = vq2 ? A[(long)p1 * n + q2] : 0.0;
-        const double c_ = vq1 ? A[(long)q1 * n + p2] : 0.0;
-        const double d = (vq1 && vq2) ? A[(long)q1 * n + q2] : 0.0;
-        // rows: row_p' = cP row_p - sP row_q, row_q' = sP row_p + cP row_q
-        const double rpp = cP * a - sP * c_, rpq = cP * b - sP * d;
-        const double rqp = sP * a + cP * c_, rqq = sP * b + cP * d;
-        // cols: col_p' = cQ col_p - sQ col_q, col_q' = sQ col_p + cQ col_q
-        double npp = cQ * rpp - sQ * rpq, npq = sQ * rpp + cQ * rpq;
-        double nqp = cQ * rqp - sQ * rqq, nqq = sQ * rqp + cQ * rqq;
-        if (Pa == Qa) {           // diagonal block: keep it exactly symmetric
-          const double off = 0.5 * (npq + nqp);
-          npq = off; nqp = off;
-        }
-        A[(long)p1 * n + p2] = npp;
-        if (vq2) A[(long)p1 * n + q2] = npq;
-        if (vq1) A[(long)q1 * n + p2] = nqp;
-        if (vq1 && vq2) A[(long)q1 * n + q2] = nqq;
-        if (Pa != Qa) {
-          A[(long)p2 * n + p1] = npp;
-          if (vq2) A[(long)q2 * n + p1] = npq;
-          if (vq1) A[(long)p2 * n + q1] = nqp;
-          if (vq1 && vq2) A[(long)q2 * n + q1] = nqq;
-        }
+      for (int jv = iv - 1; jv >= 0 && fabs(w[jv] - lam) <= ortol; --jv) {   // same cluster: MGS
+        const double* zj = Z + (long)jv * n;
+        double dp = 0.0;
+        for (int i = tid; i < n; i += nt) dp += zj[i] * zs[i];
+        const double dot = block_sum(dp, red);
+        for (int i = tid; i < n; i += nt) zs[i] -= dot * zj[i];
+        __syncthreads();
       }
-      // V <- V J
-      for (long idx = tid; idx < (long)n * half; idx += nt) {
-        const int i = (int)(idx / half), Q = (int)(idx % half);
-        const int p = pp[Q], q = qq[Q];
-        if (q >= n) continue;
-        const double c = cs[Q], s = sn[Q];
-        const double vp = V[(long)i * n + p], vq = V[(long)i * n + q];
-        V[(long)i * n + p] = c * vp - s * vq;
-        V[(long)i * n + q] = s * vp + c * vq;
-      }
+      double np = 0.0;
+      for (int i = tid; i < n; i += nt) np += zs[i] * zs[i];
+      const double inv = 1.0 / sqrt(block_sum(np, red));
+      for (int i = tid; i < n; i += nt) zs[i] *= inv;
       __syncthreads();
     }
-    done = (rot_count == 0);
+    for (int i = tid; i < n; i += nt) Z[(long)iv * n + i] = zs[i];
     __syncthreads();
   }
-  if (!done && tid == 0) atomicOr(&st->eig_fail, 1);
-  // sort eigenvalues descending (ties by index) and permute the eigenvector columns
-  for (int i = tid; i < n; i += nt) {
-    const double wi = A[(long)i * n + i];
-    int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      const double wj = A[(long)j * n + j];
-      rank += (wj > wi) || (wj == wi && j < i);
+  __syncthreads();
+
+  // ---- 4. back-transformation: V[:, iv] = H_0 H_1 ... H_{n-3} z_iv -------------
+  constexpr int PER = EIG_MAXN / 64;
+  for (int iv = wv; iv < kvec; iv += nw) {
+    double y[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) { const int i = lane + 64 * t; y[t] = i < n ? Z[(long)iv * n + i] : 0.0; }
+    for (int k = n - 3; k >= 0; --k) {
+      const double* v = R + (long)k * n;
+      double dp = 0.0;
+#pragma unroll
+      for (int t = 0; t < PER; ++t) { const int i = lane + 64 * t; if (i < n) dp += v[i] * y[t]; }
+      for (int o = 32; o > 0; o >>= 1) dp += __shfl_xor(dp, o);
+#pragma unroll
+      for (int t = 0; t < PER; ++t) { const int i = lane + 64 * t; if (i < n) y[t] -= 2.0 * dp * v[i]; }
     }
-    w[rank] = wi;
-    for (int r = 0; r < n; ++r) Vo[(long)r * n + rank] = V[(long)r * n + i];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) { const int i = lane + 64 * t; if (i < n) V[(long)i * n + iv] = y[t]; }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Judgement values, choice and truncation (Sections 2, 4.2.6-4.2.7):
 //   epsilon = sum_{l >= chi_new} max(lambda_l, 0),  U if epsilon < epsilon' else U'.
-// When the cut splits a multiplet of equal eigenvalues (relative difference at most
-// MULT_RTOL, eigenvalue at least MULT_ATOL of the largest) the whole multiplet is
-// dropped by zeroing its columns: "the first chi columns" are not unique there.
+// When the cut splits a multiplet of equal eigenvalues (difference at most
+// max(MULT_RTOL lambda_{k-1}, tau lambda_0), eigenvalue at least max(MULT_ATOL, tau) of the
+// largest) the whole multiplet is dropped by zeroing its columns: "the first chi columns"
+// are not unique there.  tau = 0 in the FP64 form (the oracle's rule); in the reduced-
+// precision forms tau is the form's noise floor relative to lambda_0, so that a multiplet
+// that is exact in the method is still recognised after rounding.
 // w: [2][n] (side 0 = A, side 1 = A'), V: [2][n][n].  identity != 0: untruncated, the
 // isometry is the identity (any orthonormal basis is exact when chi_new = n).
 // ---------------------------------------------------------------------------
 constexpr double MULT_RTOL = 1e-10, MULT_ATOL = 1e-12;
 
-__global__ void k_choose(const double* __restrict__ w, const double* __restrict__ V, int n, int chi_new,
-                         int identity, double* __restrict__ Ut, float* __restrict__ Ut32, StepRec* rec,
-                         int dir_index) {
+__global__ void k_choose(const double* __restrict__ w0, const double* __restrict__ w1,
+                         const double* __restrict__ V0, const double* __restrict__ V1, int n, int chi_new,
+                         int identity, double tau, double* __restrict__ Ut, float* __restrict__ Ut32,
+                         StepRec* rec, int dir_index) {
   __shared__ double eps_s[2];
   __shared__ int prime_s, kept_s;
   const int tid = threadIdx.x;
@@ -492,23 +793,26 @@ __global__ void k_choose(const double* __restrict__ w, const double* __restrict_
     return;
   }
   if (tid < 2) {
+    const double* ws = tid == 0 ? w0 : w1;
     double e = 0.0;
-    for (int l = chi_new; l < n; ++l) e += fmax(w[tid * n + l], 0.0);
+    for (int l = chi_new; l < n; ++l) e += fmax(ws[l], 0.0);
     eps_s[tid] = e;
   }
   __syncthreads();
   if (tid == 0) {
     const int side = !(eps_s[0] < eps_s[1]);
-    const double* lam = w + side * n;
+    const double* lam = side ? w1 : w0;
     int k = chi_new;
+    const double floor_ = fmax(MULT_ATOL, tau) * lam[0];
     if (k < n)
-      while (k > 1 && lam[k - 1] >= MULT_ATOL * lam[0] && lam[k - 1] - lam[k] <= MULT_RTOL * lam[k - 1]) --k;
+      while (k > 1 && lam[k - 1] >= floor_ &&
+             lam[k - 1] - lam[k] <= fmax(MULT_RTOL * lam[k - 1], tau * lam[0])) --k;
     prime_s = side;
     kept_s = k;
   }
   __syncthreads();
   const int side = prime_s, kept = kept_s;
-  const double* Vs = V + (long)side * n * n;
+  const double* Vs = side ? V1 : V0;
   for (int i = tid; i < n * chi_new; i += blockDim.x) {
     const int r = i / chi_new, c = i % chi_new;
     const double v = c < kept ? Vs[(long)r * n + c] : 0.0;
@@ -520,10 +824,10 @@ __global__ void k_choose(const double* __restrict__ w, const double* __restrict_
     rec->chose_prime[dir_index] = side; rec->truncated[dir_index] = 1;
     rec->chi_new[dir_index] = chi_new; rec->kept[dir_index] = kept;
     for (int s = 0; s < 2; ++s) {
+      const double* ws = s ? w1 : w0;
       const int ns = n < NSPEC ? n : NSPEC;
       rec->nspec[dir_index][s] = ns;
-      const double w0 = w[s * n];
-      for (int l = 0; l < ns; ++l) rec->spec[dir_index][s][l] = w[s * n + l] / w0;
+      for (int l = 0; l < ns; ++l) rec->spec[dir_index][s][l] = ws[l] / ws[0];
     }
   }
 }
@@ -585,6 +889,103 @@ __global__ __launch_bounds__(256) void k_pstage(const MT* __restrict__ T, const 
       const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
       Store<F>::put(B, row * ldb + (long)rho * b + nh1, bplane, (double)s * sB);
     }
+  }
+}
+
+// Prime chain (3D) with the isometries staged in LDS: one workgroup per check row
+// h = (rho, nc), looping over c' and the chunk's pair groups; same output as k_pstage.
+// LDS: U2 as [n2'][nc2'][nh2'], the chunk's columns of U1 as [n1'][nc1'][nh1'].
+template <class MT, class UT, int F>
+__global__ __launch_bounds__(256) void k_pstage3(const MT* __restrict__ T, const UT* __restrict__ U1,
+                                                 const UT* __restrict__ U2, Dims dm, int pr0, int pr1,
+                                                 typename Store<F>::T* __restrict__ B, long ldb, long bplane,
+                                                 const DevState* __restrict__ st) {
+  __shared__ MT u2t[16 * 256];
+  __shared__ MT u1t[16 * 256];
+  __shared__ MT X[256];
+  __shared__ MT Z[16 * 256];
+  const int tid = threadIdx.x;
+  const int h = blockIdx.x;
+  const int b = dm.b, chi1 = dm.chi1, chi2 = dm.chi2, k1 = dm.k1, k2 = dm.k2;
+  const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * sqrt((double)b)) : 1.0;
+  const int rho = h / b, nc = h % b;
+  const int n1lo = pr0 / k2, n1hi = (pr1 - 1) / k2, nn1 = n1hi - n1lo + 1;
+  const int c2sq = chi2 * chi2, c1sq = chi1 * chi1;
+  for (int i = tid; i < k2 * c2sq; i += 256) {
+    const int n2 = i / c2sq, rem = i % c2sq, nc2 = rem / chi2, nh2 = rem % chi2;
+    u2t[i] = (MT)U2[(nh2 + chi2 * nc2) * k2 + n2];
+  }
+  for (int i = tid; i < nn1 * c1sq; i += 256) {
+    const int n1 = n1lo + i / c1sq, rem = i % c1sq, nc1 = rem / chi1, nh1 = rem % chi1;
+    u1t[i] = (MT)U1[(nh1 + chi1 * nc1) * k1 + n1];
+  }
+  const int npairs = pr1 - pr0;
+  for (int cp = 0; cp < dm.chic; ++cp) {
+    __syncthreads();
+    for (int i = tid; i < b; i += 256) X[i] = T[(long)h * dm.H + (long)cp * b + i];
+    __syncthreads();
+    // Z[n1'][nh1'][nc2'] = sum_{nc1'} U1[nh1' + chi1 nc1', n1'] X[nc1'][nc2']
+    for (int i = tid; i < nn1 * b; i += 256) {
+      const int n1l = i / b, r = i % b, nh1 = r / chi2, nc2 = r % chi2;
+      const MT* u = &u1t[n1l * c1sq + nh1];
+      MT s = 0;
+      for (int nc1 = 0; nc1 < chi1; ++nc1) s += u[nc1 * chi1] * X[nc1 * chi2 + nc2];
+      Z[i] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < npairs * b; i += 256) {
+      const int pr = pr0 + i / b, r = i % b, nh1 = r / chi2, nh2 = r % chi2;
+      const int n1 = pr / k2, n2 = pr % k2;
+      const MT* z = &Z[(n1 - n1lo) * b + nh1 * chi2];
+      const MT* u = &u2t[n2 * c2sq + nh2];
+      MT s = 0;
+      for (int nc2 = 0; nc2 < chi2; ++nc2) s += z[nc2] * u[nc2 * chi2];
+      const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
+      Store<F>::put(B, row * ldb + (long)rho * b + r, bplane, (double)s * sB);
+    }
+  }
+}
+
+// Non-prime chain (3D) with U1, U2 staged in LDS; one workgroup per (c, group of up to 8 g).
+template <class AT, class MT, class UT>
+__global__ __launch_bounds__(256) void k_nstage3b(const AT* __restrict__ C, long ldc, const UT* __restrict__ U1,
+                                                  const UT* __restrict__ U2, Dims dm, int g0, int gcount,
+                                                  MT* __restrict__ Tn) {
+  constexpr int GPB = 8;
+  __shared__ MT u1s[16 * 256];   // [nh1][nc1][n1]
+  __shared__ MT u2s[16 * 256];   // [nh2][nc2][n2]
+  __shared__ MT tile[16 * 256];
+  __shared__ MT Q[256];
+  const int tid = threadIdx.x;
+  const int ngrp = (gcount + GPB - 1) / GPB;
+  const int c = blockIdx.x / ngrp, grp = blockIdx.x % ngrp;
+  const int b = dm.b, chi1 = dm.chi1, chi2 = dm.chi2, k1 = dm.k1, k2 = dm.k2;
+  const int Hn = k1 * k2 * dm.chic;
+  for (int i = tid; i < chi1 * chi1 * k1; i += 256) u1s[i] = (MT)U1[i];   // U1[(nh1 + chi1 nc1) k1 + n1]
+  for (int i = tid; i < chi2 * chi2 * k2; i += 256) u2s[i] = (MT)U2[i];
+  const int qa = tid / k2, qn2 = tid % k2;          // Q[nc1][n2]
+  const int on1 = tid / k2, on2 = tid % k2;         // out[n1][n2]
+  for (int gl = grp * GPB; gl < gcount && gl < (grp + 1) * GPB; ++gl) {
+    MT acc = 0;
+    for (int nh1 = 0; nh1 < chi1; ++nh1) {
+      __syncthreads();
+      for (int i = tid; i < chi2 * b; i += 256) {
+        const int nh2 = i / b, col = i % b;
+        tile[i] = (MT)C[(long)(c * b + nh1 * chi2 + nh2) * ldc + (long)gl * b + col];
+      }
+      __syncthreads();
+      if (qa < chi1) {
+        MT sq = 0;
+        for (int nh2 = 0; nh2 < chi2; ++nh2)
+          for (int nc2 = 0; nc2 < chi2; ++nc2)
+            sq += u2s[(nh2 + chi2 * nc2) * k2 + qn2] * tile[nh2 * b + qa * chi2 + nc2];
+        Q[qa * k2 + qn2] = sq;
+      }
+      __syncthreads();
+      if (on1 < k1)
+        for (int nc1 = 0; nc1 < chi1; ++nc1) acc += u1s[(nh1 + chi1 * nc1) * k1 + on1] * Q[nc1 * k2 + on2];
+    }
+    if (on1 < k1) Tn[(long)((on1 * k2 + on2) * dm.chic + c) * Hn + (g0 + gl)] = acc;
   }
 }
 

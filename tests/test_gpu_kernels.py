@@ -100,6 +100,22 @@ def test_contract_full_size_sampled():
         assert err < tol(P.HOTRG_FP64, 4096)
 
 
+@pytest.mark.parametrize("form", [P.HOTRG_SPLIT_FP16, P.HOTRG_SPLIT_BF16, P.HOTRG_FP16, P.HOTRG_FP32])
+def test_contract_forms_full_size_sampled(form):
+    """chi = 16 in 3D through the production kernels of each form (for the 16-bit forms the
+    non-prime chain runs in the GEMM epilogue at this size); sampled slices vs the oracle."""
+    dims, kdims = (16, 16, 16), (16, 16)
+    Ts, Us = _random_case(dims, kdims, seed=8)
+    Tp = LY.to_paper(Ts)
+    got = gu.contract(Ts, Us, list(kdims), form)
+    picks = [(0, 0), (15, 15), (7, 2)]
+    ref = LY.to_storage(H.rename(H.new_tensor(Tp, {1: Us[0], 2: Us[1]}, only=picks)))
+    for (n1p, n2p) in picks:
+        err = gu.relerr(got[:, :, :, n1p, n2p, :], ref[:, :, :, n1p, n2p, :])
+        print(f"form={form} full-size slice ({n1p},{n2p}) relerr={err:.3e} tol={tol(form, 4096):.1e}")
+        assert err < tol(form, 4096)
+
+
 @pytest.mark.parametrize("dims", [(4, 4, 4), (3, 5, 2), (8, 8, 8), (8, 8)])
 def test_gram_matches_oracle(dims):
     d = len(dims)
