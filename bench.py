@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--reference-form", default="fp64")
     ap.add_argument("--reference-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--other-forms", default="fp32,split_bf16,fp16,bf16",
+                    help="comma-separated forms also reported (2 timed steps each); empty for none")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of the "
@@ -149,6 +151,21 @@ def main():
     if ref_lnz is not None:
         n = min(len(ref_lnz), len(ref["lnz"]))
         ref_err = max(abs(ref["lnz"][i] - ref_lnz[i]) / abs(ref_lnz[i]) for i in range(n))
+
+    forms = {}
+    for form in [f for f in args.other_forms.split(",") if f]:
+        res = run_form(P, torch, form, 2, 0)
+        ftm = res["timings"]
+        e = None
+        if ref_lnz is not None:
+            n = min(len(ref_lnz), len(res["lnz"]))
+            e = max(abs(res["lnz"][i] - ref_lnz[i]) / abs(ref_lnz[i]) for i in range(n))
+        forms[form] = {
+            "ms_per_step": round(res["wall"] * 1e3 / 2, 3),
+            "contract_tflops": round(ftm["flops_contract"] / (ftm["contract"]["ms"] * 1e-3) / 1e12, 3),
+            "bottleneck_tflops": round(ftm["flops_bottleneck"] / (ftm["bottleneck"]["ms"] * 1e-3) / 1e12, 3),
+            "free_energy_rel_err_vs_oracle": e,
+        }
 
     out = {
         "metric": METRIC,
@@ -191,6 +208,7 @@ def main():
             "free_energy_rel_err_vs_oracle": ref_err,
             "speedup_of_headline_form": round(ref_ms_per_step / ms_per_step, 3),
         },
+        "other_forms": forms,
     }
     if not args.no_cpu:
         cb = cpu_baseline()

@@ -157,33 +157,42 @@ def gu_wen_ratio(T: np.ndarray) -> float:
 # ----------------------------------------------------------------------------
 
 
-def s_hat(T: np.ndarray, side_axis: int) -> np.ndarray:
+def s_hat(T: np.ndarray, side_axis: int, T2: np.ndarray | None = None) -> np.ndarray:
     """S^hat[f, g, rho, eta] = sum T[.. f .., c, rho] T[.. g .., c, eta] (eq. Aux_Tensor_hat_S).
 
     The sum runs over every leg except the side leg (n_j or n'_j) and c'; c is
-    summed.  rho and eta are the c' legs of the two copies.
+    summed.  rho and eta are the c' legs of the two copies.  T2 (default T) is the
+    second factor, for the bilinear form used by the derivative.
     """
+    T2 = T if T2 is None else T2
     d = T.ndim // 2
     L = _letters(2 * d)
     a = list(L)
     b = list(L)
     a[side_axis], b[side_axis] = "F", "G"
     a[axis_cp(d)], b[axis_cp(d)] = "R", "E"
-    return np.einsum("".join(a) + "," + "".join(b) + "->FGRE", T, T, optimize=True)
+    return np.einsum("".join(a) + "," + "".join(b) + "->FGRE", T, T2, optimize=True)
 
 
-def s_check(T: np.ndarray, side_axis: int) -> np.ndarray:
+def s_check(T: np.ndarray, side_axis: int, T2: np.ndarray | None = None) -> np.ndarray:
     """S^check[f, g, rho, eta] = sum T[.. f .., rho, c'] T[.. g .., eta, c'] (eq. Aux_Tensor_check_S).
 
     The sum runs over every leg except the side leg and c; c' is summed.
     """
+    T2 = T if T2 is None else T2
     d = T.ndim // 2
     L = _letters(2 * d)
     a = list(L)
     b = list(L)
     a[side_axis], b[side_axis] = "F", "G"
     a[axis_c(d)], b[axis_c(d)] = "R", "E"
-    return np.einsum("".join(a) + "," + "".join(b) + "->FGRE", T, T, optimize=True)
+    return np.einsum("".join(a) + "," + "".join(b) + "->FGRE", T, T2, optimize=True)
+
+
+def combine_gram(Sh: np.ndarray, Sc: np.ndarray) -> np.ndarray:
+    """A[(f^ f~), (g^ g~)] = sum_{rho, eta} Sh[f^ g^ rho eta] Sc[f~ g~ rho eta] (third step)."""
+    chi = Sh.shape[0]
+    return np.einsum("PQRE,pqRE->pPqQ", Sh, Sc).reshape(chi * chi, chi * chi)
 
 
 def gram_matrix(T: np.ndarray, side_axis: int) -> np.ndarray:
@@ -279,7 +288,8 @@ def _contract_leg(X: np.ndarray, axis: int, W: np.ndarray) -> np.ndarray:
     return np.moveaxis(Y, -1, axis)
 
 
-def new_tensor(T: np.ndarray, Ut: dict[int, np.ndarray], only=None) -> np.ndarray:
+def new_tensor(T: np.ndarray, Ut: dict[int, np.ndarray], only=None, T_check: np.ndarray | None = None,
+               U_prime: dict[int, np.ndarray] | None = None) -> np.ndarray:
     """T^new[n_{d-1}..n_1, n'_{d-1}..n'_1, c, c'] from two copies of T (hat and check)
     and the isometries Ut[j] (chi_{n_j}^2 x chi_new_j), in the order of Section 4.2.8:
 
@@ -293,13 +303,18 @@ def new_tensor(T: np.ndarray, Ut: dict[int, np.ndarray], only=None) -> np.ndarra
 
     only: optional list of tuples (n'_1, .., n'_{d-1}); when given, only those slices
     of T^new are computed (the others stay zero) -- used to sample large cases.
+    T_check, U_prime: the check copy and the isometries of the prime legs when they
+    differ from T and Ut (the terms of the derivative, which is multilinear in them).
     """
+    Tc = T if T_check is None else T_check
+    Up = Ut if U_prime is None else U_prime
     d = T.ndim // 2
     chi_c = T.shape[axis_c(d)]
     chi_n = {j: T.shape[axis_n(d, j)] for j in range(1, d)}
     k = {j: Ut[j].shape[1] for j in range(1, d)}
     # U[(a b), new] with (a b) = a + b chi  ->  Wj[b, a, new]: b = check index, a = hat index
     Wm = {j: Ut[j].reshape(chi_n[j], chi_n[j], k[j]) for j in range(1, d)}
+    Wp = {j: Up[j].reshape(chi_n[j], chi_n[j], k[j]) for j in range(1, d)}
 
     out_shape = tuple(k[j] for j in range(d - 1, 0, -1)) * 2 + (chi_c, chi_c)
     Tnew = np.zeros(out_shape)
@@ -314,7 +329,7 @@ def new_tensor(T: np.ndarray, Ut: dict[int, np.ndarray], only=None) -> np.ndarra
                 continue
             # C^check(j) = sum_{n'^check_j} U^(j)[(n'^hat_j n'^check_j), n'_j] C^check(j-1)
             # the leg n'^check_j of C is replaced by n'^hat_j
-            Uslice = Wm[j][:, :, nj]                     # [n'^check_j, n'^hat_j]
+            Uslice = Wp[j][:, :, nj]                     # [n'^check_j, n'^hat_j]
             Cj = _contract_leg(C, axis_np(d, j), Uslice)
             prime_chain(Cj, j + 1, {**fixed, j: nj})
 
@@ -344,7 +359,7 @@ def new_tensor(T: np.ndarray, Ut: dict[int, np.ndarray], only=None) -> np.ndarra
         idx += tuple(fixed[j] for j in range(d - 1, 0, -1))
         Tnew[idx] = Ch
 
-    prime_chain(T, 1, {})
+    prime_chain(Tc, 1, {})
     return Tnew
 
 

@@ -313,7 +313,7 @@ void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, 
   if constexpr (F != F_FP64 && F != F_FP32) {
     if (Z == 1 && smult == 1.0 && Mp % GB_BM == 0 && Np % GB_BN == 0 && Kp % GB_BK == 0) {
       const int mt = (int)(Mp / GB_BM), nt = (int)(Np / GB_BN);
-      constexpr int WAVES = PL == 2 ? 4 : 8;
+      constexpr int WAVES = 8;   // 2 waves per SIMD: one wave's LDS/barrier phase hides under the other's MFMAs
       if (fuse)
         hipLaunchKernelGGL((k_gemm_big<Op, PL, WAVES, true>), dim3((unsigned)(mt * nt)), dim3(64 * WAVES), 0, s,
                            (const typename Op::T*)A, lda, aplane, (const typename Op::T*)B, ldb, bplane,

@@ -933,15 +933,26 @@ __global__ __launch_bounds__(256) void k_pstage3(const MT* __restrict__ T, const
       Z[i] = s;
     }
     __syncthreads();
-    for (int i = tid; i < npairs * b; i += 256) {
-      const int pr = pr0 + i / b, r = i % b, nh1 = r / chi2, nh2 = r % chi2;
-      const int n1 = pr / k2, n2 = pr % k2;
-      const MT* z = &Z[(n1 - n1lo) * b + nh1 * chi2];
-      const MT* u = &u2t[n2 * c2sq + nh2];
-      MT s = 0;
-      for (int nc2 = 0; nc2 < chi2; ++nc2) s += z[nc2] * u[nc2 * chi2];
-      const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
-      Store<F>::put(B, row * ldb + (long)rho * b + r, bplane, (double)s * sB);
+    // thread <-> output position r = (nh1', nh2'); its 16 Z values stay in registers across
+    // the chunk's n2' values (one LDS read of U2 per multiply-add)
+    for (int r = tid; r < b; r += 256) {
+      const int nh1 = r / chi2, nh2 = r % chi2;
+      for (int n1 = n1lo; n1 <= n1hi; ++n1) {
+        MT z[16];
+#pragma unroll
+        for (int nc2 = 0; nc2 < 16; ++nc2) z[nc2] = nc2 < chi2 ? Z[(n1 - n1lo) * b + nh1 * chi2 + nc2] : (MT)0;
+        const int pa = n1 * k2 > pr0 ? n1 * k2 : pr0;
+        const int pb = (n1 + 1) * k2 < pr1 ? (n1 + 1) * k2 : pr1;
+        for (int pr = pa; pr < pb; ++pr) {
+          const MT* u = &u2t[(pr % k2) * c2sq + nh2];
+          MT s = 0;
+#pragma unroll
+          for (int nc2 = 0; nc2 < 16; ++nc2)
+            if (nc2 < chi2) s += z[nc2] * u[nc2 * chi2];
+          const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
+          Store<F>::put(B, row * ldb + (long)rho * b + r, bplane, (double)s * sB);
+        }
+      }
     }
   }
 }
