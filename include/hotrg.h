@@ -74,7 +74,8 @@ typedef struct hotrg_opts {
     int chunk;        /* new-tensor columns per chunk in units of (n'_1..,c') groups;
                          0 = automatic.  Bounds the memory of the prime-chain output
                          (the paper's loop over n'_1, Section 4.2.8).            */
-    int record_grad;  /* reserved: must be 0                                     */
+    int record_grad;  /* 1: carry d/dbeta through every step (FP64 / FP32 forms,
+                         beta > 0); hotrg_grad then returns d(lnZ/V)/dbeta        */
 } hotrg_opts;
 
 typedef struct hotrg_handle hotrg_handle;
@@ -156,7 +157,11 @@ int hotrg_profile(hotrg_handle* h, int enable);
 /* Synchronise and return the accumulated timings since profiling was enabled. */
 int hotrg_timings(hotrg_handle* h, hotrg_timing* out);
 
-/* Reserved for the adjoint d(lnZ/V)/dbeta; returns HOTRG_E_STATE in this version. */
+/* Synchronise and return d(lnZ^(p)/V^(p))/dbeta after the steps so far (minus the internal
+ * energy per site).  Requires record_grad = 1 at init (else HOTRG_E_STATE).  The derivative
+ * is carried forward through every step by the product rule: bond factor, Gram matrices,
+ * the leading eigenvectors (over the discarded ones; the choice U/U' and the truncation are
+ * held fixed), the multilinear new tensor, trace and normalisation (Sections 2-4). */
 int hotrg_grad(hotrg_handle* h, double* dlnz_dbeta_per_site);
 
 /* Release the handle (idempotent on NULL).  Does not free the workspace. */

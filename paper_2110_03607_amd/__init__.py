@@ -225,13 +225,14 @@ class HOTRG:
     """
 
     def __init__(self, kind: str, d: int, beta: float, chi: int, q: int | None = None, J: float = 1.0,
-                 h: float = 0.0, precision: str = "fp64", max_steps: int = 64, chunk: int = 0):
+                 h: float = 0.0, precision: str = "fp64", max_steps: int = 64, chunk: int = 0,
+                 record_grad: bool = False):
         import torch
 
         kind_id = {"ising": HOTRG_ISING, "potts": HOTRG_POTTS}[kind]
         q = 2 if kind == "ising" else (3 if q is None else q)
         self.model = hotrg_model(kind_id, d, q, J, h)
-        self.opts = hotrg_opts(FORMS[precision], max_steps, chunk, 0)
+        self.opts = hotrg_opts(FORMS[precision], max_steps, chunk, 1 if record_grad else 0)
         self.d = d
         nbytes = hotrg_workspace_bytes(self.model, chi, self.opts)
         if nbytes == 0:
@@ -255,6 +256,10 @@ class HOTRG:
 
     def log_z(self) -> float:
         return hotrg_log_z(self.handle)[0]
+
+    def grad(self) -> float:
+        """d(lnZ/V)/d(beta) after the steps so far (needs record_grad=True)."""
+        return hotrg_grad(self.handle)
 
     def info(self, step: int) -> hotrg_step_record:
         return hotrg_step_info(self.handle, step)
@@ -282,3 +287,29 @@ class HOTRG:
             self.close()
         except Exception:
             pass
+
+
+def lnz_per_site(beta, kind: str = "ising", d: int = 3, chi: int = 16, steps: int = 20, q: int | None = None,
+                 J: float = 1.0, precision: str = "fp64"):
+    """lnZ/V after `steps` steps as a differentiable function of beta (a 0-d torch tensor).
+
+    The forward pass runs HOTRG on the GPU with the derivative carried along
+    (record_grad); backward multiplies the incoming gradient by d(lnZ/V)/d(beta).
+    """
+    import torch
+
+    class _LnZ(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, b):
+            r = HOTRG(kind, d, float(b), chi, q=q, J=J, precision=precision, max_steps=steps, record_grad=True)
+            r.run(steps)
+            val, der = r.log_z(), r.grad()
+            r.close()
+            ctx.der = der
+            return torch.tensor(val, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, g):
+            return g * ctx.der
+
+    return _LnZ.apply(beta)

@@ -90,32 +90,36 @@ struct Need {
   size_t T, Aop, Bop, Cc, X, part, G, Amat, w, Ut;
 };
 
-long chunk_pairs_for(const LocalDims& ld, const int* k, int form, int user_chunk) {
+// Derivative mode doubles the operand rows ([dT | T] and [C2 | dC2]) and the product chunk.
+inline int grad_mult(bool grad) { return grad ? 2 : 1; }
+
+long chunk_pairs_for(const LocalDims& ld, const int* k, int form, int user_chunk, bool grad = false) {
   long total = 1;
   for (int j = 1; j < ld.d; ++j) total *= k[j - 1];
   if (user_chunk > 0) return std::min<long>(total, user_chunk);
   const Dims dm = make_dims(ld, k);
   const long Kp = roundup(dm.H, TILE_K), Mp = roundup(dm.H, TILE_M);
-  const double per_pair = (double)dm.chic * dm.b * (Kp * op_esize(form) * op_planes(form) + Mp * acc_size(form));
+  const double per_pair = (double)dm.chic * dm.b * (Kp * op_esize(form) * op_planes(form) + Mp * acc_size(form)) *
+                          grad_mult(grad);
   const double budget = 2.0 * 1024 * 1024 * 1024;
   long c = (long)std::max(1.0, std::floor(budget / per_pair));
   return std::min(total, c);
 }
 
-Need need_for(const LocalDims& ld, int chi, int form, int user_chunk) {
+Need need_for(const LocalDims& ld, int chi, int form, int user_chunk, bool grad = false) {
   Need n{};
   int k[MAXD];
   for (int j = 1; j < ld.d; ++j) k[j - 1] = std::min(ld.chi[j] * ld.chi[j], chi);
   const Dims dm = make_dims(ld, k);
   const long H = dm.H;
   const long Mp = roundup(H, TILE_M), Kp = roundup(H, TILE_K);
-  const long pairs = chunk_pairs_for(ld, k, form, user_chunk);
+  const long pairs = chunk_pairs_for(ld, k, form, user_chunk, grad);
   const long Np = roundup(pairs * dm.chic * dm.b, TILE_N);
   long Hn = dm.chic;
   for (int j = 0; j < ld.d - 1; ++j) Hn *= k[j];
   n.T = (size_t)std::max(H * H, Hn * Hn) * master_size(form);
-  n.Aop = (size_t)Mp * Kp * op_esize(form) * op_planes(form);
-  n.Bop = (size_t)Np * Kp * op_esize(form) * op_planes(form);
+  n.Aop = (size_t)Mp * Kp * op_esize(form) * op_planes(form) * grad_mult(grad);
+  n.Bop = (size_t)Np * Kp * op_esize(form) * op_planes(form) * grad_mult(grad);
   n.Cc = (size_t)Mp * Np * acc_size(form);
   size_t X = 0, part = 0, G = 0, Am = 0;
   for (int j = 1; j < ld.d; ++j) {
@@ -158,10 +162,13 @@ struct Plan {
   Need need;
   size_t off_state, off_rec, off_T, off_Tn, off_Aop, off_Bop, off_Cc, off_X, off_part, off_Gh, off_Gc,
       off_A, off_Vw, off_Vo, off_w, off_Ut, off_Ut32, total;
+  // derivative mode (0 when off)
+  size_t off_dT, off_dTn, off_dCc, off_Xd, off_dGh, off_dGc, off_dA, off_dUt, off_dUt32, off_dUw;
+  bool grad;
   int max_steps;
 };
 
-Plan make_plan(int d, int q, int chi, int form, int user_chunk, int max_steps) {
+Plan make_plan(int d, int q, int chi, int form, int user_chunk, int max_steps, bool grad = false) {
   Plan P{};
   Need nd{};
   const std::vector<int> vals = reachable_dims(q, chi);
@@ -173,10 +180,11 @@ Plan make_plan(int d, int q, int chi, int form, int user_chunk, int max_steps) {
   for (int cidx = 0; cidx < combos; ++cidx) {
     int r = cidx;
     for (int i = 0; i < d; ++i) { ld.chi[i] = vals[r % nv]; r /= nv; }
-    need_max(nd, need_for(ld, chi, form, user_chunk));
+    need_max(nd, need_for(ld, chi, form, user_chunk, grad));
   }
   P.need = nd;
   P.max_steps = max_steps;
+  P.grad = grad;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = roundup(o + bytes, ALIGN); return r; };
   P.off_state = take(sizeof(DevState));
@@ -196,6 +204,18 @@ Plan make_plan(int d, int q, int chi, int form, int user_chunk, int max_steps) {
   P.off_w = take(EIG_SLOTS * nd.w);
   P.off_Ut = take(MAXD * nd.Ut);
   P.off_Ut32 = take(MAXD * nd.Ut / 2 + 64);
+  if (grad) {
+    P.off_dT = take(nd.T);
+    P.off_dTn = take(nd.T);
+    P.off_dCc = take(nd.Cc);
+    P.off_Xd = take(nd.X);
+    P.off_dGh = take(nd.G);
+    P.off_dGc = take(nd.G);
+    P.off_dA = take(EIG_SLOTS * nd.Amat);
+    P.off_dUt = take(MAXD * nd.Ut);
+    P.off_dUt32 = take(MAXD * nd.Ut / 2 + 64);
+    P.off_dUw = take(2 * nd.Amat);   // k_dU: W = dA U_kept and the kept x discarded coefficients
+  }
   P.total = o;
   return P;
 }
@@ -235,6 +255,7 @@ struct hotrg_handle {
   int p = 0;
   bool failed = false;
   bool no_fuse = false;   // force the separate non-prime kernel (tests of the fused epilogue)
+  bool grad = false;      // derivative mode: carry dT/dbeta through every step
   std::string err;
   // live timing: pairs of events recorded on the stream, resolved at hotrg_timings
   bool profiling = false;
@@ -333,8 +354,9 @@ void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, 
 }
 
 // Gram matrices for direction j (1-based) into A_out[side] (n x n each, n = chi_j^2).
+// With dT != null (derivative mode) also dA_out = dA/dbeta.
 int enqueue_gram(hotrg_handle* h, const void* T, bool t_is_f64, const LocalDims& ld, int j, int side,
-                 double* A_out) {
+                 double* A_out, const void* dT = nullptr, double* dA_out = nullptr) {
   const int d = ld.d;
   long H = 1;
   for (int i = 0; i < d; ++i) H *= ld.chi[i];
@@ -365,20 +387,37 @@ int enqueue_gram(hotrg_handle* h, const void* T, bool t_is_f64, const LocalDims&
       ps.od[k] = dims2[l]; ps.sstride[k++] = str[l];
     }
     ps.rows = R; ps.cols = g.C; ps.rows_p = g.Rp; ps.ldd = g.Cp;
-    if (t_is_f64)
-      hipLaunchKernelGGL((k_permute<double, double>), dim3(grid_for(g.Rp * g.Cp)), dim3(256), 0, h->s,
-                         (const double*)T, X, ps, 1.0);
-    else
-      hipLaunchKernelGGL((k_permute<float, double>), dim3(grid_for(g.Rp * g.Cp)), dim3(256), 0, h->s,
-                         (const float*)T, X, ps, 1.0);
+    auto permute = [&](const void* src, double* dst) {
+      if (t_is_f64)
+        hipLaunchKernelGGL((k_permute<double, double>), dim3(grid_for(g.Rp * g.Cp)), dim3(256), 0, h->s,
+                           (const double*)src, dst, ps, 1.0);
+      else
+        hipLaunchKernelGGL((k_permute<float, double>), dim3(grid_for(g.Rp * g.Cp)), dim3(256), 0, h->s,
+                           (const float*)src, dst, ps, 1.0);
+    };
+    permute(T, X);
     launch_gemm<F_FP64>(X, g.Cp, 0, X, g.Cp, 0, part, g.Rp, g.Rp * g.Rp, g.Rp, g.Rp, g.Cp, g.Z, g.kchunk,
                         nullptr, 1.0, h->s);
     hipLaunchKernelGGL(k_reduce_z, dim3(grid_for(R * R)), dim3(256), 0, h->s, (const double*)part,
                        g.Rp * g.Rp, g.Rp, g.Z, (int)R, which == 0 ? Gh : Gc);
+    if (dT) {
+      // d(X X^T) = dX X^T + (dX X^T)^T
+      double* Xd = h->at<double>(h->plan.off_Xd);
+      permute(dT, Xd);
+      launch_gemm<F_FP64>(Xd, g.Cp, 0, X, g.Cp, 0, part, g.Rp, g.Rp * g.Rp, g.Rp, g.Rp, g.Cp, g.Z, g.kchunk,
+                          nullptr, 1.0, h->s);
+      hipLaunchKernelGGL(k_reduce_z_sym, dim3(grid_for(R * R)), dim3(256), 0, h->s, (const double*)part,
+                         g.Rp * g.Rp, g.Rp, g.Z, (int)R,
+                         which == 0 ? h->at<double>(h->plan.off_dGh) : h->at<double>(h->plan.off_dGc));
+    }
   }
   const long n = (long)ld.chi[j] * ld.chi[j];
   hipLaunchKernelGGL(k_gram_combine, dim3(grid_for(n * n)), dim3(256), 0, h->s, (const double*)Gh,
                      (const double*)Gc, ld.chi[j], ld.chi[0], A_out);
+  if (dT)
+    hipLaunchKernelGGL(k_gram_combine_t, dim3(grid_for(n * n)), dim3(256), 0, h->s, (const double*)Gh,
+                       (const double*)Gc, (const double*)h->at<double>(h->plan.off_dGh),
+                       (const double*)h->at<double>(h->plan.off_dGc), ld.chi[j], ld.chi[0], dA_out);
   HIPCHK(h, hipGetLastError());
   return HOTRG_OK;
 }
@@ -407,8 +446,8 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
   typedef typename std::conditional<F == F_FP64, double, float>::type UT;
   const long aplane = Mp * Kp;
   hipEvent_t t_all = tmark(h);
-  hipLaunchKernelGGL((k_make_a<MT, F>), dim3(grid_for(aplane)), dim3(256), 0, h->s, T, (int)H, Aop, Mp, Kp,
-                     (const DevState*)st);
+  hipLaunchKernelGGL((k_make_a<MT, F>), dim3(grid_for(aplane)), dim3(256), 0, h->s, T, (int)H, Aop, Mp, Kp, Kp,
+                     0L, (const DevState*)st);
   for (long pr0 = 0; pr0 < pairs_total; pr0 += cp) {
     const long pr1 = std::min(pairs_total, pr0 + cp);
     const long ncols = (pr1 - pr0) * dm.chic * dm.b;
@@ -416,7 +455,7 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     const long bplane = Np * Kp;
     hipEvent_t t0 = tmark(h);
     hipLaunchKernelGGL((k_zero_pad<ST>), dim3(grid_for((Np - ncols) * Kp + ncols * (Kp - H) + 1)), dim3(256), 0,
-                       h->s, Bop, ncols, Np, H, Kp, bplane, FormInfo<F>::planes);
+                       h->s, Bop, ncols, Np, H, Kp, bplane, FormInfo<F>::planes, 1);
     if (ld.d == 3)
       hipLaunchKernelGGL((k_pstage3<MT, UT, F>), dim3((unsigned)H), dim3(256), 0, h->s, T, (const UT*)U1,
                          (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane, (const DevState*)st);
@@ -478,6 +517,104 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
   return HOTRG_OK;
 }
 
+// Derivative mode (FP64 / FP32 forms): the new tensor and dT^new/dbeta.  The contraction is
+// multilinear in (hat copy, check copy, isometries), so
+//   dC2 = P(dT; U) + P(T; dU1, U2) + P(T; U1, dU2)          (prime chain, accumulated)
+//   dC  = dA C2 + A dC2 = [dA | A] . [C2 | dC2]^T            (one GEMM over 2 Kp)
+//   dT^new = N(dC; U) + N(C; dU1, U2) + N(C; U1, dU2)       (non-prime chain, accumulated)
+// Operand rows hold both halves: A rows [dT | T], B rows [C2 | dC2] (row length 2 Kp).
+template <int F>
+int enqueue_contract_grad(hotrg_handle* h, const void* Tv, void* Tnv, const void* dTv, void* dTnv,
+                          const LocalDims& ld, const int* k) {
+  static_assert(F == F_FP64 || F == F_FP32, "derivative mode: FP64 and FP32 forms");
+  typedef typename std::conditional<F == F_FP64, double, float>::type MT;
+  typedef MT UT;
+  const MT* T = (const MT*)Tv;
+  const MT* dT = (const MT*)dTv;
+  MT* Tn = (MT*)Tnv;
+  MT* dTn = (MT*)dTnv;
+  const Dims dm = make_dims(ld, k);
+  const long H = dm.H, Mp = roundup(H, TILE_M), Kp = roundup(H, TILE_K), L2 = 2 * Kp;
+  const long pairs_total = (ld.d == 3) ? (long)k[0] * k[1] : k[0];
+  const long cp = chunk_pairs_for(ld, k, h->form, h->opts.chunk, true);
+  MT* Aop = h->at<MT>(h->plan.off_Aop);
+  MT* Bop = h->at<MT>(h->plan.off_Bop);
+  MT* Cc = h->at<MT>(h->plan.off_Cc);
+  MT* dCc = h->at<MT>(h->plan.off_dCc);
+  DevState* st = h->st();
+  const size_t ut_stride = h->plan.need.Ut / 8;
+  const UT* U1 = F == F_FP64 ? (const UT*)h->at<double>(h->plan.off_Ut) : (const UT*)h->at<float>(h->plan.off_Ut32);
+  const UT* dU1 = F == F_FP64 ? (const UT*)h->at<double>(h->plan.off_dUt)
+                              : (const UT*)h->at<float>(h->plan.off_dUt32);
+  const UT* U2 = U1 + ut_stride;
+  const UT* dU2 = dU1 + ut_stride;
+  hipEvent_t t_all = tmark(h);
+  hipLaunchKernelGGL((k_make_a<MT, F>), dim3(grid_for(Mp * Kp)), dim3(256), 0, h->s, dT, (int)H, Aop, Mp, Kp, L2,
+                     0L, (const DevState*)st);
+  hipLaunchKernelGGL((k_make_a<MT, F>), dim3(grid_for(Mp * Kp)), dim3(256), 0, h->s, T, (int)H, Aop, Mp, Kp, L2,
+                     Kp, (const DevState*)st);
+  for (long pr0 = 0; pr0 < pairs_total; pr0 += cp) {
+    const long pr1 = std::min(pairs_total, pr0 + cp);
+    const long ncols = (pr1 - pr0) * dm.chic * dm.b;
+    const long Np = roundup(ncols, TILE_N);
+    const long bplane = Np * L2;
+    const int ip0 = (int)pr0, ip1 = (int)pr1;
+    hipEvent_t t0 = tmark(h);
+    hipLaunchKernelGGL((k_zero_pad<MT>), dim3(grid_for((Np - ncols) * L2 + 2 * ncols * (Kp - H) + 1)), dim3(256), 0,
+                       h->s, Bop, ncols, Np, H, Kp, bplane, 1, 2);
+    if (ld.d == 3) {
+      const dim3 g((unsigned)H);
+      hipLaunchKernelGGL((k_pstage3<MT, UT, F, false>), g, dim3(256), 0, h->s, T, U1, U2, dm, ip0, ip1, Bop, L2,
+                         bplane, (const DevState*)st);
+      hipLaunchKernelGGL((k_pstage3<MT, UT, F, false>), g, dim3(256), 0, h->s, dT, U1, U2, dm, ip0, ip1, Bop + Kp,
+                         L2, bplane, (const DevState*)st);
+      hipLaunchKernelGGL((k_pstage3<MT, UT, F, true>), g, dim3(256), 0, h->s, T, dU1, U2, dm, ip0, ip1, Bop + Kp,
+                         L2, bplane, (const DevState*)st);
+      hipLaunchKernelGGL((k_pstage3<MT, UT, F, true>), g, dim3(256), 0, h->s, T, U1, dU2, dm, ip0, ip1, Bop + Kp,
+                         L2, bplane, (const DevState*)st);
+    } else {
+      const dim3 g((unsigned)(H * dm.chic));
+      hipLaunchKernelGGL((k_pstage<MT, UT, F, false>), g, dim3(256), 0, h->s, T, U1, U2, dm, ip0, ip1, Bop, L2,
+                         bplane, (const DevState*)st);
+      hipLaunchKernelGGL((k_pstage<MT, UT, F, false>), g, dim3(256), 0, h->s, dT, U1, U2, dm, ip0, ip1, Bop + Kp,
+                         L2, bplane, (const DevState*)st);
+      hipLaunchKernelGGL((k_pstage<MT, UT, F, true>), g, dim3(256), 0, h->s, T, dU1, U2, dm, ip0, ip1, Bop + Kp,
+                         L2, bplane, (const DevState*)st);
+    }
+    tclose(h, HOTRG_T_PRIME, t0);
+    hipEvent_t t1 = tmark(h);
+    launch_gemm<F>(Aop + Kp, L2, 0, Bop, L2, 0, Cc, Np, 0, Mp, Np, Kp, 1, Kp, nullptr, 1.0, h->s);
+    launch_gemm<F>(Aop, L2, 0, Bop, L2, 0, dCc, Np, 0, Mp, Np, L2, 1, L2, nullptr, 1.0, h->s);
+    tclose(h, HOTRG_T_BOTTLENECK, t1);
+    if (h->profiling) h->acc.flops_bottleneck += 3.0 * 2.0 * (double)H * (double)ncols * (double)H;
+    hipEvent_t t2 = tmark(h);
+    const int g0 = ip0 * dm.chic, gcount = (ip1 - ip0) * dm.chic;
+    if (ld.d == 3) {
+      const dim3 g((unsigned)(dm.chic * ((gcount + 7) / 8)));
+      hipLaunchKernelGGL((k_nstage3b<MT, MT, UT, false>), g, dim3(256), 0, h->s, (const MT*)Cc, Np, U1, U2, dm, g0,
+                         gcount, Tn);
+      hipLaunchKernelGGL((k_nstage3b<MT, MT, UT, false>), g, dim3(256), 0, h->s, (const MT*)dCc, Np, U1, U2, dm,
+                         g0, gcount, dTn);
+      hipLaunchKernelGGL((k_nstage3b<MT, MT, UT, true>), g, dim3(256), 0, h->s, (const MT*)Cc, Np, dU1, U2, dm, g0,
+                         gcount, dTn);
+      hipLaunchKernelGGL((k_nstage3b<MT, MT, UT, true>), g, dim3(256), 0, h->s, (const MT*)Cc, Np, U1, dU2, dm, g0,
+                         gcount, dTn);
+    } else {
+      const dim3 g((unsigned)((long)dm.chic * gcount));
+      hipLaunchKernelGGL((k_nstage2<MT, MT, UT, false>), g, dim3(64), 0, h->s, (const MT*)Cc, Np, U1, dm, g0, gcount,
+                         Tn);
+      hipLaunchKernelGGL((k_nstage2<MT, MT, UT, false>), g, dim3(64), 0, h->s, (const MT*)dCc, Np, U1, dm, g0,
+                         gcount, dTn);
+      hipLaunchKernelGGL((k_nstage2<MT, MT, UT, true>), g, dim3(64), 0, h->s, (const MT*)Cc, Np, dU1, dm, g0, gcount,
+                         dTn);
+    }
+    tclose(h, HOTRG_T_NONPRIME, t2);
+  }
+  tclose(h, HOTRG_T_CONTRACT, t_all);
+  HIPCHK(h, hipGetLastError());
+  return HOTRG_OK;
+}
+
 int enqueue_contract(hotrg_handle* h, const void* T, void* Tn, const LocalDims& ld, const int* k) {
   switch (h->form) {
     case HOTRG_FP64: return enqueue_contract_f<F_FP64>(h, T, Tn, ld, k);
@@ -492,7 +629,8 @@ int enqueue_contract(hotrg_handle* h, const void* T, void* Tn, const LocalDims& 
 
 // Gram matrices of every truncated direction, one eigensolver launch over all of them,
 // then the choice / truncation of U^(j) per direction (untruncated: identity).
-int enqueue_decomposition(hotrg_handle* h, const void* T, const LocalDims& ld, const int* k, StepRec* rec) {
+int enqueue_decomposition(hotrg_handle* h, const void* T, const LocalDims& ld, const int* k, StepRec* rec,
+                          const void* dT = nullptr) {
   const int d = ld.d;
   const size_t ut_stride = h->plan.need.Ut / 8;
   const size_t am = h->plan.need.Amat / 8, wn = h->plan.need.w / 8;
@@ -506,11 +644,12 @@ int enqueue_decomposition(hotrg_handle* h, const void* T, const LocalDims& ld, c
     if (n <= h->chi) continue;
     for (int side = 0; side < 2; ++side) {
       const int slot = (j - 1) * 2 + side;
-      int rc = enqueue_gram(h, T, h->form == HOTRG_FP64, ld, j, side, Am + slot * am);
+      int rc = enqueue_gram(h, T, h->form == HOTRG_FP64, ld, j, side, Am + slot * am, dT,
+                            dT ? h->at<double>(h->plan.off_dA) + slot * am : nullptr);
       if (rc) return rc;
       const int b = eb.count++;
       eb.n[b] = n;
-      eb.kvec[b] = k[j - 1];
+      eb.kvec[b] = dT ? n : k[j - 1];   // the derivative needs the discarded eigenvectors too
       eb.A[b] = Am + slot * am;
       eb.w[b] = w + slot * wn;
       eb.V[b] = Vo + slot * am;
@@ -527,6 +666,22 @@ int enqueue_decomposition(hotrg_handle* h, const void* T, const LocalDims& ld, c
     hipLaunchKernelGGL(k_choose, dim3(1), dim3(256), 0, h->s, (const double*)(w + s0 * wn),
                        (const double*)(w + s1 * wn), (const double*)(Vo + s0 * am), (const double*)(Vo + s1 * am),
                        n, k[j - 1], n <= h->chi ? 1 : 0, multiplet_tau(h->form), Ut, Ut32, rec, j - 1);
+    if (dT) {
+      double* dUt = h->at<double>(h->plan.off_dUt) + (size_t)(j - 1) * ut_stride;
+      float* dUt32 = h->at<float>(h->plan.off_dUt32) + (size_t)(j - 1) * ut_stride;
+      if (n <= h->chi) {
+        hipLaunchKernelGGL(k_zero_f64_f32, dim3(grid_for((long)n * n)), dim3(256), 0, h->s, dUt, dUt32,
+                           (long)n * n);
+      } else {
+        double* dAm = h->at<double>(h->plan.off_dA);
+        double* scr = h->at<double>(h->plan.off_dUw);
+        hipLaunchKernelGGL(k_dU, dim3(1), dim3(256), 0, h->s, (const double*)(w + s0 * wn),
+                           (const double*)(w + s1 * wn), (const double*)(Vo + s0 * am),
+                           (const double*)(Vo + s1 * am), (const double*)(dAm + s0 * am),
+                           (const double*)(dAm + s1 * am), n, k[j - 1], (const StepRec*)rec, j - 1, scr, scr + am,
+                           dUt, dUt32);
+      }
+    }
   }
   HIPCHK(h, hipGetLastError());
   return HOTRG_OK;
@@ -562,6 +717,17 @@ int enqueue_relayout(hotrg_handle* h, int axis) {
   else
     hipLaunchKernelGGL((k_permute<float, float>), dim3(grid_for(H * H)), dim3(256), 0, h->s, (const float*)T,
                        (float*)Tn, ps, 1.0);
+  if (h->grad) {
+    void* dT = h->at<void>(h->plan.off_dT);
+    void* dTn = h->at<void>(h->plan.off_dTn);
+    if (h->form == HOTRG_FP64)
+      hipLaunchKernelGGL((k_permute<double, double>), dim3(grid_for(H * H)), dim3(256), 0, h->s, (const double*)dT,
+                         (double*)dTn, ps, 1.0);
+    else
+      hipLaunchKernelGGL((k_permute<float, float>), dim3(grid_for(H * H)), dim3(256), 0, h->s, (const float*)dT,
+                         (float*)dTn, ps, 1.0);
+    std::swap(h->plan.off_dT, h->plan.off_dTn);
+  }
   HIPCHK(h, hipGetLastError());
   std::swap(h->plan.off_T, h->plan.off_Tn);
   LocalDims nl = h->ld;
@@ -610,7 +776,9 @@ static int check_model(const hotrg_model* m, int chi) {
 size_t hotrg_workspace_bytes(const hotrg_model* model, int chi, const hotrg_opts* opts) {
   if (!opts || check_model(model, chi) != HOTRG_OK || !form_valid(opts->precision) || opts->max_steps < 1)
     return 0;
-  return make_plan(model->d, model->q, chi, opts->precision, opts->chunk, opts->max_steps).total;
+  if (opts->record_grad && opts->precision != HOTRG_FP64 && opts->precision != HOTRG_FP32) return 0;
+  return make_plan(model->d, model->q, chi, opts->precision, opts->chunk, opts->max_steps, opts->record_grad != 0)
+      .total;
 }
 
 int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts* opts, void* workspace,
@@ -619,13 +787,18 @@ int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts*
   *out = nullptr;
   if (!opts || !model) return fail(nullptr, HOTRG_E_ARG, "model or opts is NULL");
   if (check_model(model, chi) != HOTRG_OK) return fail(nullptr, HOTRG_E_ARG, "invalid model or chi");
-  if (!form_valid(opts->precision) || opts->max_steps < 1 || opts->chunk < 0 || opts->record_grad != 0)
+  if (!form_valid(opts->precision) || opts->max_steps < 1 || opts->chunk < 0 || opts->record_grad < 0 ||
+      opts->record_grad > 1)
     return fail(nullptr, HOTRG_E_ARG, "invalid options");
+  if (opts->record_grad && opts->precision != HOTRG_FP64 && opts->precision != HOTRG_FP32)
+    return fail(nullptr, HOTRG_E_ARG, "the derivative is available in the FP64 and FP32 forms");
+  if (opts->record_grad && !(beta > 0.0))
+    return fail(nullptr, HOTRG_E_ARG, "the derivative needs beta > 0");
   if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(nullptr, HOTRG_E_ARG, "beta must be finite and >= 0");
   // W must be positive semi-definite: Ising needs sinh(beta J) >= 0, Potts e^{beta J} - 1 >= 0
   if (beta * model->J < 0.0) return fail(nullptr, HOTRG_E_NOT_PSD, "bond weight matrix is not PSD (J < 0)");
   if (!workspace) return fail(nullptr, HOTRG_E_ARG, "workspace is NULL");
-  Plan P = make_plan(model->d, model->q, chi, opts->precision, opts->chunk, opts->max_steps);
+  Plan P = make_plan(model->d, model->q, chi, opts->precision, opts->chunk, opts->max_steps, opts->record_grad != 0);
   if (ws_bytes < P.total) return fail(nullptr, HOTRG_E_OOM, "workspace too small");
   if (((uintptr_t)workspace) % ALIGN) return fail(nullptr, HOTRG_E_ARG, "workspace must be 256-byte aligned");
   hotrg_handle* h = new hotrg_handle();
@@ -638,16 +811,19 @@ int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts*
   h->ws_bytes = ws_bytes;
   h->s = (hipStream_t)stream;
   h->plan = P;
+  h->grad = opts->record_grad != 0;
   h->ld.d = model->d;
   for (int i = 0; i < model->d; ++i) { h->ld.chi[i] = model->q; h->axes[i] = i; }
   hipError_t e = hipMemsetAsync(h->ws, 0, P.off_T, h->s);   // state + records
   if (e == hipSuccess) {
     if (h->form == HOTRG_FP64)
       hipLaunchKernelGGL((k_init_tensor<double>), dim3(1), dim3(256), 0, h->s, h->at<double>(P.off_T),
-                         model->kind, model->d, model->q, beta, model->J, model->h, h->st());
+                         h->grad ? h->at<double>(P.off_dT) : (double*)nullptr, model->kind, model->d, model->q, beta,
+                         model->J, model->h, h->st());
     else
       hipLaunchKernelGGL((k_init_tensor<float>), dim3(1), dim3(256), 0, h->s, h->at<float>(P.off_T),
-                         model->kind, model->d, model->q, beta, model->J, model->h, h->st());
+                         h->grad ? h->at<float>(P.off_dT) : (float*)nullptr, model->kind, model->d, model->q, beta,
+                         model->J, model->h, h->st());
     e = hipGetLastError();
   }
   if (e != hipSuccess) {
@@ -677,11 +853,18 @@ int hotrg_step(hotrg_handle* h, int axis) {
                      d == 3 ? ld.chi[2] : 0);
   void* T = h->at<void>(h->plan.off_T);
   void* Tn = h->at<void>(h->plan.off_Tn);
+  void* dT = h->grad ? h->at<void>(h->plan.off_dT) : nullptr;
+  void* dTn = h->grad ? h->at<void>(h->plan.off_dTn) : nullptr;
   hipEvent_t t_dec = tmark(h);
-  rc = enqueue_decomposition(h, T, ld, k, rec);
+  rc = enqueue_decomposition(h, T, ld, k, rec, dT);
   if (rc) return rc;
   tclose(h, HOTRG_T_DECOMP, t_dec);
-  rc = enqueue_contract(h, T, Tn, ld, k);
+  if (!h->grad)
+    rc = enqueue_contract(h, T, Tn, ld, k);
+  else if (h->form == HOTRG_FP64)
+    rc = enqueue_contract_grad<F_FP64>(h, T, Tn, dT, dTn, ld, k);
+  else
+    rc = enqueue_contract_grad<F_FP32>(h, T, Tn, dT, dTn, ld, k);
   if (rc) return rc;
   // new dims after renaming: c^bar = n_1, n^bar_j = n_{j+1}, n^bar_{d-1} = c
   LocalDims nl;
@@ -692,7 +875,23 @@ int hotrg_step(hotrg_handle* h, int axis) {
   for (int i = 0; i < d; ++i) Hn *= nl.chi[i];
   DevState* st = h->st();
   hipEvent_t t_tr = tmark(h);
-  if (h->form == HOTRG_FP64) {
+  if (h->grad) {
+    if (h->form == HOTRG_FP64) {
+      hipLaunchKernelGGL((k_trace_lnz<double>), dim3(1), dim3(256), 0, h->s, (const double*)Tn, (int)Hn, ld.chi[0],
+                         st, rec, p);
+      hipLaunchKernelGGL((k_trace_t<double>), dim3(1), dim3(256), 0, h->s, (const double*)dTn, (int)Hn, st, p);
+      hipLaunchKernelGGL(k_reset_maxabs, dim3(1), dim3(1), 0, h->s, st);
+      hipLaunchKernelGGL((k_scale_t<double>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (double*)Tn,
+                         (double*)dTn, Hn * Hn, st);
+    } else {
+      hipLaunchKernelGGL((k_trace_lnz<float>), dim3(1), dim3(256), 0, h->s, (const float*)Tn, (int)Hn, ld.chi[0],
+                         st, rec, p);
+      hipLaunchKernelGGL((k_trace_t<float>), dim3(1), dim3(256), 0, h->s, (const float*)dTn, (int)Hn, st, p);
+      hipLaunchKernelGGL(k_reset_maxabs, dim3(1), dim3(1), 0, h->s, st);
+      hipLaunchKernelGGL((k_scale_t<float>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (float*)Tn, (float*)dTn,
+                         Hn * Hn, st);
+    }
+  } else if (h->form == HOTRG_FP64) {
     hipLaunchKernelGGL((k_trace_lnz<double>), dim3(1), dim3(256), 0, h->s, (const double*)Tn, (int)Hn, ld.chi[0],
                        st, rec, p);
     hipLaunchKernelGGL(k_reset_maxabs, dim3(1), dim3(1), 0, h->s, st);
@@ -707,6 +906,7 @@ int hotrg_step(hotrg_handle* h, int axis) {
   tclose(h, HOTRG_T_STEP, t_step);
   HIPCHK(h, hipGetLastError());
   std::swap(h->plan.off_T, h->plan.off_Tn);
+  if (h->grad) std::swap(h->plan.off_dT, h->plan.off_dTn);
   int na[MAXD];
   for (int i = 0; i < d; ++i) na[i] = h->axes[(i + 1) % d];
   for (int i = 0; i < d; ++i) h->axes[i] = na[i];
@@ -768,9 +968,13 @@ int hotrg_spectrum(hotrg_handle* h, int step, int dir, int side, double* outv, i
 }
 
 int hotrg_grad(hotrg_handle* h, double* outv) {
-  (void)outv;
-  if (!h) return fail(nullptr, HOTRG_E_ARG, "handle is NULL");
-  return fail(h, HOTRG_E_STATE, "gradient recording is not enabled in this version");
+  if (!h || !outv) return fail(h, HOTRG_E_ARG, "NULL argument");
+  if (!h->grad) return fail(h, HOTRG_E_STATE, "the handle was created without record_grad");
+  DevState s;
+  int rc = sync_state(h, &s);
+  if (rc) return rc;
+  *outv = s.dlnz;
+  return HOTRG_OK;
 }
 
 int hotrg_profile(hotrg_handle* h, int enable) {

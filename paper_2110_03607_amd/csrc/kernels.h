@@ -28,6 +28,8 @@ struct DevState {
   double f;            // f^(p) = 1 / Tr T^(p), applied to the new tensor
   double maxabs;       // max |T| of the current (normalised) tensor
   double inv_scale;    // 1 / (s_A s_B) applied to the FP16-form products
+  double dlnz;         // d(lnZ/V)/d(beta) (derivative mode)
+  double dt;           // d(Tr T^new)/d(beta) of the last step
   int err;             // sticky error code (HOTRG_E_*)
   int p;               // steps done
   int eig_fail;        // eigensolver did not converge
@@ -482,15 +484,17 @@ __global__ void k_permute(const S* __restrict__ src, D* __restrict__ dst, PermSp
 
 // A operand of the bottleneck in form F: A[m][k] = s_A * T[m][k] for m, k < H, zero padded
 // to Mp x Kp.  s_A = 1 except for the FP16 forms (power of two from max|T|).
+// The operand rows may be longer than Kp (ld >= Kp, derivative mode stores [dT | T] per row):
+// this writes columns [off, off + Kp) of every row.
 template <class MT, int F>
 __global__ void k_make_a(const MT* __restrict__ T, int H, typename Store<F>::T* __restrict__ A, long Mp,
-                         long Kp, const DevState* __restrict__ st) {
+                         long Kp, long ld, long off, const DevState* __restrict__ st) {
   const double sA = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs) : 1.0;
-  const long plane = Mp * Kp;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < plane; i += (long)gridDim.x * blockDim.x) {
+  const long plane = Mp * ld;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < Mp * Kp; i += (long)gridDim.x * blockDim.x) {
     const long m = i / Kp, k = i % Kp;
     const double x = (m < H && k < H) ? (double)T[m * H + k] * sA : 0.0;
-    Store<F>::put(A, i, plane, x);
+    Store<F>::put(A, m * ld + off + k, plane, x);
   }
 }
 
@@ -548,6 +552,28 @@ struct EigBatch {
   double* scratch[4];
 };
 
+// zs -= sum_{j0 <= j < j1} (Z_j . zs) Z_j: all coefficients first (a wave per vector,
+// lanes over entries), then one update; zs in LDS, the Z_j rows in global memory.
+__device__ inline void cgs_cluster(double* zs, const double* __restrict__ Z, int n, int j0, int j1, double* coef,
+                                   int tid, int nt, int lane, int wv, int nw) {
+  if (j1 <= j0) return;
+  __syncthreads();
+  for (int j = j0 + wv; j < j1; j += nw) {
+    const double* zj = Z + (long)j * n;
+    double dp = 0.0;
+    for (int i = lane; i < n; i += 64) dp += zj[i] * zs[i];
+    for (int o = 32; o > 0; o >>= 1) dp += __shfl_xor(dp, o);
+    if (lane == 0) coef[j - j0] = dp;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += nt) {
+    double v = zs[i];
+    for (int j = j0; j < j1; ++j) v -= coef[j - j0] * Z[(long)j * n + i];
+    zs[i] = v;
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
   __shared__ double d[EIG_MAXN], e[EIG_MAXN], vv[EIG_MAXN], qv[EIG_MAXN];
   __shared__ double red[EIG_THREADS / 64];
@@ -566,11 +592,13 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
     for (int i = tid; i < m; i += nt) {
       x = A[(long)(k + 1 + i) * n + k];
       vv[i] = x;
-      ss += x * x;
+      if (i > 0) ss += x * x;
     }
-    const double sigma = block_sum(ss, red);          // includes a barrier: vv visible
+    // squared norm of the entries below the subdiagonal, summed on its own: taking it as
+    // |x|^2 - x0^2 would cancel and drop entries up to sqrt(u) |x0|
+    const double tail = block_sum(ss, red);           // includes a barrier: vv visible
     const double x0 = vv[0];
-    const double tail = sigma - x0 * x0;
+    const double sigma = x0 * x0 + tail;
     if (tid == 0) d[k] = A[(long)k * n + k];
     if (!(tail > 0.0)) {                              // already tridiagonal in this column
       if (tid == 0) e[k] = x0;
@@ -665,6 +693,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
   const double ortol = 1e-3 * tnorm;
   const double pivlu = fmax(1e-290, 2.2e-16 * tnorm);   // pivot floor: bounded growth, no overflow
   double* zs = vv;                                       // LDS copy of the current vector
+  double* coef = qv;                                     // Gram-Schmidt coefficients (qv is free now)
   for (int iv = 0; iv < kvec; ++iv) {
     const double lam = w[iv];
     if (tid == 0) {
@@ -695,12 +724,20 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
         }
       }
     }
-    for (int i = tid; i < n; i += nt) {      // deterministic start vector
+    for (int i = tid; i < n; i += nt) {      // deterministic start vector, zero-mean entries
       const unsigned hsh = (unsigned)(i + 1) * 2654435761u ^ (unsigned)(iv + 7) * 40503u;
-      zs[i] = 0.5 + (double)(hsh & 0xFFFFu) / 65536.0;
+      zs[i] = (double)(hsh & 0xFFFFu) / 32768.0 - 1.0;
     }
     __syncthreads();
-    for (int it = 0; it < 2; ++it) {
+    // vectors already found in this cluster (consecutive eigenvalues within ortol)
+    int j0 = iv;
+    while (j0 > 0 && fabs(w[j0 - 1] - lam) <= ortol) --j0;
+    // the start vector is made orthogonal to them first, so that the solve amplifies the
+    // directions not found yet (inside a cluster of equal eigenvalues all of them grow alike)
+    cgs_cluster(zs, Z, n, j0, iv, coef, tid, nt, lane, wv, nw);
+    // three solves: inside a large cluster of (numerically) zero eigenvalues the first two
+    // still leave components of the order 1e-9 along eigenvalues outside the cluster
+    for (int it = 0; it < 3; ++it) {
       if (tid == 0) {
         double cur = zs[0];
         for (int r = 0; r + 1 < n; ++r) {        // row operations, value of row r carried in cur
@@ -718,14 +755,10 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
         }
       }
       __syncthreads();
-      for (int jv = iv - 1; jv >= 0 && fabs(w[jv] - lam) <= ortol; --jv) {   // same cluster: MGS
-        const double* zj = Z + (long)jv * n;
-        double dp = 0.0;
-        for (int i = tid; i < n; i += nt) dp += zj[i] * zs[i];
-        const double dot = block_sum(dp, red);
-        for (int i = tid; i < n; i += nt) zs[i] -= dot * zj[i];
-        __syncthreads();
-      }
+      // same cluster: classical Gram-Schmidt, twice (one pass leaves the rounding of a
+      // vector dominated by found directions unorthogonalised)
+      cgs_cluster(zs, Z, n, j0, iv, coef, tid, nt, lane, wv, nw);
+      cgs_cluster(zs, Z, n, j0, iv, coef, tid, nt, lane, wv, nw);
       double np = 0.0;
       for (int i = tid; i < n; i += nt) np += zs[i] * zs[i];
       const double inv = 1.0 / sqrt(block_sum(np, red));
@@ -846,7 +879,7 @@ struct Dims {
   int d, chic, chi1, chi2, k1, k2, b, H;   // chi2 = k2 = 1 for d = 2
 };
 
-template <class MT, class UT, int F>
+template <class MT, class UT, int F, bool ACC = false>
 __global__ __launch_bounds__(256) void k_pstage(const MT* __restrict__ T, const UT* __restrict__ U1,
                                                 const UT* __restrict__ U2, Dims dm, int pr0, int pr1,
                                                 typename Store<F>::T* __restrict__ B, long ldb, long bplane,
@@ -879,7 +912,8 @@ __global__ __launch_bounds__(256) void k_pstage(const MT* __restrict__ T, const 
       MT s = 0;
       for (int nc2 = 0; nc2 < chi2; ++nc2) s += z[nc2] * (MT)U2[(nh2 + chi2 * nc2) * dm.k2 + n2];
       const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
-      Store<F>::put(B, row * ldb + (long)rho * b + r, bplane, (double)s * sB);
+      if constexpr (ACC) B[row * ldb + (long)rho * b + r] += s;
+      else Store<F>::put(B, row * ldb + (long)rho * b + r, bplane, (double)s * sB);
     }
   } else {
     for (int i = tid; i < npairs * b; i += blockDim.x) {
@@ -887,7 +921,8 @@ __global__ __launch_bounds__(256) void k_pstage(const MT* __restrict__ T, const 
       MT s = 0;
       for (int nc1 = 0; nc1 < chi1; ++nc1) s += (MT)U1[(nh1 + chi1 * nc1) * dm.k1 + pr] * X[nc1];
       const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
-      Store<F>::put(B, row * ldb + (long)rho * b + nh1, bplane, (double)s * sB);
+      if constexpr (ACC) B[row * ldb + (long)rho * b + nh1] += s;
+      else Store<F>::put(B, row * ldb + (long)rho * b + nh1, bplane, (double)s * sB);
     }
   }
 }
@@ -895,7 +930,8 @@ __global__ __launch_bounds__(256) void k_pstage(const MT* __restrict__ T, const 
 // Prime chain (3D) with the isometries staged in LDS: one workgroup per check row
 // h = (rho, nc), looping over c' and the chunk's pair groups; same output as k_pstage.
 // LDS: U2 as [n2'][nc2'][nh2'], the chunk's columns of U1 as [n1'][nc1'][nh1'].
-template <class MT, class UT, int F>
+// ACC: add to the operand instead of writing it (FP64 / FP32 forms; terms of the derivative).
+template <class MT, class UT, int F, bool ACC = false>
 __global__ __launch_bounds__(256) void k_pstage3(const MT* __restrict__ T, const UT* __restrict__ U1,
                                                  const UT* __restrict__ U2, Dims dm, int pr0, int pr1,
                                                  typename Store<F>::T* __restrict__ B, long ldb, long bplane,
@@ -950,7 +986,8 @@ __global__ __launch_bounds__(256) void k_pstage3(const MT* __restrict__ T, const
           for (int nc2 = 0; nc2 < 16; ++nc2)
             if (nc2 < chi2) s += z[nc2] * u[nc2 * chi2];
           const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
-          Store<F>::put(B, row * ldb + (long)rho * b + r, bplane, (double)s * sB);
+          if constexpr (ACC) B[row * ldb + (long)rho * b + r] += s;
+          else Store<F>::put(B, row * ldb + (long)rho * b + r, bplane, (double)s * sB);
         }
       }
     }
@@ -958,7 +995,7 @@ __global__ __launch_bounds__(256) void k_pstage3(const MT* __restrict__ T, const
 }
 
 // Non-prime chain (3D) with U1, U2 staged in LDS; one workgroup per (c, group of up to 8 g).
-template <class AT, class MT, class UT>
+template <class AT, class MT, class UT, bool ACC = false>
 __global__ __launch_bounds__(256) void k_nstage3b(const AT* __restrict__ C, long ldc, const UT* __restrict__ U1,
                                                   const UT* __restrict__ U2, Dims dm, int g0, int gcount,
                                                   MT* __restrict__ Tn) {
@@ -996,19 +1033,28 @@ __global__ __launch_bounds__(256) void k_nstage3b(const AT* __restrict__ C, long
       if (on1 < k1)
         for (int nc1 = 0; nc1 < chi1; ++nc1) acc += u1s[(nh1 + chi1 * nc1) * k1 + on1] * Q[nc1 * k2 + on2];
     }
-    if (on1 < k1) Tn[(long)((on1 * k2 + on2) * dm.chic + c) * Hn + (g0 + gl)] = acc;
+    if (on1 < k1) {
+      MT* o = &Tn[(long)((on1 * k2 + on2) * dm.chic + c) * Hn + (g0 + gl)];
+      if constexpr (ACC) *o += acc; else *o = acc;
+    }
   }
 }
 
-// Zero the padding of a B operand: columns [K, Kp) of rows [0, N) and all of rows [N, Np).
+// Zero the padding of a B operand whose rows (length ld = nblk * Kp) hold nblk blocks of Kp
+// columns: columns [K, Kp) of every block of rows [0, N), and all of rows [N, Np).
 template <class ST>
-__global__ void k_zero_pad(ST* __restrict__ B, long N, long Np, long K, long Kp, long plane, int planes) {
-  const long padc = Kp - K;
-  const long n1 = N * padc, n2 = (Np - N) * Kp;
+__global__ void k_zero_pad(ST* __restrict__ B, long N, long Np, long K, long Kp, long plane, int planes,
+                           int nblk) {
+  const long padc = Kp - K, ld = Kp * nblk;
+  const long n1 = N * padc * nblk, n2 = (Np - N) * ld;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n1 + n2; i += (long)gridDim.x * blockDim.x) {
     long off;
-    if (i < n1) off = (i / padc) * Kp + K + (i % padc);
-    else off = N * Kp + (i - n1);
+    if (i < n1) {
+      const long row = i / (padc * nblk), rem = i % (padc * nblk);
+      off = row * ld + (rem / padc) * Kp + K + (rem % padc);
+    } else {
+      off = N * ld + (i - n1);
+    }
     for (int p = 0; p < planes; ++p) B[off + p * plane] = (ST)0;
   }
 }
@@ -1056,7 +1102,7 @@ __global__ __launch_bounds__(256) void k_nstage3(const AT* __restrict__ C, long 
   if (on1 < k1) Tn[(long)((on1 * k2 + on2) * dm.chic + c) * Hn + g] = acc;
 }
 
-template <class AT, class MT, class UT>
+template <class AT, class MT, class UT, bool ACC = false>
 __global__ __launch_bounds__(64) void k_nstage2(const AT* __restrict__ C, long ldc, const UT* __restrict__ U1,
                                                 Dims dm, int g0, int gcount, MT* __restrict__ Tn) {
   __shared__ MT tile[32 * 32];
@@ -1073,7 +1119,8 @@ __global__ __launch_bounds__(64) void k_nstage2(const AT* __restrict__ C, long l
     MT s = 0;
     for (int nh1 = 0; nh1 < chi1; ++nh1)
       for (int nc1 = 0; nc1 < chi1; ++nc1) s += (MT)U1[(nh1 + chi1 * nc1) * k1 + n1] * tile[nh1 * chi1 + nc1];
-    Tn[(long)(n1 * dm.chic + c) * Hn + g] = s;
+    if constexpr (ACC) Tn[(long)(n1 * dm.chic + c) * Hn + g] += s;
+    else Tn[(long)(n1 * dm.chic + c) * Hn + g] = s;
   }
 }
 
@@ -1128,6 +1175,144 @@ __global__ __launch_bounds__(256) void k_trace_lnz(const MT* __restrict__ Tn, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// Derivative (forward mode) helpers.
+// ---------------------------------------------------------------------------
+
+// dG = G1 + G1^T from the split-K slices of G1 = dX X^T (the derivative of G = X X^T).
+__global__ void k_reduce_z_sym(const double* __restrict__ part, long zstride, long ldp, int Z, int R,
+                               double* __restrict__ out) {
+  const long n = (long)R * R;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long r = i / R, c = i % R;
+    double s = 0.0;
+    for (int z = 0; z < Z; ++z) s += part[z * zstride + r * ldp + c] + part[z * zstride + c * ldp + r];
+    out[i] = s;
+  }
+}
+
+// dA = sum_{rho, eta} (dGh Gc + Gh dGc), the derivative of the third Gram step.
+__global__ void k_gram_combine_t(const double* __restrict__ Gh, const double* __restrict__ Gc,
+                                 const double* __restrict__ dGh, const double* __restrict__ dGc, int chis, int chic,
+                                 double* __restrict__ dA) {
+  const int n = chis * chis, R = chis * chic;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (long)n * n; i += (long)gridDim.x * blockDim.x) {
+    const int row = (int)(i / n), col = (int)(i % n);
+    const int fh = row % chis, fc = row / chis, gh = col % chis, gc = col / chis;
+    double s = 0.0;
+    for (int r = 0; r < chic; ++r)
+      for (int e = 0; e < chic; ++e) {
+        const long ih = (long)(fh * chic + r) * R + gh * chic + e, ic = (long)(fc * chic + r) * R + gc * chic + e;
+        s += dGh[ih] * Gc[ic] + Gh[ih] * dGc[ic];
+      }
+    dA[i] = s;
+  }
+}
+
+// Derivative of the kept columns of the adopted isometry (choice and multiplet cut held):
+//   dU_k = sum_{l >= kept} U_l (U_l^T dA U_k) / (lambda_k - lambda_l),  k < kept.
+// Rotations among kept columns are a bond gauge and are left out.  Evaluated as
+//   dU_k = P_D g_k / lambda_k + sum_{l >= kept} U_l (U_l^T g_k) lambda_l / (lambda_k (lambda_k - lambda_l))
+// with g_k = dA U_k and P_D = I - U_K U_K^T (the same sum, split with
+// 1/(lambda_k - lambda_l) = 1/lambda_k + lambda_l/(lambda_k (lambda_k - lambda_l))): the
+// discarded eigenvectors enter weighted by their eigenvalue, so the large cluster of
+// near-zero eigenvalues, whose individual vectors are least accurate, only counts through
+// the projector built from the kept vectors.  One workgroup; the side and `kept` come from
+// the step record written by k_choose.  W: n x kept scratch, M: n x kept scratch.
+__global__ __launch_bounds__(256) void k_dU(const double* __restrict__ w0, const double* __restrict__ w1,
+                                            const double* __restrict__ V0, const double* __restrict__ V1,
+                                            const double* __restrict__ dA0, const double* __restrict__ dA1,
+                                            int n, int chi_new, const StepRec* __restrict__ rec, int dir_index,
+                                            double* __restrict__ W, double* __restrict__ M,
+                                            double* __restrict__ dUt, float* __restrict__ dUt32) {
+  const int tid = threadIdx.x;
+  const int side = rec->chose_prime[dir_index], kept = rec->kept[dir_index];
+  const double* lam = side ? w1 : w0;
+  const double* V = side ? V1 : V0;
+  const double* dA = side ? dA1 : dA0;
+  // W = dA U_K
+  for (int i = tid; i < n * kept; i += 256) {
+    const int a = i / kept, k = i % kept;
+    double s = 0.0;
+    for (int b = 0; b < n; ++b) s += dA[(long)a * n + b] * V[(long)b * n + k];
+    W[i] = s;
+  }
+  __syncthreads();
+  // M[l][k] = U_l . g_k for every l (kept rows first)
+  for (int i = tid; i < n * kept; i += 256) {
+    const int l = i / kept, k = i % kept;
+    double s = 0.0;
+    for (int a = 0; a < n; ++a) s += V[(long)a * n + l] * W[a * kept + k];
+    M[i] = s;
+  }
+  __syncthreads();
+  for (int i = tid; i < n * chi_new; i += 256) {
+    const int a = i / chi_new, k = i % chi_new;
+    double s = 0.0;
+    if (k < kept && lam[k] > 0.0) {
+      const double lk = lam[k];
+      double pk = W[a * kept + k];
+      for (int j = 0; j < kept; ++j) pk -= V[(long)a * n + j] * M[j * kept + k];
+      double t = 0.0;
+      for (int l = kept; l < n; ++l) t += V[(long)a * n + l] * M[l * kept + k] * (lam[l] / (lk - lam[l]));
+      s = (pk + t) / lk;
+    }
+    dUt[i] = s;
+    dUt32[i] = (float)s;
+  }
+}
+
+// dU = 0 (untruncated directions: the identity does not depend on beta).
+__global__ void k_zero_f64_f32(double* a, float* b, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    a[i] = 0.0;
+    b[i] = 0.f;
+  }
+}
+
+// dt = Tr dT^new and d(lnZ/V) += (dt / t) / 2^p (after k_trace_lnz of the same step).
+template <class MT>
+__global__ __launch_bounds__(256) void k_trace_t(const MT* __restrict__ dTn, int Hn, DevState* st, int p) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int h = tid; h < Hn; h += 256) s += (double)dTn[(long)h * Hn + h];
+  red[tid] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double dt = red[0];
+    st->dt = dt;
+    st->dlnz += dt * st->f / ldexp(1.0, p);   // f = 1 / t
+  }
+}
+
+// Normalisation with its derivative: T <- f T, dT <- f (dT - T dt f) (f = 1 / t), both
+// from the un-normalised T; max |f T| into st->maxabs.
+template <class MT>
+__global__ void k_scale_t(MT* __restrict__ T, MT* __restrict__ dT, long n, DevState* st) {
+  __shared__ double red[256];
+  const double f = st->f, dtf = st->dt * st->f;
+  double mx = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double t = (double)T[i];
+    const MT v = (MT)(t * f);
+    T[i] = v;
+    dT[i] = (MT)(f * ((double)dT[i] - t * dtf));
+    mx = fmax(mx, fabs((double)v));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax((unsigned long long*)&st->maxabs, __double_as_longlong(red[0]));
+}
+
 // T <- f T over n elements, and max |f T| into st->maxabs (for the FP16 scaling).
 template <class MT>
 __global__ void k_scale(MT* __restrict__ T, long n, DevState* st) {
@@ -1179,29 +1364,39 @@ __global__ void k_rec_init(StepRec* rec, int p, int axis, int d, int c0, int c1,
 // (1, .., 1)/sqrt q (e^{bJ} + q - 1) and the Helmert vectors (e^{bJ} - 1).
 // T0[h][h'] = sum_s V_s prod_legs X[s][k_leg], normalised by f^(0) = 1/Tr T0.
 // ---------------------------------------------------------------------------
+// With dT != null also the derivative: dX from d(sqrt(lambda))/d(beta) with the beta-independent
+// eigenvectors, dT0 by the product rule, d(lnZ/V) at p = 0 and dT = dT0/t0 - T0 dt0/t0^2.
 template <class MT>
-__global__ void k_init_tensor(MT* __restrict__ T, int kind, int d, int q, double beta, double J, double hfield,
-                              DevState* st) {
-  __shared__ double X[8 * 8];
-  __shared__ double V[8];
-  __shared__ double tr_s;
+__global__ void k_init_tensor(MT* __restrict__ T, MT* __restrict__ dT, int kind, int d, int q, double beta,
+                              double J, double hfield, DevState* st) {
+  __shared__ double X[8 * 8], dX[8 * 8];
+  __shared__ double V[8], dV[8];
+  __shared__ double tr_s, dtr_s;
   const int tid = threadIdx.x;
   if (tid == 0) {
     if (kind == 0) {
-      const double ch = sqrt(cosh(beta * J)), sh = sqrt(sinh(beta * J));
+      const double c = cosh(beta * J), sn = sinh(beta * J);
+      const double ch = sqrt(c), sh = sqrt(sn);
       X[0 * q + 0] = ch; X[0 * q + 1] = sh;
       X[1 * q + 0] = ch; X[1 * q + 1] = -sh;
+      const double dch = J * sn / (2.0 * ch), dsh = sh > 0.0 ? J * c / (2.0 * sh) : 0.0;
+      dX[0 * q + 0] = dch; dX[0 * q + 1] = dsh;
+      dX[1 * q + 0] = dch; dX[1 * q + 1] = -dsh;
       V[0] = exp(beta * hfield); V[1] = exp(-beta * hfield);
+      dV[0] = hfield * V[0]; dV[1] = -hfield * V[1];
     } else {
-      const double l0 = exp(beta * J) + q - 1, l1 = exp(beta * J) - 1;
+      const double e = exp(beta * J), l0 = e + q - 1, l1 = e - 1, dl = J * e;
       for (int s = 0; s < q; ++s) {
         X[s * q + 0] = sqrt(l0 / q);
+        dX[s * q + 0] = dl / (2.0 * sqrt(l0 * q));
         for (int k = 1; k < q; ++k) {
           const double nk = 1.0 / sqrt((double)k * (k + 1));
           const double u = (s < k) ? nk : (s == k ? -k * nk : 0.0);
           X[s * q + k] = u * sqrt(l1);
+          dX[s * q + k] = l1 > 0.0 ? u * dl / (2.0 * sqrt(l1)) : 0.0;
         }
         V[s] = 1.0;
+        dV[s] = 0.0;
       }
     }
     // Tr T0 = sum_s V_s (sum_k X[s][k]^2)^d
@@ -1211,9 +1406,18 @@ __global__ void k_init_tensor(MT* __restrict__ T, int kind, int d, int q, double
       for (int k = 0; k < q; ++k) wss += X[s * q + k] * X[s * q + k];
       tr += V[s] * pow(wss, (double)d);
     }
+    // dTr T0 = sum_s [dV_s w_ss^d + V_s d w_ss^{d-1} dw_ss],  w_ss = sum_k X[s][k]^2
+    double dtr = 0.0;
+    for (int s = 0; s < q; ++s) {
+      double wss = 0.0, dwss = 0.0;
+      for (int k = 0; k < q; ++k) { wss += X[s * q + k] * X[s * q + k]; dwss += 2.0 * X[s * q + k] * dX[s * q + k]; }
+      dtr += dV[s] * pow(wss, (double)d) + V[s] * d * pow(wss, (double)(d - 1)) * dwss;
+    }
     tr_s = tr;
+    dtr_s = dtr;
     st->lnz0 = log(tr);
     st->lnz = log(tr);
+    st->dlnz = dtr / tr;
     st->f = 1.0 / tr;
     st->p = 0;
     st->err = 0;
@@ -1222,17 +1426,32 @@ __global__ void k_init_tensor(MT* __restrict__ T, int kind, int d, int q, double
   __syncthreads();
   int H = 1;
   for (int i = 0; i < d; ++i) H *= q;
-  const double f = 1.0 / tr_s;
+  const double f = 1.0 / tr_s, dtf = dtr_s / tr_s;
   double mx = 0.0;
   for (int i = tid; i < H * H; i += blockDim.x) {
-    double v = 0.0;
+    double v = 0.0, dv = 0.0;
     for (int s = 0; s < q; ++s) {
       double prod = V[s];
       int rem = i;
-      for (int l = 0; l < 2 * d; ++l) { prod *= X[s * q + rem % q]; rem /= q; }
+      double legs[16];
+      for (int l = 0; l < 2 * d; ++l) { legs[l] = X[s * q + rem % q]; prod *= legs[l]; rem /= q; }
       v += prod;
+      if (dT) {
+        double dprod = dV[s];
+        for (int l = 0; l < 2 * d; ++l) dprod *= legs[l];
+        rem = i;
+        for (int l = 0; l < 2 * d; ++l) {
+          double term = V[s] * dX[s * q + rem % q];
+          for (int l2 = 0; l2 < 2 * d; ++l2)
+            if (l2 != l) term *= legs[l2];
+          dprod += term;
+          rem /= q;
+        }
+        dv += dprod;
+      }
     }
     T[i] = (MT)(v * f);
+    if (dT) dT[i] = (MT)(f * (dv - v * dtf));
     mx = fmax(mx, fabs(v * f));
   }
   // maxabs (single block)

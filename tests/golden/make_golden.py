@@ -21,6 +21,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle import hotrg as H  # noqa: E402
+from oracle import tangent as TG  # noqa: E402
 from tests import seeded_inputs as SI  # noqa: E402
 
 N_SPEC = 24
@@ -79,7 +80,39 @@ def provenance():
                 numpy_blas_threads=os.environ.get("OMP_NUM_THREADS", "default"))
 
 
+# d(lnZ/V)/dbeta cases: (kind, d, q, beta, chi, steps); 2D chi = 16 reaches n = 256 Gram
+# matrices, 3D Potts chi = 9 has S3 doublets and multiplet cuts.  The 2D Potts run at
+# beta = 1.0 (near its critical point) stops at step 14: from step 16 on, its cuts sit in
+# clusters with relative gaps of 1e-6 to 1e-9, where the kept subspace moves by about
+# (rounding of A) / gap, so two correct FP64 implementations part at the 1e-8 level.
+GRAD_CASES = [
+    ("ising", 2, 2, 0.44, 16, 20),
+    ("potts", 2, 3, 1.0, 16, 14),
+    ("potts", 3, 3, 0.55, 9, 8),
+]
+
+
+def run_grad():
+    runs = []
+    for kind, d, q, beta, chi, steps in GRAD_CASES:
+        t0 = time.time()
+        lnz0, dlnz0, recs = TG.run_with_tangent(H.Model(kind, d, q), beta, chi, steps)
+        runs.append(dict(kind=kind, d=d, q=q, beta=beta, chi=chi, steps=steps, lnz0=lnz0, dlnz0=dlnz0,
+                         lnz=[r[0] for r in recs], dlnz=[r[1] for r in recs], wall_seconds=time.time() - t0))
+        print(f"  grad {kind} d={d} chi={chi} beta={beta}: dlnz/dbeta={recs[-1][1]:.15f} "
+              f"({time.time() - t0:.1f}s)", flush=True)
+    return runs
+
+
 def main(names):
+    if "grad" in names:
+        doc = dict(config="grad", runs=run_grad(), provenance=provenance(),
+                   source="oracle/tangent.py (FP64 NumPy), written by tests/golden/make_golden.py")
+        path = os.path.join(HERE, "grad.json")
+        with open(path, "w") as f:
+            json.dump(doc, f, indent=1)
+        print("wrote", path, flush=True)
+        names = [n for n in names if n != "grad"]
     table = {
         "config1": (SI.CONFIG1, [1.0 / T for T in SI.CONFIG1["temps"]]),
         "config2": (SI.CONFIG2, [1.0 / T for T in SI.CONFIG2["temps"]]),

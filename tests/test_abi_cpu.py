@@ -93,3 +93,14 @@ def test_debug_workspace_bytes():
     assert P.hotrg_debug_workspace_bytes(2, [8, 8], [16], P.HOTRG_SPLIT_FP16) > 0
     assert P.hotrg_debug_eigh_workspace_bytes(256, 2) >= 2 * 256 * 256 * 8
     assert P.hotrg_debug_eigh_workspace_bytes(2000, 1) == 0
+
+
+def test_derivative_mode_forms():
+    o = P.hotrg_opts(P.HOTRG_FP64, 8, 0, 1)
+    assert P.hotrg_workspace_bytes(_model(), 8, o) > P.hotrg_workspace_bytes(_model(), 8, P.hotrg_opts(0, 8, 0, 0))
+    assert P.hotrg_workspace_bytes(_model(), 8, P.hotrg_opts(P.HOTRG_FP32, 8, 0, 1)) > 0
+    assert P.hotrg_workspace_bytes(_model(), 8, P.hotrg_opts(P.HOTRG_SPLIT_FP16, 8, 0, 1)) == 0
+    h = ctypes.c_void_p()
+    rc = P.lib().hotrg_init(ctypes.byref(_model()), 0.0, 8, ctypes.byref(o), ctypes.c_void_p(256), 1 << 40, None,
+                            ctypes.byref(h))
+    assert rc == P.HOTRG_E_ARG     # the derivative needs beta > 0

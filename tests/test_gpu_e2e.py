@@ -102,6 +102,27 @@ def test_config2_3d_ising_chi8(precision, bound):
     assert worst < bound
 
 
+@pytest.mark.parametrize("precision,bound", [("fp64", 1e-10), ("split_fp16", 1e-6), ("fp32", 1e-6),
+                                             ("split_bf16", 1e-4)])
+def test_config3_3d_ising_chi16(precision, bound):
+    """3D Ising, chi = 16, T = 4.5115, 25 steps (the benchmark workload) against the oracle
+    fixture after every step; steps 1-3 are untruncated, step 3 is the 2x2x2 torus."""
+    path = os.path.join(GOLDEN, "config3.json")
+    if not os.path.exists(path):
+        pytest.skip("config3 fixture not generated")
+    fx = load("config3.json")
+    run = fx["runs"][0]
+    r, lnz = run_gpu("ising", 3, run["beta"], fx["chi"], fx["steps"], precision=precision)
+    emax, elast = _compare_run(run, lnz, bound)
+    per_step = [abs(g - rec["lnz_per_site"]) / abs(rec["lnz_per_site"]) for rec, g in zip(run["steps"], lnz)]
+    print(f"config3 {precision} beta={run['beta']:.7f} max rel err={emax:.2e} final={elast:.2e}")
+    print("  per step:", " ".join(f"{e:.1e}" for e in per_step))
+    kept = [[r.info(p).kept[j] for j in range(2)] for p in range(1, fx["steps"] + 1)]
+    kept_ref = [[rec["dirs"][str(j)]["kept"] for j in (1, 2)] for rec in run["steps"]]
+    print("  kept differs at steps:", [p + 1 for p in range(fx["steps"]) if kept[p] != kept_ref[p]])
+    assert emax < bound
+
+
 def test_config2_spectra_and_judgement_values():
     fx = load("config2.json")
     run = fx["runs"][1]

@@ -154,3 +154,45 @@ def test_eigh_matches_library(n):
         R = A[b] @ V[b] - V[b] * w[b][None, :]
         assert np.linalg.norm(R) < 1e-13 * abs(ref[0]) * n
         assert np.linalg.norm(V[b].T @ V[b] - np.eye(n)) < 1e-13 * n
+
+
+def _near_tridiagonal(n, eps, seed):
+    rng = np.random.default_rng(seed)
+    B = np.diag(2 + rng.random(n)) + np.diag(0.5 * rng.random(n - 1), 1)
+    B = B + np.triu(B, 1).T
+    N = rng.standard_normal((n, n)) * eps
+    return B + (N + N.T) / 2
+
+
+def _gram_with_null_index(chi, seed):
+    # Gram matrix of a bond with one null index (a multiplet dropped at the previous cut):
+    # rows and columns (a, b) with a or b = chi - 1 are exactly zero
+    n = chi * chi
+    Q = SI.random_isometry(n, n, seed=seed)
+    lam = np.exp(-0.05 * np.arange(n))
+    lam[1::7] = lam[0::7][: lam[1::7].size]          # exact doublets
+    A = (Q * lam) @ Q.T
+    null = [a * chi + b for a in range(chi) for b in range(chi) if a == chi - 1 or b == chi - 1]
+    A[null, :] = 0.0
+    A[:, null] = 0.0
+    return 0.5 * (A + A.T)
+
+
+@pytest.mark.parametrize("case", ["near_tridiagonal_1e-10", "near_tridiagonal_1e-11", "gram_null_index"])
+def test_eigh_structured_matrices(case):
+    """Matrices whose Householder columns have a dominant subdiagonal entry and a tail below
+    sqrt(u) of it (the tail norm must not be taken by cancellation), and a Gram matrix with
+    exactly zero rows and columns."""
+    n = 256
+    if case.startswith("near"):
+        A = _near_tridiagonal(n, float(case.split("_")[-1]), seed=7)
+    else:
+        A = _gram_with_null_index(16, seed=11)
+    w, V = gu.eigh(A[None].copy())
+    ref = np.sort(np.linalg.eigvalsh(A))[::-1]
+    err = np.max(np.abs(w[0] - ref)) / abs(ref[0])
+    print(f"{case}: max |dlambda| / |lambda_0| = {err:.2e}")
+    assert err <= 2 * n * 2.0 ** -52
+    R = A @ V[0] - V[0] * w[0][None, :]
+    assert np.linalg.norm(R) < 1e-13 * abs(ref[0]) * n
+    assert np.linalg.norm(V[0].T @ V[0] - np.eye(n)) < 1e-13 * n
