@@ -206,6 +206,58 @@ size_t hotrg_debug_eigh_workspace_bytes(int n, int batch);
 int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_dev,
                      void* workspace_dev, size_t workspace_bytes, void* hip_stream);
 
+/* ---- batched runs: a sweep of independent instances (models, beta, chi) --------------
+ * The same coarse-graining step (Sections 3-4) applied to many independent runs, e.g. a
+ * temperature sweep with mixed d and chi.  hotrg_batch_step advances every instance by one
+ * step along its natural axis cycle (0, 1, .., d-1, 0, ..): the records and Gram matrices of
+ * all instances, ONE eigensolver launch over all their Gram matrices, then choice,
+ * contraction, trace and normalisation of each instance.  Once every instance has reached
+ * dims that a step no longer changes, the step is recorded into a HIP graph (two graphs, for
+ * the alternating tensor buffers; the step counter lives on the device) and each later step
+ * is one graph launch.  Recording needs a non-NULL stream; on the NULL stream every step is
+ * enqueued kernel by kernel.
+ * Memory: one caller-owned workspace (256-byte aligned) holding every instance's state and
+ * one scratch area sized for the largest instance (instances run one after the other on
+ * the stream).  opts applies to all instances; record_grad must be 0. */
+typedef struct {
+    hotrg_model model;
+    double beta;
+    int chi;
+    int pad;
+} hotrg_instance;
+
+typedef struct hotrg_batch hotrg_batch;
+
+/* Workspace bytes for the batch, 0 if an instance or opts is invalid. */
+size_t hotrg_batch_workspace_bytes(const hotrg_instance* inst, int n, const hotrg_opts* opts);
+
+/* Builds every instance's initial tensor on `hip_stream` (asynchronous).  Errors as
+ * hotrg_init (checked per instance), plus HOTRG_E_ARG for n < 1 or record_grad != 0. */
+int hotrg_batch_init(const hotrg_instance* inst, int n, const hotrg_opts* opts, void* workspace,
+                     size_t workspace_bytes, void* hip_stream, hotrg_batch** out);
+
+/* One step of every instance (enqueue only; the first steps with new dims may upload an
+ * eigensolver descriptor table).  Errors: HOTRG_E_ARG, HOTRG_E_STATE (failed, or max_steps
+ * reached), HOTRG_E_DEVICE. */
+int hotrg_batch_step(hotrg_batch* b);
+
+/* Synchronise; lnZ/V of every instance into lnz_per_site[n]; steps done into *steps_done
+ * (may be NULL).  Device errors of any instance surface here (HOTRG_E_NUMERIC, ...). */
+int hotrg_batch_log_z(hotrg_batch* b, double* lnz_per_site, int* steps_done);
+
+/* Steps run as graph launches and steps enqueued kernel by kernel so far. */
+int hotrg_batch_info(hotrg_batch* b, int* graph_launches, int* eager_steps);
+
+/* Instance i as a handle for the read-only queries (hotrg_step_info, hotrg_spectrum,
+ * hotrg_log_z); it must not be stepped or destroyed.  NULL if i is out of range. */
+hotrg_handle* hotrg_batch_instance(hotrg_batch* b, int i);
+
+/* Idempotent on NULL. */
+void hotrg_batch_destroy(hotrg_batch* b);
+
+/* Message of the last error of b (NULL: of the last failed hotrg_batch_init). */
+const char* hotrg_batch_last_error(const hotrg_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -55,6 +55,10 @@ class hotrg_timing(ctypes.Structure):
                 ("flops_bottleneck", ctypes.c_double), ("flops_contract", ctypes.c_double)]
 
 
+class hotrg_instance(ctypes.Structure):
+    _fields_ = [("model", hotrg_model), ("beta", ctypes.c_double), ("chi", ctypes.c_int), ("pad", ctypes.c_int)]
+
+
 class HotrgError(RuntimeError):
     def __init__(self, code: int, message: str):
         super().__init__(f"hotrg error {code}: {message}")
@@ -87,6 +91,18 @@ _SIGS = {
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p]),
     "hotrg_debug_eigh_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+    "hotrg_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(hotrg_instance), ctypes.c_int,
+                                                      ctypes.POINTER(hotrg_opts)]),
+    "hotrg_batch_init": (ctypes.c_int, [ctypes.POINTER(hotrg_instance), ctypes.c_int, ctypes.POINTER(hotrg_opts),
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "hotrg_batch_step": (ctypes.c_int, [ctypes.c_void_p]),
+    "hotrg_batch_log_z": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int)]),
+    "hotrg_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "hotrg_batch_instance": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.c_int]),
+    "hotrg_batch_destroy": (None, [ctypes.c_void_p]),
+    "hotrg_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "hotrg_debug_eigh": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
 }
@@ -215,6 +231,59 @@ def hotrg_debug_eigh(n, batch, A_ptr, w_ptr, V_ptr, ws_ptr, ws_bytes, stream_ptr
     _check(rc, None)
 
 
+def _check_batch(rc: int, b=None):
+    if rc != HOTRG_OK:
+        msg = lib().hotrg_batch_last_error(b)
+        raise HotrgError(rc, msg.decode() if msg else "")
+
+
+def _instances(inst):
+    arr = (hotrg_instance * len(inst))(*inst)
+    return arr
+
+
+def hotrg_batch_workspace_bytes(inst, opts: hotrg_opts) -> int:
+    return lib().hotrg_batch_workspace_bytes(_instances(inst), len(inst), ctypes.byref(opts))
+
+
+def hotrg_batch_init(inst, opts: hotrg_opts, workspace_ptr: int, workspace_bytes: int, stream_ptr: int):
+    b = ctypes.c_void_p()
+    rc = lib().hotrg_batch_init(_instances(inst), len(inst), ctypes.byref(opts), ctypes.c_void_p(workspace_ptr),
+                                workspace_bytes, ctypes.c_void_p(stream_ptr), ctypes.byref(b))
+    _check_batch(rc, None)
+    return b
+
+
+def hotrg_batch_step(b) -> None:
+    _check_batch(lib().hotrg_batch_step(b), b)
+
+
+def hotrg_batch_log_z(b, n: int):
+    out = (ctypes.c_double * n)()
+    steps = ctypes.c_int()
+    _check_batch(lib().hotrg_batch_log_z(b, out, ctypes.byref(steps)), b)
+    return [out[i] for i in range(n)], steps.value
+
+
+def hotrg_batch_info(b):
+    g, e = ctypes.c_int(), ctypes.c_int()
+    _check_batch(lib().hotrg_batch_info(b, ctypes.byref(g), ctypes.byref(e)), b)
+    return g.value, e.value
+
+
+def hotrg_batch_instance(b, i: int):
+    return ctypes.c_void_p(lib().hotrg_batch_instance(b, i))
+
+
+def hotrg_batch_destroy(b) -> None:
+    lib().hotrg_batch_destroy(b)
+
+
+def hotrg_batch_last_error(b=None) -> str:
+    m = lib().hotrg_batch_last_error(b)
+    return m.decode() if m else ""
+
+
 # ---- convenience wrapper (torch for memory and the stream) ----------------------
 
 class HOTRG:
@@ -313,3 +382,72 @@ def lnz_per_site(beta, kind: str = "ising", d: int = 3, chi: int = 16, steps: in
             return g * ctx.der
 
     return _LnZ.apply(beta)
+
+
+def make_instance(kind: str, d: int, beta: float, chi: int, q: int | None = None, J: float = 1.0,
+                  h: float = 0.0) -> hotrg_instance:
+    kind_id = {"ising": HOTRG_ISING, "potts": HOTRG_POTTS}[kind]
+    q = 2 if kind == "ising" else (3 if q is None else q)
+    return hotrg_instance(hotrg_model(kind_id, d, q, J, h), beta, chi, 0)
+
+
+class HOTRGBatch:
+    """Many independent HOTRG runs advanced together (a temperature sweep, mixed d and chi).
+
+    Runs on a stream of its own (default priority) so that the saturated steps can be
+    recorded into HIP graphs and replayed with one launch per step.
+
+    >>> b = HOTRGBatch([make_instance("ising", 3, 1 / T, 12) for T in (4.0, 4.5, 5.0)], precision="split_fp16")
+    >>> b.run(20); b.log_z()
+    """
+
+    def __init__(self, instances, precision: str = "fp64", max_steps: int = 64, chunk: int = 0):
+        import torch
+
+        self.instances = list(instances)
+        self.n = len(self.instances)
+        self.opts = hotrg_opts(FORMS[precision], max_steps, chunk, 0)
+        nbytes = hotrg_batch_workspace_bytes(self.instances, self.opts)
+        if nbytes == 0:
+            raise HotrgError(HOTRG_E_ARG, "invalid instance or options")
+        self.workspace_bytes = nbytes
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.Stream()
+        # the workspace was allocated on the current stream: make ours wait for that
+        self.stream.wait_stream(torch.cuda.current_stream())
+        self.handle = hotrg_batch_init(self.instances, self.opts, aligned, nbytes, self.stream.cuda_stream)
+        self.steps = 0
+
+    def step(self) -> None:
+        hotrg_batch_step(self.handle)
+        self.steps += 1
+
+    def run(self, steps: int) -> None:
+        for _ in range(steps):
+            self.step()
+
+    def log_z(self):
+        return hotrg_batch_log_z(self.handle, self.n)[0]
+
+    def info(self, i: int, step: int) -> hotrg_step_record:
+        return hotrg_step_info(hotrg_batch_instance(self.handle, i), step)
+
+    def graph_stats(self):
+        """(steps run as one graph launch, steps enqueued kernel by kernel)."""
+        return hotrg_batch_info(self.handle)
+
+    def synchronize(self) -> None:
+        self.stream.synchronize()
+
+    def close(self) -> None:
+        if self.handle is not None:
+            self.stream.synchronize()
+            hotrg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

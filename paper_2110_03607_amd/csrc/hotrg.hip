@@ -168,8 +168,8 @@ struct Plan {
   int max_steps;
 };
 
-Plan make_plan(int d, int q, int chi, int form, int user_chunk, int max_steps, bool grad = false) {
-  Plan P{};
+// Maximum needs over every bond-dimension combination a run can reach.
+Need plan_need(int d, int q, int chi, int form, int user_chunk, bool grad) {
   Need nd{};
   const std::vector<int> vals = reachable_dims(q, chi);
   LocalDims ld;
@@ -182,40 +182,66 @@ Plan make_plan(int d, int q, int chi, int form, int user_chunk, int max_steps, b
     for (int i = 0; i < d; ++i) { ld.chi[i] = vals[r % nv]; r /= nv; }
     need_max(nd, need_for(ld, chi, form, user_chunk, grad));
   }
+  return nd;
+}
+
+inline size_t take_at(size_t& o, size_t bytes) {
+  const size_t r = o;
+  o = roundup(o + bytes, ALIGN);
+  return r;
+}
+
+// Regions that hold one run's state from step to step: device state and step records
+// (contiguous, cleared at init), the tensor pair, the Gram matrices and eigenvectors, the
+// isometries, and the derivative copies.
+void place_private(Plan& P, size_t& o, const Need& nd, int max_steps, bool grad) {
+  P.off_state = take_at(o, sizeof(DevState));
+  P.off_rec = take_at(o, sizeof(StepRec) * (size_t)(max_steps + 1));
+  P.off_T = take_at(o, nd.T);
+  P.off_Tn = take_at(o, nd.T);
+  P.off_A = take_at(o, EIG_SLOTS * nd.Amat);
+  P.off_Vw = take_at(o, EIG_SLOTS * 2 * nd.Amat);
+  P.off_Vo = take_at(o, EIG_SLOTS * nd.Amat);
+  P.off_w = take_at(o, EIG_SLOTS * nd.w);
+  P.off_Ut = take_at(o, MAXD * nd.Ut);
+  P.off_Ut32 = take_at(o, MAXD * nd.Ut / 2 + 64);
+  if (grad) {
+    P.off_dT = take_at(o, nd.T);
+    P.off_dTn = take_at(o, nd.T);
+    P.off_dA = take_at(o, EIG_SLOTS * nd.Amat);
+    P.off_dUt = take_at(o, MAXD * nd.Ut);
+    P.off_dUt32 = take_at(o, MAXD * nd.Ut / 2 + 64);
+  }
+}
+
+// Scratch used only inside one step (operands, products, Gram pieces): runs that execute
+// one after the other on the same stream may share it.
+void place_scratch(Plan& P, size_t& o, const Need& nd, bool grad) {
+  P.off_Aop = take_at(o, nd.Aop);
+  P.off_Bop = take_at(o, nd.Bop);
+  P.off_Cc = take_at(o, nd.Cc);
+  P.off_X = take_at(o, nd.X);
+  P.off_part = take_at(o, nd.part);
+  P.off_Gh = take_at(o, nd.G);
+  P.off_Gc = take_at(o, nd.G);
+  if (grad) {
+    P.off_dCc = take_at(o, nd.Cc);
+    P.off_Xd = take_at(o, nd.X);
+    P.off_dGh = take_at(o, nd.G);
+    P.off_dGc = take_at(o, nd.G);
+    P.off_dUw = take_at(o, 2 * nd.Amat);   // k_dU: W = dA U_kept and the coefficients U^T W
+  }
+}
+
+Plan make_plan(int d, int q, int chi, int form, int user_chunk, int max_steps, bool grad = false) {
+  Plan P{};
+  const Need nd = plan_need(d, q, chi, form, user_chunk, grad);
   P.need = nd;
   P.max_steps = max_steps;
   P.grad = grad;
   size_t o = 0;
-  auto take = [&](size_t bytes) { size_t r = o; o = roundup(o + bytes, ALIGN); return r; };
-  P.off_state = take(sizeof(DevState));
-  P.off_rec = take(sizeof(StepRec) * (size_t)(max_steps + 1));
-  P.off_T = take(nd.T);
-  P.off_Tn = take(nd.T);
-  P.off_Aop = take(nd.Aop);
-  P.off_Bop = take(nd.Bop);
-  P.off_Cc = take(nd.Cc);
-  P.off_X = take(nd.X);
-  P.off_part = take(nd.part);
-  P.off_Gh = take(nd.G);
-  P.off_Gc = take(nd.G);
-  P.off_A = take(EIG_SLOTS * nd.Amat);
-  P.off_Vw = take(EIG_SLOTS * 2 * nd.Amat);
-  P.off_Vo = take(EIG_SLOTS * nd.Amat);
-  P.off_w = take(EIG_SLOTS * nd.w);
-  P.off_Ut = take(MAXD * nd.Ut);
-  P.off_Ut32 = take(MAXD * nd.Ut / 2 + 64);
-  if (grad) {
-    P.off_dT = take(nd.T);
-    P.off_dTn = take(nd.T);
-    P.off_dCc = take(nd.Cc);
-    P.off_Xd = take(nd.X);
-    P.off_dGh = take(nd.G);
-    P.off_dGc = take(nd.G);
-    P.off_dA = take(EIG_SLOTS * nd.Amat);
-    P.off_dUt = take(MAXD * nd.Ut);
-    P.off_dUt32 = take(MAXD * nd.Ut / 2 + 64);
-    P.off_dUw = take(2 * nd.Amat);   // k_dU: W = dA U_kept and the kept x discarded coefficients
-  }
+  place_private(P, o, nd, max_steps, grad);
+  place_scratch(P, o, nd, grad);
   P.total = o;
   return P;
 }
@@ -267,6 +293,30 @@ struct hotrg_handle {
   template <class X> X* at(size_t off) { return reinterpret_cast<X*>(ws + off); }
   DevState* st() { return at<DevState>(plan.off_state); }
   StepRec* rec(int step) { return at<StepRec>(plan.off_rec) + step; }
+};
+
+struct hotrg_batch {
+  int n = 0;
+  hotrg_opts opts{};
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t s = nullptr;
+  std::vector<hotrg_handle*> inst;
+  // eigensolver descriptor tables, one per distinct dims signature of a step
+  size_t off_tables = 0;
+  int table_cap = 0;                       // descriptors per table
+  int n_tables = 0;                        // table slots in the workspace
+  struct Table { std::vector<EigDesc> key; int slot; };
+  std::vector<Table> tables;
+  int next_slot = 0;
+  // recorded steps: one graph per parity of the step (the tensor buffers alternate)
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  bool use_graphs = true;
+  int p = 0;
+  int graph_launches = 0, eager_steps = 0;
+  bool failed = false;
+  std::string err;
+  template <class X> X* at(size_t off) { return reinterpret_cast<X*>(ws + off); }
 };
 
 namespace {
@@ -627,37 +677,57 @@ int enqueue_contract(hotrg_handle* h, const void* T, void* Tn, const LocalDims& 
   return fail(h, HOTRG_E_ARG, "bad precision form");
 }
 
-// Gram matrices of every truncated direction, one eigensolver launch over all of them,
-// then the choice / truncation of U^(j) per direction (untruncated: identity).
-int enqueue_decomposition(hotrg_handle* h, const void* T, const LocalDims& ld, const int* k, StepRec* rec,
-                          const void* dT = nullptr) {
-  const int d = ld.d;
-  const size_t ut_stride = h->plan.need.Ut / 8;
+// Eigensolver work of one step: one descriptor per Gram matrix of a truncated direction
+// (slot = 2 (j - 1) + side).  Host-side only: the descriptors depend on the dims alone.
+int collect_eig(hotrg_handle* h, const LocalDims& ld, EigDesc* out) {
   const size_t am = h->plan.need.Amat / 8, wn = h->plan.need.w / 8;
-  double* Am = h->at<double>(h->plan.off_A);
-  double* Vw = h->at<double>(h->plan.off_Vw);
-  double* Vo = h->at<double>(h->plan.off_Vo);
-  double* w = h->at<double>(h->plan.off_w);
-  EigBatch eb{};
-  for (int j = 1; j < d; ++j) {
+  int count = 0;
+  for (int j = 1; j < ld.d; ++j) {
+    const int n = ld.chi[j] * ld.chi[j];
+    if (n <= h->chi) continue;
+    const int kj = std::min(n, h->chi);
+    for (int side = 0; side < 2; ++side) {
+      const int slot = (j - 1) * 2 + side;
+      EigDesc e;
+      e.n = n;
+      e.kvec = h->grad ? n : kj;   // the derivative needs the discarded eigenvectors too
+      e.A = h->at<double>(h->plan.off_A) + slot * am;
+      e.w = h->at<double>(h->plan.off_w) + slot * wn;
+      e.V = h->at<double>(h->plan.off_Vo) + slot * am;
+      e.scratch = h->at<double>(h->plan.off_Vw) + slot * 2 * am;
+      out[count++] = e;
+    }
+  }
+  return count;
+}
+
+// Gram matrices (and their derivatives) of every truncated direction, into the slots of
+// collect_eig.
+int enqueue_grams(hotrg_handle* h, const void* T, const LocalDims& ld, const void* dT) {
+  const size_t am = h->plan.need.Amat / 8;
+  for (int j = 1; j < ld.d; ++j) {
     const int n = ld.chi[j] * ld.chi[j];
     if (n <= h->chi) continue;
     for (int side = 0; side < 2; ++side) {
       const int slot = (j - 1) * 2 + side;
-      int rc = enqueue_gram(h, T, h->form == HOTRG_FP64, ld, j, side, Am + slot * am, dT,
+      int rc = enqueue_gram(h, T, h->form == HOTRG_FP64, ld, j, side, h->at<double>(h->plan.off_A) + slot * am, dT,
                             dT ? h->at<double>(h->plan.off_dA) + slot * am : nullptr);
       if (rc) return rc;
-      const int b = eb.count++;
-      eb.n[b] = n;
-      eb.kvec[b] = dT ? n : k[j - 1];   // the derivative needs the discarded eigenvectors too
-      eb.A[b] = Am + slot * am;
-      eb.w[b] = w + slot * wn;
-      eb.V[b] = Vo + slot * am;
-      eb.scratch[b] = Vw + slot * 2 * am;
     }
   }
-  if (eb.count > 0)
-    hipLaunchKernelGGL(k_eigh_tri, dim3(eb.count), dim3(EIG_THREADS), 0, h->s, eb);
+  return HOTRG_OK;
+}
+
+// Choice and truncation of U^(j) per direction (untruncated: identity), after the
+// eigensolver; in derivative mode also dU^(j).
+int enqueue_choose(hotrg_handle* h, const LocalDims& ld, const int* k, const void* dT) {
+  const int d = ld.d;
+  const size_t ut_stride = h->plan.need.Ut / 8;
+  const size_t am = h->plan.need.Amat / 8, wn = h->plan.need.w / 8;
+  double* Vo = h->at<double>(h->plan.off_Vo);
+  double* w = h->at<double>(h->plan.off_w);
+  StepRec* rec_base = h->rec(0);
+  DevState* st = h->st();
   for (int j = 1; j < d; ++j) {
     const int n = ld.chi[j] * ld.chi[j];
     double* Ut = h->at<double>(h->plan.off_Ut) + (size_t)(j - 1) * ut_stride;
@@ -665,7 +735,8 @@ int enqueue_decomposition(hotrg_handle* h, const void* T, const LocalDims& ld, c
     const int s0 = (j - 1) * 2, s1 = s0 + 1;
     hipLaunchKernelGGL(k_choose, dim3(1), dim3(256), 0, h->s, (const double*)(w + s0 * wn),
                        (const double*)(w + s1 * wn), (const double*)(Vo + s0 * am), (const double*)(Vo + s1 * am),
-                       n, k[j - 1], n <= h->chi ? 1 : 0, multiplet_tau(h->form), Ut, Ut32, rec, j - 1);
+                       n, k[j - 1], n <= h->chi ? 1 : 0, multiplet_tau(h->form), Ut, Ut32, rec_base,
+                       (const DevState*)st, j - 1);
     if (dT) {
       double* dUt = h->at<double>(h->plan.off_dUt) + (size_t)(j - 1) * ut_stride;
       float* dUt32 = h->at<float>(h->plan.off_dUt32) + (size_t)(j - 1) * ut_stride;
@@ -678,8 +749,8 @@ int enqueue_decomposition(hotrg_handle* h, const void* T, const LocalDims& ld, c
         hipLaunchKernelGGL(k_dU, dim3(1), dim3(256), 0, h->s, (const double*)(w + s0 * wn),
                            (const double*)(w + s1 * wn), (const double*)(Vo + s0 * am),
                            (const double*)(Vo + s1 * am), (const double*)(dAm + s0 * am),
-                           (const double*)(dAm + s1 * am), n, k[j - 1], (const StepRec*)rec, j - 1, scr, scr + am,
-                           dUt, dUt32);
+                           (const double*)(dAm + s1 * am), n, k[j - 1], (const StepRec*)rec_base,
+                           (const DevState*)st, j - 1, scr, scr + am, dUt, dUt32);
       }
     }
   }
@@ -738,6 +809,106 @@ int enqueue_relayout(hotrg_handle* h, int axis) {
   return HOTRG_OK;
 }
 
+// Dims of the step about to run with the current layout, and after it (renamed:
+// c^bar = n_1, n^bar_j = n_{j+1}, n^bar_{d-1} = c).
+struct StepPlan {
+  LocalDims ld, nl;
+  int k[MAXD];
+  long Hn;
+};
+
+StepPlan step_plan(const hotrg_handle* h) {
+  StepPlan sp{};
+  sp.ld = h->ld;
+  const int d = sp.ld.d;
+  for (int j = 1; j < d; ++j) sp.k[j - 1] = std::min(sp.ld.chi[j] * sp.ld.chi[j], h->chi);
+  sp.nl.d = d;
+  for (int j = 1; j < d; ++j) sp.nl.chi[j - 1] = sp.k[j - 1];
+  sp.nl.chi[d - 1] = sp.ld.chi[0];
+  sp.Hn = 1;
+  for (int i = 0; i < d; ++i) sp.Hn *= sp.nl.chi[i];
+  return sp;
+}
+
+bool same_dims(const LocalDims& a, const LocalDims& b) {
+  if (a.d != b.d) return false;
+  for (int i = 0; i < a.d; ++i)
+    if (a.chi[i] != b.chi[i]) return false;
+  return true;
+}
+
+// First half of a step: its record and the Gram matrices.  axis_rec < 0 records the
+// natural cycle (computed on the device from the step counter).
+int enqueue_step_front(hotrg_handle* h, int axis_rec) {
+  const LocalDims& ld = h->ld;
+  hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(256), 0, h->s, h->rec(0), (const DevState*)h->st(), axis_rec, ld.d,
+                     ld.chi[0], ld.chi[1], ld.d == 3 ? ld.chi[2] : 0);
+  void* dT = h->grad ? h->at<void>(h->plan.off_dT) : nullptr;
+  return enqueue_grams(h, h->at<void>(h->plan.off_T), ld, dT);
+}
+
+// Second half (after the eigensolver): choice and truncation, the new tensor, trace,
+// lnZ/V and normalisation.  Host state is not touched (advance_host does that).
+int enqueue_step_back(hotrg_handle* h, const StepPlan& sp, hipEvent_t t_dec) {
+  void* T = h->at<void>(h->plan.off_T);
+  void* Tn = h->at<void>(h->plan.off_Tn);
+  void* dT = h->grad ? h->at<void>(h->plan.off_dT) : nullptr;
+  void* dTn = h->grad ? h->at<void>(h->plan.off_dTn) : nullptr;
+  int rc = enqueue_choose(h, sp.ld, sp.k, dT);
+  if (rc) return rc;
+  tclose(h, HOTRG_T_DECOMP, t_dec);
+  if (!h->grad)
+    rc = enqueue_contract(h, T, Tn, sp.ld, sp.k);
+  else if (h->form == HOTRG_FP64)
+    rc = enqueue_contract_grad<F_FP64>(h, T, Tn, dT, dTn, sp.ld, sp.k);
+  else
+    rc = enqueue_contract_grad<F_FP32>(h, T, Tn, dT, dTn, sp.ld, sp.k);
+  if (rc) return rc;
+  DevState* st = h->st();
+  const long Hn = sp.Hn;
+  const int chic = sp.ld.chi[0];
+  hipEvent_t t_tr = tmark(h);
+  if (h->form == HOTRG_FP64) {
+    hipLaunchKernelGGL((k_trace_lnz<double>), dim3(1), dim3(256), 0, h->s, (const double*)Tn, (int)Hn, chic, st,
+                       h->rec(0));
+    if (h->grad)
+      hipLaunchKernelGGL((k_trace_t<double>), dim3(1), dim3(256), 0, h->s, (const double*)dTn, (int)Hn, st);
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, h->s, st);
+    if (h->grad)
+      hipLaunchKernelGGL((k_scale_t<double>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (double*)Tn,
+                         (double*)dTn, Hn * Hn, st);
+    else
+      hipLaunchKernelGGL((k_scale<double>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (double*)Tn, Hn * Hn, st);
+  } else {
+    hipLaunchKernelGGL((k_trace_lnz<float>), dim3(1), dim3(256), 0, h->s, (const float*)Tn, (int)Hn, chic, st,
+                       h->rec(0));
+    if (h->grad)
+      hipLaunchKernelGGL((k_trace_t<float>), dim3(1), dim3(256), 0, h->s, (const float*)dTn, (int)Hn, st);
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, h->s, st);
+    if (h->grad)
+      hipLaunchKernelGGL((k_scale_t<float>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (float*)Tn, (float*)dTn,
+                         Hn * Hn, st);
+    else
+      hipLaunchKernelGGL((k_scale<float>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (float*)Tn, Hn * Hn, st);
+  }
+  tclose(h, HOTRG_T_TRACE, t_tr);
+  HIPCHK(h, hipGetLastError());
+  return HOTRG_OK;
+}
+
+// Host bookkeeping of a step that was enqueued (or replayed): tensor buffers swap, the
+// slots rotate to the next Current axis, dims and step count advance.
+void advance_host(hotrg_handle* h, const StepPlan& sp) {
+  std::swap(h->plan.off_T, h->plan.off_Tn);
+  if (h->grad) std::swap(h->plan.off_dT, h->plan.off_dTn);
+  const int d = sp.ld.d;
+  int na[MAXD];
+  for (int i = 0; i < d; ++i) na[i] = h->axes[(i + 1) % d];
+  for (int i = 0; i < d; ++i) h->axes[i] = na[i];
+  h->ld = sp.nl;
+  h->p += 1;
+}
+
 int sync_state(hotrg_handle* h, DevState* out) {
   HIPCHK(h, hipStreamSynchronize(h->s));
   HIPCHK(h, hipMemcpy(out, h->st(), sizeof(DevState), hipMemcpyDeviceToHost));
@@ -781,10 +952,7 @@ size_t hotrg_workspace_bytes(const hotrg_model* model, int chi, const hotrg_opts
       .total;
 }
 
-int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts* opts, void* workspace,
-               size_t ws_bytes, void* stream, hotrg_handle** out) {
-  if (!out) return fail(nullptr, HOTRG_E_ARG, "out is NULL");
-  *out = nullptr;
+static int check_init_args(const hotrg_model* model, double beta, int chi, const hotrg_opts* opts) {
   if (!opts || !model) return fail(nullptr, HOTRG_E_ARG, "model or opts is NULL");
   if (check_model(model, chi) != HOTRG_OK) return fail(nullptr, HOTRG_E_ARG, "invalid model or chi");
   if (!form_valid(opts->precision) || opts->max_steps < 1 || opts->chunk < 0 || opts->record_grad < 0 ||
@@ -797,10 +965,13 @@ int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts*
   if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(nullptr, HOTRG_E_ARG, "beta must be finite and >= 0");
   // W must be positive semi-definite: Ising needs sinh(beta J) >= 0, Potts e^{beta J} - 1 >= 0
   if (beta * model->J < 0.0) return fail(nullptr, HOTRG_E_NOT_PSD, "bond weight matrix is not PSD (J < 0)");
-  if (!workspace) return fail(nullptr, HOTRG_E_ARG, "workspace is NULL");
-  Plan P = make_plan(model->d, model->q, chi, opts->precision, opts->chunk, opts->max_steps, opts->record_grad != 0);
-  if (ws_bytes < P.total) return fail(nullptr, HOTRG_E_OOM, "workspace too small");
-  if (((uintptr_t)workspace) % ALIGN) return fail(nullptr, HOTRG_E_ARG, "workspace must be 256-byte aligned");
+  return HOTRG_OK;
+}
+
+// A handle over `workspace` with the given plan: clears its state and records, builds the
+// initial tensor (asynchronous, on `stream`).  Returns null with g_static_err set on error.
+static hotrg_handle* new_handle(const hotrg_model* model, double beta, int chi, const hotrg_opts* opts,
+                                void* workspace, size_t ws_bytes, void* stream, const Plan& P) {
   hotrg_handle* h = new hotrg_handle();
   h->model = *model;
   h->opts = *opts;
@@ -814,7 +985,7 @@ int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts*
   h->grad = opts->record_grad != 0;
   h->ld.d = model->d;
   for (int i = 0; i < model->d; ++i) { h->ld.chi[i] = model->q; h->axes[i] = i; }
-  hipError_t e = hipMemsetAsync(h->ws, 0, P.off_T, h->s);   // state + records
+  hipError_t e = hipMemsetAsync(h->ws + P.off_state, 0, P.off_T - P.off_state, h->s);   // state + records
   if (e == hipSuccess) {
     if (h->form == HOTRG_FP64)
       hipLaunchKernelGGL((k_init_tensor<double>), dim3(1), dim3(256), 0, h->s, h->at<double>(P.off_T),
@@ -829,8 +1000,23 @@ int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts*
   if (e != hipSuccess) {
     g_static_err = std::string("device error in hotrg_init: ") + hipGetErrorString(e);
     delete h;
-    return HOTRG_E_DEVICE;
+    return nullptr;
   }
+  return h;
+}
+
+int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts* opts, void* workspace,
+               size_t ws_bytes, void* stream, hotrg_handle** out) {
+  if (!out) return fail(nullptr, HOTRG_E_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = check_init_args(model, beta, chi, opts);
+  if (rc) return rc;
+  if (!workspace) return fail(nullptr, HOTRG_E_ARG, "workspace is NULL");
+  Plan P = make_plan(model->d, model->q, chi, opts->precision, opts->chunk, opts->max_steps, opts->record_grad != 0);
+  if (ws_bytes < P.total) return fail(nullptr, HOTRG_E_OOM, "workspace too small");
+  if (((uintptr_t)workspace) % ALIGN) return fail(nullptr, HOTRG_E_ARG, "workspace must be 256-byte aligned");
+  hotrg_handle* h = new_handle(model, beta, chi, opts, workspace, ws_bytes, stream, P);
+  if (!h) return HOTRG_E_DEVICE;
   *out = h;
   return HOTRG_OK;
 }
@@ -843,75 +1029,25 @@ int hotrg_step(hotrg_handle* h, int axis) {
   hipEvent_t t_step = tmark(h);
   int rc = enqueue_relayout(h, axis);
   if (rc) return rc;
-  const int d = h->ld.d;
-  const LocalDims ld = h->ld;
-  int k[MAXD];
-  for (int j = 1; j < d; ++j) k[j - 1] = std::min(ld.chi[j] * ld.chi[j], h->chi);
-  const int p = h->p + 1;
-  StepRec* rec = h->rec(p - 1);
-  hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(256), 0, h->s, rec, p, axis, d, ld.chi[0], ld.chi[1],
-                     d == 3 ? ld.chi[2] : 0);
-  void* T = h->at<void>(h->plan.off_T);
-  void* Tn = h->at<void>(h->plan.off_Tn);
-  void* dT = h->grad ? h->at<void>(h->plan.off_dT) : nullptr;
-  void* dTn = h->grad ? h->at<void>(h->plan.off_dTn) : nullptr;
+  const StepPlan sp = step_plan(h);
   hipEvent_t t_dec = tmark(h);
-  rc = enqueue_decomposition(h, T, ld, k, rec, dT);
+  EigDesc eig[EIG_SLOTS];
+  const int ne = collect_eig(h, sp.ld, eig);
+  rc = enqueue_step_front(h, axis);
   if (rc) return rc;
-  tclose(h, HOTRG_T_DECOMP, t_dec);
-  if (!h->grad)
-    rc = enqueue_contract(h, T, Tn, ld, k);
-  else if (h->form == HOTRG_FP64)
-    rc = enqueue_contract_grad<F_FP64>(h, T, Tn, dT, dTn, ld, k);
-  else
-    rc = enqueue_contract_grad<F_FP32>(h, T, Tn, dT, dTn, ld, k);
-  if (rc) return rc;
-  // new dims after renaming: c^bar = n_1, n^bar_j = n_{j+1}, n^bar_{d-1} = c
-  LocalDims nl;
-  nl.d = d;
-  for (int j = 1; j < d; ++j) nl.chi[j - 1] = k[j - 1];
-  nl.chi[d - 1] = ld.chi[0];
-  long Hn = 1;
-  for (int i = 0; i < d; ++i) Hn *= nl.chi[i];
-  DevState* st = h->st();
-  hipEvent_t t_tr = tmark(h);
-  if (h->grad) {
-    if (h->form == HOTRG_FP64) {
-      hipLaunchKernelGGL((k_trace_lnz<double>), dim3(1), dim3(256), 0, h->s, (const double*)Tn, (int)Hn, ld.chi[0],
-                         st, rec, p);
-      hipLaunchKernelGGL((k_trace_t<double>), dim3(1), dim3(256), 0, h->s, (const double*)dTn, (int)Hn, st, p);
-      hipLaunchKernelGGL(k_reset_maxabs, dim3(1), dim3(1), 0, h->s, st);
-      hipLaunchKernelGGL((k_scale_t<double>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (double*)Tn,
-                         (double*)dTn, Hn * Hn, st);
-    } else {
-      hipLaunchKernelGGL((k_trace_lnz<float>), dim3(1), dim3(256), 0, h->s, (const float*)Tn, (int)Hn, ld.chi[0],
-                         st, rec, p);
-      hipLaunchKernelGGL((k_trace_t<float>), dim3(1), dim3(256), 0, h->s, (const float*)dTn, (int)Hn, st, p);
-      hipLaunchKernelGGL(k_reset_maxabs, dim3(1), dim3(1), 0, h->s, st);
-      hipLaunchKernelGGL((k_scale_t<float>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (float*)Tn, (float*)dTn,
-                         Hn * Hn, st);
+  if (ne > 0) {
+    EigBatch eb{};
+    eb.count = ne;
+    for (int i = 0; i < ne; ++i) {
+      eb.n[i] = eig[i].n; eb.kvec[i] = eig[i].kvec; eb.A[i] = eig[i].A; eb.w[i] = eig[i].w;
+      eb.V[i] = eig[i].V; eb.scratch[i] = eig[i].scratch;
     }
-  } else if (h->form == HOTRG_FP64) {
-    hipLaunchKernelGGL((k_trace_lnz<double>), dim3(1), dim3(256), 0, h->s, (const double*)Tn, (int)Hn, ld.chi[0],
-                       st, rec, p);
-    hipLaunchKernelGGL(k_reset_maxabs, dim3(1), dim3(1), 0, h->s, st);
-    hipLaunchKernelGGL((k_scale<double>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (double*)Tn, Hn * Hn, st);
-  } else {
-    hipLaunchKernelGGL((k_trace_lnz<float>), dim3(1), dim3(256), 0, h->s, (const float*)Tn, (int)Hn, ld.chi[0],
-                       st, rec, p);
-    hipLaunchKernelGGL(k_reset_maxabs, dim3(1), dim3(1), 0, h->s, st);
-    hipLaunchKernelGGL((k_scale<float>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (float*)Tn, Hn * Hn, st);
+    hipLaunchKernelGGL(k_eigh_tri, dim3(ne), dim3(EIG_THREADS), 0, h->s, eb);
   }
-  tclose(h, HOTRG_T_TRACE, t_tr);
+  rc = enqueue_step_back(h, sp, t_dec);
+  if (rc) return rc;
   tclose(h, HOTRG_T_STEP, t_step);
-  HIPCHK(h, hipGetLastError());
-  std::swap(h->plan.off_T, h->plan.off_Tn);
-  if (h->grad) std::swap(h->plan.off_dT, h->plan.off_dTn);
-  int na[MAXD];
-  for (int i = 0; i < d; ++i) na[i] = h->axes[(i + 1) % d];
-  for (int i = 0; i < d; ++i) h->axes[i] = na[i];
-  h->ld = nl;
-  h->p = p;
+  advance_host(h, sp);
   return HOTRG_OK;
 }
 
@@ -1203,6 +1339,250 @@ int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_d
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
   return HOTRG_OK;
+}
+
+
+// ===========================================================================
+// Batched runs
+// ===========================================================================
+
+static int batch_fail(hotrg_batch* b, int code, const std::string& msg) {
+  if (b) {
+    b->err = msg;
+    if (code == HOTRG_E_DEVICE || code == HOTRG_E_NUMERIC) b->failed = true;
+  } else {
+    g_static_err = msg;
+  }
+  return code;
+}
+
+struct BatchLayout {
+  std::vector<Plan> plans;
+  size_t off_tables = 0;
+  int table_cap = 0, n_tables = 0;
+  size_t total = 0;
+};
+
+static constexpr int BATCH_TABLES = 8;
+
+static int batch_layout(const hotrg_instance* inst, int n, const hotrg_opts* o, BatchLayout* L) {
+  if (!inst || !o || n < 1) return HOTRG_E_ARG;
+  if (o->record_grad) return HOTRG_E_ARG;     // the derivative is carried by single handles
+  std::vector<Need> needs((size_t)n);
+  Need shared{};
+  for (int i = 0; i < n; ++i) {
+    const int rc = check_init_args(&inst[i].model, inst[i].beta, inst[i].chi, o);
+    if (rc) return rc;
+    needs[i] = plan_need(inst[i].model.d, inst[i].model.q, inst[i].chi, o->precision, o->chunk, false);
+    need_max(shared, needs[i]);
+  }
+  size_t off = 0;
+  Plan S{};
+  place_scratch(S, off, shared, false);
+  L->table_cap = n * EIG_SLOTS;
+  L->n_tables = BATCH_TABLES;
+  L->off_tables = take_at(off, sizeof(EigDesc) * (size_t)L->table_cap * L->n_tables);
+  L->plans.clear();
+  for (int i = 0; i < n; ++i) {
+    Plan P = S;
+    P.need = needs[i];
+    P.max_steps = o->max_steps;
+    P.grad = false;
+    place_private(P, off, needs[i], o->max_steps, false);
+    L->plans.push_back(P);
+  }
+  L->total = off;
+  for (auto& P : L->plans) P.total = off;
+  return HOTRG_OK;
+}
+
+size_t hotrg_batch_workspace_bytes(const hotrg_instance* inst, int n, const hotrg_opts* opts) {
+  BatchLayout L;
+  if (batch_layout(inst, n, opts, &L) != HOTRG_OK) return 0;
+  return L.total;
+}
+
+int hotrg_batch_init(const hotrg_instance* inst, int n, const hotrg_opts* opts, void* workspace, size_t ws_bytes,
+                     void* stream, hotrg_batch** out) {
+  if (!out) return batch_fail(nullptr, HOTRG_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!inst || !opts || n < 1) return batch_fail(nullptr, HOTRG_E_ARG, "instances or opts missing");
+  if (opts->record_grad) return batch_fail(nullptr, HOTRG_E_ARG, "record_grad is not available for batches");
+  BatchLayout L;
+  const int rc = batch_layout(inst, n, opts, &L);
+  if (rc) return batch_fail(nullptr, rc, "invalid instance or options");
+  if (!workspace) return batch_fail(nullptr, HOTRG_E_ARG, "workspace is NULL");
+  if (ws_bytes < L.total) return batch_fail(nullptr, HOTRG_E_OOM, "workspace too small");
+  if (((uintptr_t)workspace) % ALIGN) return batch_fail(nullptr, HOTRG_E_ARG, "workspace must be 256-byte aligned");
+  hotrg_batch* b = new hotrg_batch();
+  b->n = n;
+  b->opts = *opts;
+  b->ws = (char*)workspace;
+  b->ws_bytes = ws_bytes;
+  b->s = (hipStream_t)stream;
+  b->off_tables = L.off_tables;
+  b->table_cap = L.table_cap;
+  b->n_tables = L.n_tables;
+  b->use_graphs = stream != nullptr;   // the legacy default stream cannot be recorded
+  for (int i = 0; i < n; ++i) {
+    hotrg_handle* h = new_handle(&inst[i].model, inst[i].beta, inst[i].chi, opts, workspace, ws_bytes, stream,
+                                 L.plans[i]);
+    if (!h) {
+      for (auto* x : b->inst) hotrg_destroy(x);
+      delete b;
+      return HOTRG_E_DEVICE;
+    }
+    b->inst.push_back(h);
+  }
+  *out = b;
+  return HOTRG_OK;
+}
+
+static bool desc_equal(const std::vector<EigDesc>& a, const std::vector<EigDesc>& c) {
+  if (a.size() != c.size()) return false;
+  for (size_t i = 0; i < a.size(); ++i)
+    if (a[i].n != c[i].n || a[i].kvec != c[i].kvec || a[i].A != c[i].A || a[i].w != c[i].w || a[i].V != c[i].V ||
+        a[i].scratch != c[i].scratch)
+      return false;
+  return true;
+}
+
+// Device table holding `descs`: found by signature, else written into a free slot (or the
+// oldest one after the stream has drained, since a pending launch may still read it).
+static int batch_table(hotrg_batch* b, const std::vector<EigDesc>& descs, const EigDesc** dev) {
+  *dev = nullptr;
+  if (descs.empty()) return HOTRG_OK;
+  for (auto& t : b->tables)
+    if (desc_equal(t.key, descs)) {
+      *dev = b->at<EigDesc>(b->off_tables) + (size_t)t.slot * b->table_cap;
+      return HOTRG_OK;
+    }
+  int slot;
+  if ((int)b->tables.size() < b->n_tables) {
+    slot = (int)b->tables.size();
+  } else {
+    slot = b->next_slot;
+    b->next_slot = (slot + 1) % b->n_tables;
+    for (size_t i = 0; i < b->tables.size(); ++i)
+      if (b->tables[i].slot == slot) { b->tables.erase(b->tables.begin() + (long)i); break; }
+    if (hipStreamSynchronize(b->s) != hipSuccess) return batch_fail(b, HOTRG_E_DEVICE, "stream synchronisation failed");
+  }
+  EigDesc* d = b->at<EigDesc>(b->off_tables) + (size_t)slot * b->table_cap;
+  if (hipMemcpy(d, descs.data(), sizeof(EigDesc) * descs.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return batch_fail(b, HOTRG_E_DEVICE, "descriptor upload failed");
+  b->tables.push_back({descs, slot});
+  *dev = d;
+  return HOTRG_OK;
+}
+
+// One step of every instance: records and Gram matrices of all, one eigensolver launch,
+// then choice, contraction, trace and normalisation of each in turn.
+static int batch_enqueue(hotrg_batch* b, const std::vector<StepPlan>& sps, int ndesc, const EigDesc* table) {
+  for (int i = 0; i < b->n; ++i) {
+    const int rc = enqueue_step_front(b->inst[i], -1);
+    if (rc) return batch_fail(b, rc, "instance " + std::to_string(i) + ": " + b->inst[i]->err);
+  }
+  if (ndesc > 0) hipLaunchKernelGGL(k_eigh_list, dim3((unsigned)ndesc), dim3(EIG_THREADS), 0, b->s, table);
+  for (int i = 0; i < b->n; ++i) {
+    const int rc = enqueue_step_back(b->inst[i], sps[i], nullptr);
+    if (rc) return batch_fail(b, rc, "instance " + std::to_string(i) + ": " + b->inst[i]->err);
+  }
+  if (hipGetLastError() != hipSuccess) return batch_fail(b, HOTRG_E_DEVICE, "kernel launch failed");
+  return HOTRG_OK;
+}
+
+int hotrg_batch_step(hotrg_batch* b) {
+  if (!b) return batch_fail(nullptr, HOTRG_E_ARG, "batch is NULL");
+  if (b->failed) return batch_fail(b, HOTRG_E_STATE, "batch is in the failed state");
+  if (b->p >= b->opts.max_steps) return batch_fail(b, HOTRG_E_STATE, "max_steps reached");
+  std::vector<StepPlan> sps((size_t)b->n);
+  std::vector<EigDesc> descs;
+  bool steady = true;
+  for (int i = 0; i < b->n; ++i) {
+    hotrg_handle* h = b->inst[i];
+    sps[i] = step_plan(h);
+    EigDesc e[EIG_SLOTS];
+    const int c = collect_eig(h, h->ld, e);
+    for (int k = 0; k < c; ++k) descs.push_back(e[k]);
+    if (!same_dims(sps[i].ld, sps[i].nl)) steady = false;
+  }
+  const EigDesc* table = nullptr;
+  int rc = batch_table(b, descs, &table);
+  if (rc) return rc;
+  const int parity = b->p & 1;
+  if (steady && b->use_graphs) {
+    // every instance keeps its dims from here on: the step is the same kernel sequence each
+    // time (the step counter is read on the device), with the tensor buffers alternating
+    if (!b->graph[parity]) {
+      if (hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return batch_fail(b, HOTRG_E_DEVICE, "stream capture could not begin");
+      rc = batch_enqueue(b, sps, (int)descs.size(), table);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(b->s, &g);
+      if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+      }
+      if (ec != hipSuccess || !g) return batch_fail(b, HOTRG_E_DEVICE, "stream capture failed");
+      const hipError_t ei = hipGraphInstantiate(&b->graph[parity], g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        b->graph[parity] = nullptr;
+        return batch_fail(b, HOTRG_E_DEVICE, "graph instantiation failed");
+      }
+    }
+    if (hipGraphLaunch(b->graph[parity], b->s) != hipSuccess)
+      return batch_fail(b, HOTRG_E_DEVICE, "graph launch failed");
+    b->graph_launches += 1;
+  } else {
+    rc = batch_enqueue(b, sps, (int)descs.size(), table);
+    if (rc) return rc;
+    b->eager_steps += 1;
+  }
+  for (int i = 0; i < b->n; ++i) advance_host(b->inst[i], sps[i]);
+  b->p += 1;
+  return HOTRG_OK;
+}
+
+int hotrg_batch_log_z(hotrg_batch* b, double* lnz, int* steps) {
+  if (!b || !lnz) return batch_fail(b, HOTRG_E_ARG, "NULL argument");
+  if (hipStreamSynchronize(b->s) != hipSuccess) {
+    b->failed = true;
+    return batch_fail(b, HOTRG_E_DEVICE, "stream synchronisation failed");
+  }
+  for (int i = 0; i < b->n; ++i) {
+    DevState st;
+    const int rc = sync_state(b->inst[i], &st);
+    if (rc) return batch_fail(b, rc, "instance " + std::to_string(i) + ": " + b->inst[i]->err);
+    lnz[i] = st.lnz;
+  }
+  if (steps) *steps = b->p;
+  return HOTRG_OK;
+}
+
+int hotrg_batch_info(hotrg_batch* b, int* graph_launches, int* eager_steps) {
+  if (!b) return batch_fail(nullptr, HOTRG_E_ARG, "batch is NULL");
+  if (graph_launches) *graph_launches = b->graph_launches;
+  if (eager_steps) *eager_steps = b->eager_steps;
+  return HOTRG_OK;
+}
+
+hotrg_handle* hotrg_batch_instance(hotrg_batch* b, int i) {
+  if (!b || i < 0 || i >= b->n) return nullptr;
+  return b->inst[i];
+}
+
+void hotrg_batch_destroy(hotrg_batch* b) {
+  if (!b) return;
+  for (auto& g : b->graph)
+    if (g) hipGraphExecDestroy(g);
+  for (auto* h : b->inst) hotrg_destroy(h);
+  delete b;
+}
+
+const char* hotrg_batch_last_error(const hotrg_batch* b) {
+  if (!b) return g_static_err.c_str();
+  return b->err.c_str();
 }
 
 }  // extern "C"

@@ -574,15 +574,21 @@ __device__ inline void cgs_cluster(double* zs, const double* __restrict__ Z, int
   __syncthreads();
 }
 
-__global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
+// One matrix per workgroup: A (n x n, destroyed), eigenvalues w (descending), the leading
+// kvec eigenvectors as columns of V (n x n storage), scratch 2 n^2 doubles.
+struct EigDesc {
+  int n, kvec;
+  double* A;
+  double* w;
+  double* V;
+  double* scratch;
+};
+
+__device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ A, double* __restrict__ w,
+                              double* __restrict__ V, double* __restrict__ R) {
   __shared__ double d[EIG_MAXN], e[EIG_MAXN], vv[EIG_MAXN], qv[EIG_MAXN];
   __shared__ double red[EIG_THREADS / 64];
-  const int n = eb.n[blockIdx.x], kvec = eb.kvec[blockIdx.x];
-  double* A = eb.A[blockIdx.x];
-  double* w = eb.w[blockIdx.x];
-  double* V = eb.V[blockIdx.x];
-  double* R = eb.scratch[blockIdx.x];                   // reflector k at R[k * n .. k * n + n)
-  double* Z = R + (long)n * n;                          // tridiagonal eigenvector i at Z[i * n ..)
+  double* Z = R + (long)n * n;                          // reflector k at R[k n ..]; tridiagonal eigenvector i at Z[i n ..)
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
 
   // ---- 1. tridiagonalisation --------------------------------------------------
@@ -790,6 +796,19 @@ __global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
   }
 }
 
+// Up to four matrices passed by value (one coarse-graining step of one instance).
+__global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
+  const int b = blockIdx.x;
+  eigh_tri_body(eb.n[b], eb.kvec[b], eb.A[b], eb.w[b], eb.V[b], eb.scratch[b]);
+}
+
+// Any number of matrices from a descriptor table in device memory (a step of a batch of
+// instances: one launch for all their decompositions).
+__global__ __launch_bounds__(EIG_THREADS) void k_eigh_list(const EigDesc* __restrict__ list) {
+  const EigDesc ds = list[blockIdx.x];
+  eigh_tri_body(ds.n, ds.kvec, ds.A, ds.w, ds.V, ds.scratch);
+}
+
 // ---------------------------------------------------------------------------
 // Judgement values, choice and truncation (Sections 2, 4.2.6-4.2.7):
 //   epsilon = sum_{l >= chi_new} max(lambda_l, 0),  U if epsilon < epsilon' else U'.
@@ -807,7 +826,8 @@ constexpr double MULT_RTOL = 1e-10, MULT_ATOL = 1e-12;
 __global__ void k_choose(const double* __restrict__ w0, const double* __restrict__ w1,
                          const double* __restrict__ V0, const double* __restrict__ V1, int n, int chi_new,
                          int identity, double tau, double* __restrict__ Ut, float* __restrict__ Ut32,
-                         StepRec* rec, int dir_index) {
+                         StepRec* rec_base, const DevState* __restrict__ st, int dir_index) {
+  StepRec* rec = rec_base + st->p;
   __shared__ double eps_s[2];
   __shared__ int prime_s, kept_s;
   const int tid = threadIdx.x;
@@ -1133,7 +1153,11 @@ __global__ __launch_bounds__(64) void k_nstage2(const AT* __restrict__ C, long l
 // ---------------------------------------------------------------------------
 template <class MT>
 __global__ __launch_bounds__(256) void k_trace_lnz(const MT* __restrict__ Tn, int Hn, int chic_old,
-                                                   DevState* st, StepRec* rec, int p) {
+                                                   DevState* st, StepRec* rec_base) {
+  // the step counter lives on the device (st->p = steps done before this one), so that a
+  // recorded step can be replayed unchanged
+  const int p = st->p + 1;
+  StepRec* rec = rec_base + (p - 1);
   __shared__ double red[256];
   __shared__ double Y[32 * 32];
   const int tid = threadIdx.x;
@@ -1167,7 +1191,6 @@ __global__ __launch_bounds__(256) void k_trace_lnz(const MT* __restrict__ Tn, in
     const double lnz = st->lnz + (ok ? log(t) : 0.0) / ldexp(1.0, p);
     st->lnz = lnz;
     st->f = ok ? 1.0 / t : 1.0;
-    st->p = p;
     rec->trace = t;
     rec->lnz = lnz;
     rec->gu_wen = ty * ty / ty2;
@@ -1222,10 +1245,12 @@ __global__ void k_gram_combine_t(const double* __restrict__ Gh, const double* __
 __global__ __launch_bounds__(256) void k_dU(const double* __restrict__ w0, const double* __restrict__ w1,
                                             const double* __restrict__ V0, const double* __restrict__ V1,
                                             const double* __restrict__ dA0, const double* __restrict__ dA1,
-                                            int n, int chi_new, const StepRec* __restrict__ rec, int dir_index,
+                                            int n, int chi_new, const StepRec* __restrict__ rec_base,
+                                            const DevState* __restrict__ st, int dir_index,
                                             double* __restrict__ W, double* __restrict__ M,
                                             double* __restrict__ dUt, float* __restrict__ dUt32) {
   const int tid = threadIdx.x;
+  const StepRec* rec = rec_base + st->p;
   const int side = rec->chose_prime[dir_index], kept = rec->kept[dir_index];
   const double* lam = side ? w1 : w0;
   const double* V = side ? V1 : V0;
@@ -1272,7 +1297,8 @@ __global__ void k_zero_f64_f32(double* a, float* b, long n) {
 
 // dt = Tr dT^new and d(lnZ/V) += (dt / t) / 2^p (after k_trace_lnz of the same step).
 template <class MT>
-__global__ __launch_bounds__(256) void k_trace_t(const MT* __restrict__ dTn, int Hn, DevState* st, int p) {
+__global__ __launch_bounds__(256) void k_trace_t(const MT* __restrict__ dTn, int Hn, DevState* st) {
+  const int p = st->p + 1;
   __shared__ double red[256];
   const int tid = threadIdx.x;
   double s = 0.0;
@@ -1333,7 +1359,12 @@ __global__ void k_scale(MT* __restrict__ T, long n, DevState* st) {
   if (threadIdx.x == 0) atomicMax((unsigned long long*)&st->maxabs, __double_as_longlong(red[0]));
 }
 
-__global__ void k_reset_maxabs(DevState* st) { st->maxabs = 0.0; }
+// End of a step (after the trace kernels, before the normalisation that recomputes max|T|):
+// the device step counter advances.
+__global__ void k_step_end(DevState* st) {
+  st->maxabs = 0.0;
+  st->p += 1;
+}
 
 // 1 / (s_A s_B) for the FP16 forms: s_A from max|T|, s_B from the bound |B| <= sqrt(b) max|T|
 // (each prime-chain output is an isometry applied to a b-vector of T).
@@ -1344,7 +1375,11 @@ __global__ void k_inv_scale_fp16(DevState* st, int b) {
 }
 
 // Fresh step record.
-__global__ void k_rec_init(StepRec* rec, int p, int axis, int d, int c0, int c1, int c2) {
+// axis < 0: the natural cycle, lattice axis (p - 1) mod d.
+__global__ void k_rec_init(StepRec* rec_base, const DevState* st, int axis, int d, int c0, int c1, int c2) {
+  const int p = st->p + 1;
+  StepRec* rec = rec_base + (p - 1);
+  if (axis < 0) axis = (p - 1) % d;
   int* w = (int*)rec;
   for (int i = threadIdx.x; i < (int)(sizeof(StepRec) / sizeof(int)); i += blockDim.x) w[i] = 0;
   __syncthreads();

@@ -104,7 +104,38 @@ def run_grad():
     return runs
 
 
+# Batched sweep: the instances of the sweep checked against the oracle (both ends of the
+# 3D temperature range; the first and last three 2D instances, one per chi).
+CONFIG4_SAMPLE_3D = (0, 63)
+CONFIG4_SAMPLE_2D = (0, 1, 2, 45, 46, 47)
+
+
+def run_config4():
+    c3, c2 = SI.CONFIG4_3D, SI.CONFIG4_2D
+    runs = []
+    for i in CONFIG4_SAMPLE_3D:
+        cfg = dict(kind=c3["kind"], d=3, q=2, chi=c3["chi"], steps=c3["steps"])
+        r = run_config(f"config4 3D[{i}]", cfg, [1.0 / c3["temps"][i]])[0]
+        r.update(index=i, d=3, chi=c3["chi"])
+        runs.append(r)
+    for i in CONFIG4_SAMPLE_2D:
+        chi = c2["chis"][i % len(c2["chis"])]
+        cfg = dict(kind=c2["kind"], d=2, q=2, chi=chi, steps=c2["steps"])
+        r = run_config(f"config4 2D[{i}]", cfg, [float(c2["betas"][i])])[0]
+        r.update(index=i, d=2, chi=chi)
+        runs.append(r)
+    return runs
+
+
 def main(names):
+    if "config4" in names:
+        doc = dict(config="config4", runs=run_config4(), steps=SI.CONFIG4_3D["steps"], provenance=provenance(),
+                   source="oracle/hotrg.py (FP64 NumPy), written by tests/golden/make_golden.py")
+        path = os.path.join(HERE, "config4.json")
+        with open(path, "w") as f:
+            json.dump(doc, f, indent=1)
+        print("wrote", path, flush=True)
+        names = [n for n in names if n != "config4"]
     if "grad" in names:
         doc = dict(config="grad", runs=run_grad(), provenance=provenance(),
                    source="oracle/tangent.py (FP64 NumPy), written by tests/golden/make_golden.py")

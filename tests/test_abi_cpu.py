@@ -104,3 +104,24 @@ def test_derivative_mode_forms():
     rc = P.lib().hotrg_init(ctypes.byref(_model()), 0.0, 8, ctypes.byref(o), ctypes.c_void_p(256), 1 << 40, None,
                             ctypes.byref(h))
     assert rc == P.HOTRG_E_ARG     # the derivative needs beta > 0
+
+
+def test_batch_workspace_and_argument_errors():
+    o = P.hotrg_opts(P.HOTRG_FP64, 8, 0, 0)
+    inst = [P.make_instance("ising", 3, 0.22, 8), P.make_instance("ising", 2, 0.44, 16),
+            P.make_instance("potts", 3, 0.55, 9)]
+    nb = P.hotrg_batch_workspace_bytes(inst, o)
+    single = [P.hotrg_workspace_bytes(i.model, i.chi, o) for i in inst]
+    # private state per instance, one shared scratch area: less than separate handles
+    assert max(single) < nb < sum(single)
+    assert P.hotrg_batch_workspace_bytes(inst + [P.make_instance("ising", 3, 0.22, 17)], o) == 0
+    assert P.hotrg_batch_workspace_bytes(inst, P.hotrg_opts(P.HOTRG_FP64, 8, 0, 1)) == 0   # no derivative
+    assert P.lib().hotrg_batch_workspace_bytes(None, 0, ctypes.byref(o)) == 0
+    b = ctypes.c_void_p()
+    arr = (P.hotrg_instance * 3)(*inst)
+    rc = P.lib().hotrg_batch_init(arr, 3, ctypes.byref(o), ctypes.c_void_p(256), 16, None, ctypes.byref(b))
+    assert rc == P.HOTRG_E_OOM and not b.value
+    assert "workspace" in P.hotrg_batch_last_error(None)
+    assert P.lib().hotrg_batch_step(None) == P.HOTRG_E_ARG
+    assert not P.lib().hotrg_batch_instance(None, 0)
+    P.lib().hotrg_batch_destroy(None)
