@@ -44,11 +44,11 @@ def fixture_lnz():
     return [s["lnz_per_site"] for s in fx["runs"][0]["steps"]]
 
 
-def run_form(P, torch, form, steps, warmup):
+def run_form(P, torch, form, steps, warmup, record_grad=False, finish=True):
     """Full run in one precision form; times exactly `steps` saturated steps."""
     beta = 1.0 / TEMP
-    total = max(STEPS_FIXTURE, UNSATURATED + warmup + steps)
-    r = P.HOTRG("ising", 3, beta, CHI, precision=form, max_steps=total)
+    total = max(STEPS_FIXTURE, UNSATURATED + warmup + steps) if finish else UNSATURATED + warmup + steps
+    r = P.HOTRG("ising", 3, beta, CHI, precision=form, max_steps=total, record_grad=record_grad)
     lnz = []
     for _ in range(UNSATURATED + warmup):
         r.step()
@@ -66,10 +66,11 @@ def run_form(P, torch, form, steps, warmup):
     while r.steps < total:
         r.step()
     final = r.log_z()
+    grad = r.grad() if record_grad else None
     # per-step lnZ/V from the step records
     lnz = [r.info(p).lnz_per_site for p in range(1, total + 1)]
     r.close()
-    return dict(wall=wall, timings=tm, lnz=lnz, final=final, total_steps=total)
+    return dict(wall=wall, timings=tm, lnz=lnz, final=final, total_steps=total, grad=grad)
 
 
 def cpu_baseline(sample_pairs=16):
@@ -111,6 +112,9 @@ def main():
     ap.add_argument("--reference-form", default="fp64")
     ap.add_argument("--reference-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-grad", action="store_true", help="skip the timing of the derivative mode")
+    ap.add_argument("--no-reference", action="store_true",
+                    help="skip the FP64 reference run (profiling runs of the headline form only)")
     ap.add_argument("--other-forms", default="fp32,split_bf16,fp16,bf16",
                     help="comma-separated forms also reported (2 timed steps each); empty for none")
     args = ap.parse_args()
@@ -143,14 +147,15 @@ def main():
         err = max(abs(head["lnz"][i] - ref_lnz[i]) / abs(ref_lnz[i]) for i in range(n))
         err_final = abs(head["lnz"][n - 1] - ref_lnz[n - 1]) / abs(ref_lnz[n - 1])
 
-    ref = run_form(P, torch, args.reference_form, args.reference_steps, 0)
-    rtm = ref["timings"]
-    ref_ms_per_step = ref["wall"] * 1e3 / args.reference_steps
-    ref_contract_tflops = rtm["flops_contract"] / (rtm["contract"]["ms"] * 1e-3) / 1e12
-    ref_err = None
-    if ref_lnz is not None:
-        n = min(len(ref_lnz), len(ref["lnz"]))
-        ref_err = max(abs(ref["lnz"][i] - ref_lnz[i]) / abs(ref_lnz[i]) for i in range(n))
+    ref_ms_per_step = ref_contract_tflops = ref_err = None
+    if not args.no_reference:
+        ref = run_form(P, torch, args.reference_form, args.reference_steps, 0)
+        rtm = ref["timings"]
+        ref_ms_per_step = ref["wall"] * 1e3 / args.reference_steps
+        ref_contract_tflops = rtm["flops_contract"] / (rtm["contract"]["ms"] * 1e-3) / 1e12
+        if ref_lnz is not None:
+            n = min(len(ref_lnz), len(ref["lnz"]))
+            ref_err = max(abs(ref["lnz"][i] - ref_lnz[i]) / abs(ref_lnz[i]) for i in range(n))
 
     forms = {}
     for form in [f for f in args.other_forms.split(",") if f]:
@@ -166,6 +171,16 @@ def main():
             "bottleneck_tflops": round(ftm["flops_bottleneck"] / (ftm["bottleneck"]["ms"] * 1e-3) / 1e12, 3),
             "free_energy_rel_err_vs_oracle": e,
         }
+
+    deriv = {}
+    if not args.no_grad:
+        for form in ("fp32", "fp64"):
+            res = run_form(P, torch, form, 1, 0, record_grad=True, finish=False)
+            fwd_ms = forms[form]["ms_per_step"] if form in forms else (ref_ms_per_step if form == args.reference_form
+                                                                         else None)
+            deriv[form] = {"ms_per_step": round(res["wall"] * 1e3, 3), "forward_ms_per_step": fwd_ms,
+                           "cost_vs_forward": round(res["wall"] * 1e3 / fwd_ms, 3) if fwd_ms else None,
+                           "dlnz_dbeta_per_site_after_4_steps": res["grad"]}
 
     out = {
         "metric": METRIC,
@@ -190,7 +205,7 @@ def main():
         "phase_ms_per_step": {k: round(tm[k]["ms"] / args.steps, 3) for k in P.TIMING_PHASES},
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_gemm_tn (bottleneck, eq. BottleneckPart)",
+            "kernel": "k_gemm_big (bottleneck GEMM with the fused non-prime chain, eq. BottleneckPart)",
             "achieved": round(bott_tflops, 3),
             "peak": peak,
             "unit": "TFLOP/s",
@@ -200,7 +215,7 @@ def main():
             "launches": tm["bottleneck"]["count"],
             "traffic": None,
         },
-        "fp64_reference": {
+        "fp64_reference": None if args.no_reference else {
             "form": args.reference_form,
             "ms_per_step": round(ref_ms_per_step, 3),
             "steps_per_s": round(1e3 / ref_ms_per_step, 4),
@@ -209,6 +224,7 @@ def main():
             "speedup_of_headline_form": round(ref_ms_per_step / ms_per_step, 3),
         },
         "other_forms": forms,
+        "derivative_mode": deriv,
     }
     if not args.no_cpu:
         cb = cpu_baseline()

@@ -281,6 +281,7 @@ struct hotrg_handle {
   int p = 0;
   bool failed = false;
   bool no_fuse = false;   // force the separate non-prime kernel (tests of the fused epilogue)
+  bool scalar_prime = false;   // force the one-element-per-thread prime chain (debug contraction)
   bool grad = false;      // derivative mode: carry dT/dbeta through every step
   std::string err;
   // live timing: pairs of events recorded on the stream, resolved at hotrg_timings
@@ -506,7 +507,10 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     hipEvent_t t0 = tmark(h);
     hipLaunchKernelGGL((k_zero_pad<ST>), dim3(grid_for((Np - ncols) * Kp + ncols * (Kp - H) + 1)), dim3(256), 0,
                        h->s, Bop, ncols, Np, H, Kp, bplane, FormInfo<F>::planes, 1);
-    if (ld.d == 3)
+    if (ld.d == 3 && dm.chi2 % 4 == 0 && !h->scalar_prime)
+      hipLaunchKernelGGL((k_pstage3v<MT, UT, F>), dim3((unsigned)H), dim3(256), 0, h->s, T, (const UT*)U1,
+                         (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane, (const DevState*)st);
+    else if (ld.d == 3)
       hipLaunchKernelGGL((k_pstage3<MT, UT, F>), dim3((unsigned)H), dim3(256), 0, h->s, T, (const UT*)U1,
                          (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane, (const DevState*)st);
     else

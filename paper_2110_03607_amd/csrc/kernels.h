@@ -68,22 +68,47 @@ __device__ inline double fp16_scale_for(double bound) {
 enum Form { F_FP64 = 0, F_FP32 = 1, F_BF16 = 2, F_FP16 = 3, F_SPLIT_BF16 = 4, F_SPLIT_FP16 = 5 };
 
 // Write value x (already scaled) in form F at position i of plane 0 (and plane 1 at +plane).
+// put: one element; put4: four consecutive elements starting at a multiple of 4 (one
+// vector store per plane: 8 bytes for the 16-bit forms, 16 for FP32).
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 template <int F> struct Store;
 template <> struct Store<F_FP64> {
   typedef double T;
   __device__ static void put(T* p, long i, long, double x) { p[i] = x; }
+  __device__ static void put4(T* p, long i, long, const double* x) {
+    for (int j = 0; j < 4; ++j) p[i + j] = x[j];
+  }
 };
 template <> struct Store<F_FP32> {
   typedef float T;
   __device__ static void put(T* p, long i, long, double x) { p[i] = (float)x; }
+  __device__ static void put4(T* p, long i, long, const double* x) {
+    f4v v;
+    v.x = (float)x[0]; v.y = (float)x[1]; v.z = (float)x[2]; v.w = (float)x[3];
+    *reinterpret_cast<f4v*>(p + i) = v;
+  }
 };
 template <> struct Store<F_BF16> {
   typedef uint16_t T;
   __device__ static void put(T* p, long i, long, double x) { p[i] = f32_to_bf16_rne((float)x); }
+  __device__ static void put4(T* p, long i, long, const double* x) {
+    u16x4 v;
+    v.x = f32_to_bf16_rne((float)x[0]); v.y = f32_to_bf16_rne((float)x[1]);
+    v.z = f32_to_bf16_rne((float)x[2]); v.w = f32_to_bf16_rne((float)x[3]);
+    *reinterpret_cast<u16x4*>(p + i) = v;
+  }
 };
 template <> struct Store<F_FP16> {
   typedef _Float16 T;
   __device__ static void put(T* p, long i, long, double x) { p[i] = (_Float16)(float)x; }
+  __device__ static void put4(T* p, long i, long, const double* x) {
+    h4v v;
+    v.x = (_Float16)(float)x[0]; v.y = (_Float16)(float)x[1]; v.z = (_Float16)(float)x[2]; v.w = (_Float16)(float)x[3];
+    *reinterpret_cast<h4v*>(p + i) = v;
+  }
 };
 template <> struct Store<F_SPLIT_BF16> {
   typedef uint16_t T;
@@ -94,6 +119,17 @@ template <> struct Store<F_SPLIT_BF16> {
     p[i] = hi;
     p[i + plane] = f32_to_bf16_rne(lo);
   }
+  __device__ static void put4(T* p, long i, long plane, const double* x) {
+    u16x4 h, l;
+    for (int j = 0; j < 4; ++j) {
+      const float xf = (float)x[j];
+      const uint16_t hi = f32_to_bf16_rne(xf);
+      h[j] = hi;
+      l[j] = f32_to_bf16_rne(xf - bf16_to_f32(hi));
+    }
+    *reinterpret_cast<u16x4*>(p + i) = h;
+    *reinterpret_cast<u16x4*>(p + i + plane) = l;
+  }
 };
 template <> struct Store<F_SPLIT_FP16> {
   typedef _Float16 T;
@@ -103,6 +139,17 @@ template <> struct Store<F_SPLIT_FP16> {
     float lo = xf - (float)hi;
     p[i] = hi;
     p[i + plane] = (_Float16)lo;
+  }
+  __device__ static void put4(T* p, long i, long plane, const double* x) {
+    h4v h, l;
+    for (int j = 0; j < 4; ++j) {
+      const float xf = (float)x[j];
+      const _Float16 hi = (_Float16)xf;
+      h[j] = hi;
+      l[j] = (_Float16)(xf - (float)hi);
+    }
+    *reinterpret_cast<h4v*>(p + i) = h;
+    *reinterpret_cast<h4v*>(p + i + plane) = l;
   }
 };
 
@@ -1009,6 +1056,78 @@ __global__ __launch_bounds__(256) void k_pstage3(const MT* __restrict__ T, const
           if constexpr (ACC) B[row * ldb + (long)rho * b + r] += s;
           else Store<F>::put(B, row * ldb + (long)rho * b + r, bplane, (double)s * sB);
         }
+      }
+    }
+  }
+}
+
+// Prime chain (3D), same output as k_pstage3, for chi2 % 4 == 0: each thread owns four
+// consecutive output columns r = (nh1', nh2' .. nh2' + 3) of one row and writes them with one
+// vector store per plane; its 16 Z values (fixed nh1') stay in registers over the pair groups
+// of the chunk, and U2 comes from LDS four columns at a time.
+template <class MT, class UT, int F>
+__global__ __launch_bounds__(256) void k_pstage3v(const MT* __restrict__ T, const UT* __restrict__ U1,
+                                                  const UT* __restrict__ U2, Dims dm, int pr0, int pr1,
+                                                  typename Store<F>::T* __restrict__ B, long ldb, long bplane,
+                                                  const DevState* __restrict__ st) {
+  __shared__ MT u2t[16 * 256];   // [n2'][nc2'][nh2']
+  __shared__ MT u1t[16 * 256];   // [n1' - n1lo][nc1'][nh1']
+  __shared__ MT X[256];
+  __shared__ MT Z[16 * 256];     // [n1' - n1lo][nh1'][nc2']
+  const int tid = threadIdx.x;
+  const int h = blockIdx.x;
+  const int b = dm.b, chi1 = dm.chi1, chi2 = dm.chi2, k1 = dm.k1, k2 = dm.k2;
+  const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * sqrt((double)b)) : 1.0;
+  const int rho = h / b, nc = h % b;
+  const int n1lo = pr0 / k2, n1hi = (pr1 - 1) / k2, nn1 = n1hi - n1lo + 1;
+  const int c2sq = chi2 * chi2, c1sq = chi1 * chi1;
+  for (int i = tid; i < k2 * c2sq; i += 256) {
+    const int n2 = i / c2sq, rem = i % c2sq, nc2 = rem / chi2, nh2 = rem % chi2;
+    u2t[i] = (MT)U2[(nh2 + chi2 * nc2) * k2 + n2];
+  }
+  for (int i = tid; i < nn1 * c1sq; i += 256) {
+    const int n1 = n1lo + i / c1sq, rem = i % c1sq, nc1 = rem / chi1, nh1 = rem % chi1;
+    u1t[i] = (MT)U1[(nh1 + chi1 * nc1) * k1 + n1];
+  }
+  const int G = b / 4;                       // column groups of four
+  const int lanes = 256 / G;                 // pair groups handled side by side
+  const int g = tid % G, prl = tid / G;
+  const bool active = prl < lanes;
+  const int r0 = 4 * g, nh1 = r0 / chi2, nh2 = r0 % chi2;
+  for (int cp = 0; cp < dm.chic; ++cp) {
+    __syncthreads();
+    for (int i = tid; i < b; i += 256) X[i] = T[(long)h * dm.H + (long)cp * b + i];
+    __syncthreads();
+    for (int i = tid; i < nn1 * b; i += 256) {
+      const int n1l = i / b, r = i % b, zh1 = r / chi2, nc2 = r % chi2;
+      const MT* u = &u1t[n1l * c1sq + zh1];
+      MT s = 0;
+      for (int nc1 = 0; nc1 < chi1; ++nc1) s += u[nc1 * chi1] * X[nc1 * chi2 + nc2];
+      Z[i] = s;
+    }
+    __syncthreads();
+    if (!active) continue;
+    for (int n1 = n1lo; n1 <= n1hi; ++n1) {
+      MT z[16];
+#pragma unroll
+      for (int nc2 = 0; nc2 < 16; ++nc2) z[nc2] = nc2 < chi2 ? Z[(n1 - n1lo) * b + nh1 * chi2 + nc2] : (MT)0;
+      const int pa = n1 * k2 > pr0 ? n1 * k2 : pr0;
+      const int pb = (n1 + 1) * k2 < pr1 ? (n1 + 1) * k2 : pr1;
+      for (int pr = pa + prl; pr < pb; pr += lanes) {
+        const MT* u = &u2t[(pr % k2) * c2sq + nh2];
+        MT s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+        for (int nc2 = 0; nc2 < 16; ++nc2)
+          if (nc2 < chi2) {
+            const MT* uu = u + nc2 * chi2;
+            s0 += z[nc2] * uu[0];
+            s1 += z[nc2] * uu[1];
+            s2 += z[nc2] * uu[2];
+            s3 += z[nc2] * uu[3];
+          }
+        const double v[4] = {(double)s0 * sB, (double)s1 * sB, (double)s2 * sB, (double)s3 * sB};
+        const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
+        Store<F>::put4(B, row * ldb + (long)rho * b + r0, bplane, v);
       }
     }
   }

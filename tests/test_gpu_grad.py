@@ -103,7 +103,8 @@ def test_autograd_function():
     assert float(b.grad) == pytest.approx(ref[-1][1], rel=1e-9)
 
 
-def fd_fp64(beta, steps, h):
+@functools.lru_cache(maxsize=None)
+def fd_fp64(beta, h, steps=20):
     """Central difference of lnZ/V after every step, GPU FP64 forward, 3D 3-state Potts, chi = 16."""
     val = {}
     for hh in (h, -h):
@@ -117,7 +118,7 @@ def fd_fp64(beta, steps, h):
 
 @functools.lru_cache(maxsize=None)
 def potts16(beta, precision, steps=20):
-    """3D 3-state Potts, chi = 16: per-step d(lnZ/V)/dbeta and the kept counts."""
+    """3D 3-state Potts, chi = 16: per-step d(lnZ/V)/dbeta and kept counts."""
     r = P.HOTRG("potts", 3, beta, 16, q=3, precision=precision, max_steps=steps, record_grad=True)
     g = []
     for p in range(steps):
@@ -130,38 +131,50 @@ def potts16(beta, precision, steps=20):
     return np.array(g), kept
 
 
-@pytest.mark.parametrize("beta", [0.50, 0.60])
+def _fmt(v):
+    return " ".join(f"{e:.1e}" for e in v)
+
+
+@pytest.mark.parametrize("beta", [0.50, 0.55, 0.60])
 def test_potts_chi16_fp64_gradient_vs_central_differences(beta):
-    """3D 3-state Potts, chi = 16: the FP64 derivative against central differences of the
-    FP64 forward (h = 1e-6) after each of the first 16 steps.  Later steps are left out: there
-    the truncated approximant has cuts with relative gaps of 1e-8 to 1e-11 and jumps inside
-    +-h (the differences grow as h shrinks), so no difference quotient converges; the
-    differences at h = 1e-4 (printed) already miss by up to 1e-1 from step 11 on."""
-    steps = 16
-    g64 = potts16(beta, "fp64")[0][:steps]
-    fd6 = fd_fp64(beta, steps, 1e-6)
-    fd4 = fd_fp64(beta, steps, 1e-4)
-    rel = np.abs(g64 - fd6) / np.abs(fd6)
-    rel4 = np.abs(g64 - fd4) / np.abs(fd4)
+    """3D 3-state Potts, chi = 16, 20 steps: the FP64 derivative against central differences
+    of the FP64 forward at h = 1e-6, to 1e-8 relative, at every step where lnZ/V is smooth on
+    the scale h = 1e-4 (the differences at h = 1e-4 and 1e-6 agree to 1e-5, so the h = 1e-6
+    difference is good to about 1e-9).  Elsewhere (beta = 0.55 from about step 11, close to
+    the first-order transition; cuts with relative gaps of 1e-8..1e-11 at late steps of
+    beta = 0.5 and 0.6) the truncated approximant bends or jumps inside +-1e-4 and no
+    difference quotient at these h converges; those steps are printed."""
+    g64 = potts16(beta, "fp64")[0]
+    fd6, fd4 = fd_fp64(beta, 1e-6), fd_fp64(beta, 1e-4)
+    rel6 = np.abs(g64 - fd6) / np.abs(g64)
+    rel4 = np.abs(g64 - fd4) / np.abs(g64)
+    smooth = np.abs(fd4 - fd6) <= 1e-5 * np.abs(g64)
     print(f"Potts chi=16 beta={beta}: d(lnZ/V)/dbeta fp64 {g64[-1]:.12f} fd(h=1e-6) {fd6[-1]:.12f} "
-          f"fd(h=1e-4) {fd4[-1]:.12f}; max rel err vs h=1e-6 {rel.max():.2e}\n  per step vs h=1e-6: "
-          + " ".join(f"{e:.1e}" for e in rel) + "\n  per step vs h=1e-4: " + " ".join(f"{e:.1e}" for e in rel4))
-    assert rel.max() < 1e-8
+          f"fd(h=1e-4) {fd4[-1]:.12f}; smooth at steps {[p + 1 for p in range(len(g64)) if smooth[p]]}; "
+          f"max rel err there {rel6[smooth].max():.2e}\n  per step vs h=1e-6: {_fmt(rel6)}"
+          f"\n  per step vs h=1e-4: {_fmt(rel4)}")
+    assert smooth[:10].all()
+    assert rel6[smooth].max() < 1e-8
 
 
 @pytest.mark.parametrize("beta", [0.50, 0.55, 0.60])
 def test_potts_chi16_fp32_gradient(beta):
     """3D 3-state Potts, chi = 16, 20 steps: the FP32 derivative against the FP64 derivative
-    to 1e-5 relative after every step up to the first step where the two forms keep different
-    numbers of columns (FP32 rounding splits S3 doublets by about 1e-6 of lambda_0, which the
-    multiplet rule then sees as distinct); from there on the two forms follow different
-    truncations and the remaining steps are printed, not compared."""
+    to 1e-5 relative after every step up to the first step where either the two forms keep
+    different numbers of columns (FP32 rounding splits S3 doublets by about 1e-6 of lambda_0,
+    which the multiplet rule then sees as distinct), or the FP64 derivative itself misses the
+    h = 1e-4 central difference by more than 1e-5 (lnZ/V bends inside +-1e-4: near the
+    first-order transition at beta = 0.55 the flow amplifies any perturbation, FP32 rounding
+    included).  The remaining steps are printed, not compared."""
     g64, k64 = potts16(beta, "fp64")
     g32, k32 = potts16(beta, "fp32")
-    same = next((p for p in range(len(k64)) if k64[p] != k32[p]), len(k64))
+    fd4 = fd_fp64(beta, 1e-4)
+    rough = np.abs(g64 - fd4) > 1e-5 * np.abs(g64)
+    n = len(k64)
+    upto = next((p for p in range(n) if k64[p] != k32[p] or rough[p]), n)
     rel = np.abs(g32 - g64) / np.abs(g64)
-    print(f"Potts chi=16 beta={beta}: d(lnZ/V)/dbeta fp32 {g32[-1]:.10f} fp64 {g64[-1]:.10f}; same truncation "
-          f"through step {same}; max rel err there {rel[:same].max():.2e}\n  per step: "
-          + " ".join(f"{e:.1e}" for e in rel) + f"\n  kept fp64 {k64}\n  kept fp32 {k32}")
-    assert same >= 8
-    assert rel[:same].max() < 1e-5
+    print(f"Potts chi=16 beta={beta}: d(lnZ/V)/dbeta fp32 {g32[-1]:.10f} fp64 {g64[-1]:.10f}; compared through "
+          f"step {upto}; max rel err there {rel[:upto].max():.2e}\n  per step: {_fmt(rel)}"
+          f"\n  fp64 vs fd(h=1e-4): {_fmt(np.abs(g64 - fd4) / np.abs(g64))}\n  kept fp64 {k64}\n  kept fp32 {k32}")
+    assert upto >= 8
+    assert rel[:upto].max() < 1e-5

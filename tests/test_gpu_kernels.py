@@ -70,7 +70,8 @@ def test_contract_fp64_matches_oracle(dims, kdims):
 
 @pytest.mark.parametrize("form", [P.HOTRG_FP32, P.HOTRG_SPLIT_FP16, P.HOTRG_SPLIT_BF16, P.HOTRG_FP16,
                                   P.HOTRG_BF16])
-@pytest.mark.parametrize("dims,kdims", [((8, 8, 8), (8, 8)), ((3, 5, 4), (7, 6)), ((8, 8), (16,))])
+@pytest.mark.parametrize("dims,kdims", [((8, 8, 8), (8, 8)), ((3, 5, 4), (7, 6)), ((8, 8), (16,)),
+                                       ((3, 12, 12), (12, 12))])
 def test_contract_forms_match_oracle(form, dims, kdims):
     Ts, Us = _random_case(dims, kdims, seed=3)
     ref = oracle_next_storage(LY.to_paper(Ts), Us)
