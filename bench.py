@@ -33,6 +33,14 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6, "fp16": 2516.6,
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16 (f32 acc)", "fp16": "f16 (f32 acc)",
          "split_bf16": "bf16x3 hi/lo split (f32 acc)", "split_fp16": "f16x3 hi/lo split (f32 acc)"}
 PRODUCTS = {"split_bf16": 3, "split_fp16": 3}
+# HBM bytes per launch of the bottleneck kernel of the split FP16 form at chi = 16 (16 pair
+# groups per launch), from two rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the
+# factors read off a 1 GiB copy); profiles/hotrg3d_chi16_split_fp16_trace_and_traffic.md.
+# Valid only while that kernel is unchanged.
+GEMM_TRAFFIC_BYTES = {"split_fp16": 6.456e9 + 4.9e6}
+# Algorithmic bytes of the same launch: A operand (2 planes x 4096^2 x 2 B), B chunk
+# (2 planes x 65536 x 4096 x 2 B) and the new-tensor chunk written (4096 x 256 x 4 B).
+GEMM_ALGO_BYTES = {"split_fp16": 2 * 4096 * 4096 * 2 + 2 * 65536 * 4096 * 2 + 4096 * 256 * 4}
 
 
 def fixture_lnz():
@@ -71,6 +79,44 @@ def run_form(P, torch, form, steps, warmup, record_grad=False, finish=True):
     lnz = [r.info(p).lnz_per_site for p in range(1, total + 1)]
     r.close()
     return dict(wall=wall, timings=tm, lnz=lnz, final=final, total_steps=total, grad=grad)
+
+
+def batch_flops(d, chi):
+    """Algorithmic flops of one saturated step of one instance (three-stage contraction)."""
+    x = float(chi)
+    return 2.0 * (x ** 11 + 2 * x ** 9 + 2 * x ** 8) if d == 3 else 2.0 * (x ** 7 + 2 * x ** 6)
+
+
+def run_batch(P, torch, form, steps=20):
+    """The temperature sweep as one batch: 64 x 3D Ising chi = 12 (T = linspace(4, 5, 64)) and
+    48 x 2D Ising (beta = linspace(0.3, 0.6, 48), chi round-robin 16, 24, 32), 20 steps.
+    Times the steps replayed from the recorded graphs (all instances saturated)."""
+    import numpy as np
+    inst = [P.make_instance("ising", 3, 1.0 / T, 12) for T in np.linspace(4.0, 5.0, 64)]
+    chis = (16, 24, 32)
+    inst += [P.make_instance("ising", 2, float(b), chis[i % 3]) for i, b in enumerate(np.linspace(0.3, 0.6, 48))]
+    b = P.HOTRGBatch(inst, precision=form, max_steps=steps)
+    t_start = time.perf_counter()
+    first_timed = 9                      # 2D chi = 32 saturates at step 7; graphs recorded at steps 7, 8
+    for p in range(1, steps + 1):
+        if p == first_timed:
+            b.synchronize()
+            t0 = time.perf_counter()
+        b.step()
+    b.synchronize()
+    t1 = time.perf_counter()
+    lnz = b.log_z()
+    graphs, eager = b.graph_stats()
+    b.close()
+    timed = steps - first_timed + 1
+    ms = (t1 - t0) * 1e3 / timed
+    flops = sum(batch_flops(i.model.d, i.chi) for i in inst)
+    return {"form": form, "instances": len(inst), "steps": steps, "timed_steps": timed,
+            "ms_per_batched_step": round(ms, 3), "batched_steps_per_s": round(1e3 / ms, 4),
+            "instance_steps_per_s": round(len(inst) * 1e3 / ms, 2),
+            "contract_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+            "graph_launches": graphs, "eager_steps": eager, "wall_s_all_steps": round(t1 - t_start, 3),
+            "lnz_per_site_first_last": [lnz[0], lnz[63], lnz[64], lnz[-1]]}
 
 
 def cpu_baseline(sample_pairs=16):
@@ -113,6 +159,8 @@ def main():
     ap.add_argument("--reference-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the timing of the derivative mode")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched temperature sweep")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched temperature sweep (profiling)")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the FP64 reference run (profiling runs of the headline form only)")
     ap.add_argument("--other-forms", default="fp32,split_bf16,fp16,bf16",
@@ -130,6 +178,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     P.lib()
+    if args.batch_only:
+        print(json.dumps({"batch_sweep": run_batch(P, torch, args.form)}), flush=True)
+        return
     ref_lnz = fixture_lnz()
 
     head = run_form(P, torch, args.form, args.steps, args.warmup)
@@ -182,6 +233,8 @@ def main():
                            "cost_vs_forward": round(res["wall"] * 1e3 / fwd_ms, 3) if fwd_ms else None,
                            "dlnz_dbeta_per_site_after_4_steps": res["grad"]}
 
+    batch = None if args.no_batch else run_batch(P, torch, args.form)
+
     out = {
         "metric": METRIC,
         "value": round(contract_tflops, 3),
@@ -213,7 +266,8 @@ def main():
             "issued_frac": round(bott_tflops * PRODUCTS.get(args.form, 1) / peak, 4),
             "avg_launch_ms": round(bott_ms_avg, 4),
             "launches": tm["bottleneck"]["count"],
-            "traffic": None,
+            "traffic": GEMM_TRAFFIC_BYTES.get(args.form),
+            "traffic_algorithmic": GEMM_ALGO_BYTES.get(args.form),
         },
         "fp64_reference": None if args.no_reference else {
             "form": args.reference_form,
@@ -225,6 +279,7 @@ def main():
         },
         "other_forms": forms,
         "derivative_mode": deriv,
+        "batch_sweep": batch,
     }
     if not args.no_cpu:
         cb = cpu_baseline()
