@@ -87,7 +87,7 @@ def batch_flops(d, chi):
     return 2.0 * (x ** 11 + 2 * x ** 9 + 2 * x ** 8) if d == 3 else 2.0 * (x ** 7 + 2 * x ** 6)
 
 
-def run_batch(P, torch, form, steps=20):
+def run_batch(P, torch, form, steps=20, graphs=True):
     """The temperature sweep as one batch: 64 x 3D Ising chi = 12 (T = linspace(4, 5, 64)) and
     48 x 2D Ising (beta = linspace(0.3, 0.6, 48), chi round-robin 16, 24, 32), 20 steps.
     Times the steps replayed from the recorded graphs (all instances saturated)."""
@@ -95,7 +95,7 @@ def run_batch(P, torch, form, steps=20):
     inst = [P.make_instance("ising", 3, 1.0 / T, 12) for T in np.linspace(4.0, 5.0, 64)]
     chis = (16, 24, 32)
     inst += [P.make_instance("ising", 2, float(b), chis[i % 3]) for i, b in enumerate(np.linspace(0.3, 0.6, 48))]
-    b = P.HOTRGBatch(inst, precision=form, max_steps=steps)
+    b = P.HOTRGBatch(inst, precision=form, max_steps=steps, graphs=graphs)
     t_start = time.perf_counter()
     first_timed = 9                      # 2D chi = 32 saturates at step 7; graphs recorded at steps 7, 8
     for p in range(1, steps + 1):
@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the timing of the derivative mode")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched temperature sweep")
     ap.add_argument("--batch-only", action="store_true", help="only the batched temperature sweep (profiling)")
+    ap.add_argument("--batch-no-graphs", action="store_true",
+                    help="batched sweep enqueued kernel by kernel (for kernel tracing)")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the FP64 reference run (profiling runs of the headline form only)")
     ap.add_argument("--other-forms", default="fp32,split_bf16,fp16,bf16",
@@ -179,7 +181,7 @@ def main():
         sys.exit(1)
     P.lib()
     if args.batch_only:
-        print(json.dumps({"batch_sweep": run_batch(P, torch, args.form)}), flush=True)
+        print(json.dumps({"batch_sweep": run_batch(P, torch, args.form, graphs=not args.batch_no_graphs)}), flush=True)
         return
     ref_lnz = fixture_lnz()
 

@@ -401,7 +401,8 @@ class HOTRGBatch:
     >>> b.run(20); b.log_z()
     """
 
-    def __init__(self, instances, precision: str = "fp64", max_steps: int = 64, chunk: int = 0):
+    def __init__(self, instances, precision: str = "fp64", max_steps: int = 64, chunk: int = 0,
+                 graphs: bool = True):
         import torch
 
         self.instances = list(instances)
@@ -413,10 +414,16 @@ class HOTRGBatch:
         self.workspace_bytes = nbytes
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         aligned = (self.workspace.data_ptr() + 255) // 256 * 256
-        self.stream = torch.cuda.Stream()
-        # the workspace was allocated on the current stream: make ours wait for that
-        self.stream.wait_stream(torch.cuda.current_stream())
-        self.handle = hotrg_batch_init(self.instances, self.opts, aligned, nbytes, self.stream.cuda_stream)
+        if graphs:
+            self.stream = torch.cuda.Stream()
+            # the workspace was allocated on the current stream: make ours wait for that
+            self.stream.wait_stream(torch.cuda.current_stream())
+            stream_ptr = self.stream.cuda_stream
+        else:
+            # the NULL stream cannot be recorded: every step is enqueued kernel by kernel
+            self.stream = torch.cuda.default_stream()
+            stream_ptr = 0
+        self.handle = hotrg_batch_init(self.instances, self.opts, aligned, nbytes, stream_ptr)
         self.steps = 0
 
     def step(self) -> None:

@@ -264,6 +264,17 @@ unsigned grid_for(long n, int block = 256) {
   return (unsigned)std::max(1L, std::min(g, 65536L));
 }
 
+// Multi-workgroup tridiagonalisation of the large matrices of an eigensolver batch (one
+// launch per reflector); k_eigh_tri then finishes every matrix.
+void enqueue_tri_steps(const EigBatch& eb, hipStream_t s) {
+  int maxn = 0;
+  for (int i = 0; i < eb.count; ++i) maxn = std::max(maxn, eb.n[i]);
+  if (maxn < TRI_MULTI_N) return;
+  const unsigned gx = (unsigned)((maxn - 1 + TRI_ROWS - 1) / TRI_ROWS);
+  for (int st = 0; st <= maxn - 2; ++st)
+    hipLaunchKernelGGL(k_tri_step, dim3(gx, (unsigned)eb.count), dim3(256), 0, s, eb, st);
+}
+
 }  // namespace
 
 struct hotrg_handle {
@@ -473,6 +484,12 @@ int enqueue_gram(hotrg_handle* h, const void* T, bool t_is_f64, const LocalDims&
   return HOTRG_OK;
 }
 
+// The one-workgroup-per-(c, g) non-prime chain holds a thread per (nh1, nc1) pair and
+// chi2 x chi2 x k2 <= 16 x 16 x 16 register/LDS blocks.
+inline bool nstage3c_ok(const Dims& dm) {
+  return dm.chi1 <= 16 && dm.chi2 <= 16 && dm.k1 <= 16 && dm.k2 <= 16;
+}
+
 // Contraction (prime chain, bottleneck, non-prime chain + rename) for form F.
 template <int F>
 int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDims& ld, const int* k) {
@@ -545,7 +562,10 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     hipEvent_t t2 = tmark(h);
     const long ncell = (long)dm.chic * (pr1 - pr0) * dm.chic;   // (c, g) blocks
     const int g0 = (int)(pr0 * dm.chic), gcount = (int)((pr1 - pr0) * dm.chic);
-    if (ld.d == 3)
+    if (ld.d == 3 && nstage3c_ok(dm))
+      hipLaunchKernelGGL((k_nstage3c<AT, MT, UT>), dim3((unsigned)(dm.chic * gcount)), dim3(256), 0, h->s,
+                         (const AT*)Cc, Np, (const UT*)U1, (const UT*)U2, dm, g0, gcount, Tn);
+    else if (ld.d == 3)
       hipLaunchKernelGGL((k_nstage3b<AT, MT, UT>), dim3((unsigned)(dm.chic * ((gcount + 7) / 8))), dim3(256), 0,
                          h->s, (const AT*)Cc, Np, (const UT*)U1, (const UT*)U2, dm, g0, gcount, Tn);
     else
@@ -643,7 +663,17 @@ int enqueue_contract_grad(hotrg_handle* h, const void* Tv, void* Tnv, const void
     if (h->profiling) h->acc.flops_bottleneck += 3.0 * 2.0 * (double)H * (double)ncols * (double)H;
     hipEvent_t t2 = tmark(h);
     const int g0 = ip0 * dm.chic, gcount = (ip1 - ip0) * dm.chic;
-    if (ld.d == 3) {
+    if (ld.d == 3 && nstage3c_ok(dm)) {
+      const dim3 g((unsigned)(dm.chic * gcount));
+      hipLaunchKernelGGL((k_nstage3c<MT, MT, UT, false>), g, dim3(256), 0, h->s, (const MT*)Cc, Np, U1, U2, dm, g0,
+                         gcount, Tn);
+      hipLaunchKernelGGL((k_nstage3c<MT, MT, UT, false>), g, dim3(256), 0, h->s, (const MT*)dCc, Np, U1, U2, dm,
+                         g0, gcount, dTn);
+      hipLaunchKernelGGL((k_nstage3c<MT, MT, UT, true>), g, dim3(256), 0, h->s, (const MT*)Cc, Np, dU1, U2, dm, g0,
+                         gcount, dTn);
+      hipLaunchKernelGGL((k_nstage3c<MT, MT, UT, true>), g, dim3(256), 0, h->s, (const MT*)Cc, Np, U1, dU2, dm, g0,
+                         gcount, dTn);
+    } else if (ld.d == 3) {
       const dim3 g((unsigned)(dm.chic * ((gcount + 7) / 8)));
       hipLaunchKernelGGL((k_nstage3b<MT, MT, UT, false>), g, dim3(256), 0, h->s, (const MT*)Cc, Np, U1, U2, dm, g0,
                          gcount, Tn);
@@ -1046,6 +1076,7 @@ int hotrg_step(hotrg_handle* h, int axis) {
       eb.n[i] = eig[i].n; eb.kvec[i] = eig[i].kvec; eb.A[i] = eig[i].A; eb.w[i] = eig[i].w;
       eb.V[i] = eig[i].V; eb.scratch[i] = eig[i].scratch;
     }
+    enqueue_tri_steps(eb, h->s);
     hipLaunchKernelGGL(k_eigh_tri, dim3(ne), dim3(EIG_THREADS), 0, h->s, eb);
   }
   rc = enqueue_step_back(h, sp, t_dec);
@@ -1337,6 +1368,7 @@ int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_d
     eb.V[b] = V_dev + (size_t)b * n * n;
     eb.scratch[b] = (double*)workspace + (size_t)b * 2 * n * n;
   }
+  enqueue_tri_steps(eb, s);
   hipLaunchKernelGGL(k_eigh_tri, dim3(batch), dim3(EIG_THREADS), 0, s, eb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
@@ -1481,12 +1513,19 @@ static int batch_table(hotrg_batch* b, const std::vector<EigDesc>& descs, const 
 
 // One step of every instance: records and Gram matrices of all, one eigensolver launch,
 // then choice, contraction, trace and normalisation of each in turn.
-static int batch_enqueue(hotrg_batch* b, const std::vector<StepPlan>& sps, int ndesc, const EigDesc* table) {
+static int batch_enqueue(hotrg_batch* b, const std::vector<StepPlan>& sps, int ndesc, const EigDesc* table,
+                         int maxn) {
   for (int i = 0; i < b->n; ++i) {
     const int rc = enqueue_step_front(b->inst[i], -1);
     if (rc) return batch_fail(b, rc, "instance " + std::to_string(i) + ": " + b->inst[i]->err);
   }
-  if (ndesc > 0) hipLaunchKernelGGL(k_eigh_list, dim3((unsigned)ndesc), dim3(EIG_THREADS), 0, b->s, table);
+  if (ndesc > 0) {
+    if (maxn >= TRI_MULTI_N)
+      for (int st = 0; st <= maxn - 2; ++st)
+        hipLaunchKernelGGL(k_tri_step_list, dim3((unsigned)((maxn - 1 + TRI_ROWS - 1) / TRI_ROWS), (unsigned)ndesc),
+                           dim3(256), 0, b->s, table, st);
+    hipLaunchKernelGGL(k_eigh_list, dim3((unsigned)ndesc), dim3(EIG_THREADS), 0, b->s, table);
+  }
   for (int i = 0; i < b->n; ++i) {
     const int rc = enqueue_step_back(b->inst[i], sps[i], nullptr);
     if (rc) return batch_fail(b, rc, "instance " + std::to_string(i) + ": " + b->inst[i]->err);
@@ -1510,6 +1549,8 @@ int hotrg_batch_step(hotrg_batch* b) {
     for (int k = 0; k < c; ++k) descs.push_back(e[k]);
     if (!same_dims(sps[i].ld, sps[i].nl)) steady = false;
   }
+  int maxn = 0;
+  for (const auto& e : descs) maxn = std::max(maxn, e.n);
   const EigDesc* table = nullptr;
   int rc = batch_table(b, descs, &table);
   if (rc) return rc;
@@ -1520,7 +1561,7 @@ int hotrg_batch_step(hotrg_batch* b) {
     if (!b->graph[parity]) {
       if (hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return batch_fail(b, HOTRG_E_DEVICE, "stream capture could not begin");
-      rc = batch_enqueue(b, sps, (int)descs.size(), table);
+      rc = batch_enqueue(b, sps, (int)descs.size(), table, maxn);
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(b->s, &g);
       if (rc) {
@@ -1539,7 +1580,7 @@ int hotrg_batch_step(hotrg_batch* b) {
       return batch_fail(b, HOTRG_E_DEVICE, "graph launch failed");
     b->graph_launches += 1;
   } else {
-    rc = batch_enqueue(b, sps, (int)descs.size(), table);
+    rc = batch_enqueue(b, sps, (int)descs.size(), table, maxn);
     if (rc) return rc;
     b->eager_steps += 1;
   }

@@ -631,15 +631,21 @@ struct EigDesc {
   double* scratch;
 };
 
+// tridiag_done: the tridiagonal form was built by k_tri_step (multi-workgroup, large n):
+// reflectors in R, diagonal and subdiagonal at Z[0, n) and Z[n, 2n).
 __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ A, double* __restrict__ w,
-                              double* __restrict__ V, double* __restrict__ R) {
+                              double* __restrict__ V, double* __restrict__ R, const bool tridiag_done) {
   __shared__ double d[EIG_MAXN], e[EIG_MAXN], vv[EIG_MAXN], qv[EIG_MAXN];
   __shared__ double red[EIG_THREADS / 64];
   double* Z = R + (long)n * n;                          // reflector k at R[k n ..]; tridiagonal eigenvector i at Z[i n ..)
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
 
   // ---- 1. tridiagonalisation --------------------------------------------------
-  for (int k = 0; k + 2 < n; ++k) {
+  if (tridiag_done) {
+    for (int i = tid; i < n; i += nt) { d[i] = Z[i]; e[i] = Z[n + i]; }
+    __syncthreads();
+  }
+  for (int k = 0; !tridiag_done && k + 2 < n; ++k) {
     const int m = n - k - 1;
     double x = 0.0, ss = 0.0;
     for (int i = tid; i < m; i += nt) {
@@ -687,17 +693,19 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    if (n >= 2) {
-      d[n - 2] = A[(long)(n - 2) * n + (n - 2)];
-      e[n - 2] = A[(long)(n - 1) * n + (n - 2)];
+  if (!tridiag_done) {
+    if (tid == 0) {
+      if (n >= 2) {
+        d[n - 2] = A[(long)(n - 2) * n + (n - 2)];
+        e[n - 2] = A[(long)(n - 1) * n + (n - 2)];
+      }
+      d[n - 1] = A[(long)(n - 1) * n + (n - 1)];
+      e[n - 1] = 0.0;
     }
-    d[n - 1] = A[(long)(n - 1) * n + (n - 1)];
-    e[n - 1] = 0.0;
+    for (int k = (n >= 2 ? n - 2 : 0); k < n; ++k)
+      for (int i = tid; i < n; i += nt) R[(long)k * n + i] = 0.0;   // no reflector for the last two
+    __syncthreads();
   }
-  for (int k = (n >= 2 ? n - 2 : 0); k < n; ++k)
-    for (int i = tid; i < n; i += nt) R[(long)k * n + i] = 0.0;   // no reflector for the last two
-  __syncthreads();
 
   // ---- 2. eigenvalues by bisection (descending) -------------------------------
   double tnorm = 0.0, lo = 0.0, hi = 0.0;
@@ -843,17 +851,130 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
   }
 }
 
+// Matrices of at least TRI_MULTI_N rows are tridiagonalised by k_tri_step (many workgroups
+// per matrix, one launch per reflector) before the one-workgroup kernels below finish them;
+// smaller ones are done entirely by one workgroup.
+constexpr int TRI_MULTI_N = 128;
+
 // Up to four matrices passed by value (one coarse-graining step of one instance).
 __global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
   const int b = blockIdx.x;
-  eigh_tri_body(eb.n[b], eb.kvec[b], eb.A[b], eb.w[b], eb.V[b], eb.scratch[b]);
+  eigh_tri_body(eb.n[b], eb.kvec[b], eb.A[b], eb.w[b], eb.V[b], eb.scratch[b], eb.n[b] >= TRI_MULTI_N);
 }
 
 // Any number of matrices from a descriptor table in device memory (a step of a batch of
 // instances: one launch for all their decompositions).
 __global__ __launch_bounds__(EIG_THREADS) void k_eigh_list(const EigDesc* __restrict__ list) {
   const EigDesc ds = list[blockIdx.x];
-  eigh_tri_body(ds.n, ds.kvec, ds.A, ds.w, ds.V, ds.scratch);
+  eigh_tri_body(ds.n, ds.kvec, ds.A, ds.w, ds.V, ds.scratch, ds.n >= TRI_MULTI_N);
+}
+
+// ---------------------------------------------------------------------------
+// Householder tridiagonalisation with many workgroups per matrix: launch s (s = 0 .. n-2)
+// applies the rank-2 update of reflector s-1 to the trailing block [s+1, n)^2 and, fused
+// with it, the product q_s = A' v_s of reflector s, row by row (each element is read and
+// written once per reflector).  Every workgroup rebuilds the small vectors it needs:
+// v_{s-1} (stored by launch s-1), p_{s-1} = q_{s-1} - (v_{s-1} . q_{s-1}) v_{s-1}, the
+// updated column s, and from it v_s.  Same reflector convention as the one-workgroup
+// solver (H = I - 2 v v^T, |v| = 1).  Scratch: R (reflectors), Z[0, n) diagonal,
+// Z[n, 2n) subdiagonal, Z[2n, 3n) and Z[3n, 4n) the q vectors of alternate launches.
+// ---------------------------------------------------------------------------
+constexpr int TRI_ROWS = 16;   // trailing-block rows per workgroup (4 per wave)
+
+__device__ inline double block_sum256(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+__device__ void tri_step(const int n, double* __restrict__ A, double* __restrict__ R, const int s) {
+  if (n < TRI_MULTI_N || s > n - 2) return;
+  __shared__ double vp[EIG_MAXN], pp[EIG_MAXN], vs[EIG_MAXN];
+  __shared__ double red[4];
+  double* Z = R + (long)n * n;
+  const int tid = threadIdx.x;
+  const int r0 = s + 1 + blockIdx.x * TRI_ROWS;           // first row of this workgroup
+  if (r0 >= n && !(blockIdx.x == 0)) return;
+  // previous reflector and p over rows [s, n)
+  const double* qprev = Z + 2 * n + ((s - 1) & 1) * n;
+  double cp = 0.0;
+  for (int i = s + tid; i < n; i += 256) {
+    const double v = s > 0 ? R[(long)(s - 1) * n + i] : 0.0;
+    const double q = s > 0 ? qprev[i] : 0.0;
+    vp[i] = v;
+    pp[i] = q;
+    cp += v * q;
+  }
+  const double c = block_sum256(cp, red);                   // (barrier inside)
+  for (int i = s + tid; i < n; i += 256) pp[i] -= c * vp[i];
+  __syncthreads();
+  // updated column s, rows [s, n): y_i = A[i][s] - 2 (v_i p_s + p_i v_s)
+  const double vps = vp[s], pps = pp[s];
+  double tl = 0.0;
+  for (int i = s + tid; i < n; i += 256) {
+    const double y = A[(long)i * n + s] - 2.0 * (vp[i] * pps + pp[i] * vps);
+    vs[i] = y;
+    if (i >= s + 2) tl += y * y;
+  }
+  const double tail = block_sum256(tl, red);
+  if (s == n - 2) {                                          // last: the 2 x 2 trailing block
+    if (blockIdx.x == 0 && tid == 0) {
+      Z[n - 2] = vs[n - 2];
+      Z[n + n - 2] = vs[n - 1];
+      Z[n - 1] = A[(long)(n - 1) * n + (n - 1)] - 4.0 * vp[n - 1] * pp[n - 1];
+      Z[n + n - 1] = 0.0;
+    }
+    if (blockIdx.x == 0)
+      for (int i = tid; i < 2 * n; i += 256) R[(long)(n - 2) * n + i] = 0.0;
+    return;
+  }
+  const double x0 = vs[s + 1], ds_ = vs[s];
+  const bool refl = tail > 0.0;
+  const double sigma = x0 * x0 + tail;
+  const double alpha = (x0 >= 0.0 ? -1.0 : 1.0) * sqrt(sigma);
+  const double inv = refl ? 1.0 / sqrt(2.0 * (sigma - x0 * alpha)) : 0.0;
+  __syncthreads();
+  for (int i = s + 1 + tid; i < n; i += 256) vs[i] = (i == s + 1 ? x0 - alpha : vs[i]) * inv;
+  if (tid == 0) vs[s] = 0.0;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int i = tid; i < n; i += 256) R[(long)s * n + i] = i > s ? vs[i] : 0.0;
+    if (tid == 0) {
+      Z[s] = ds_;
+      Z[n + s] = refl ? alpha : x0;
+    }
+  }
+  if (r0 >= n) return;
+  // rows of this workgroup: update and q_s
+  double* qcur = Z + 2 * n + (s & 1) * n;
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int rr = wv; rr < TRI_ROWS; rr += 4) {
+    const int i = r0 + rr;
+    if (i >= n) break;
+    double* row = A + (long)i * n;
+    const double vi = vp[i], pi = pp[i];
+    double acc = 0.0;
+    for (int j = s + 1 + lane; j < n; j += 64) {
+      const double a = row[j] - 2.0 * (vi * pp[j] + pi * vp[j]);
+      row[j] = a;
+      acc += a * vs[j];
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) qcur[i] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tri_step(EigBatch eb, int s) {
+  const int b = blockIdx.y;
+  if (b >= eb.count) return;
+  tri_step(eb.n[b], eb.A[b], eb.scratch[b], s);
+}
+
+__global__ __launch_bounds__(256) void k_tri_step_list(const EigDesc* __restrict__ list, int s) {
+  const EigDesc ds = list[blockIdx.y];
+  tri_step(ds.n, ds.A, ds.scratch, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1130,6 +1251,57 @@ __global__ __launch_bounds__(256) void k_pstage3v(const MT* __restrict__ T, cons
         Store<F>::put4(B, row * ldb + (long)rho * b + r0, bplane, v);
       }
     }
+  }
+}
+
+// Non-prime chain (3D), one workgroup per (c, g), for chi_1^2 <= 256: thread (nh1', nc1')
+// reads its chi_2 x chi_2 sub-block of C straight from memory (each element once) and
+// contracts it with U2 (from LDS, the same address for every lane) into registers
+// W[n2] = sum_{nh2, nc2} C[(nh1, nh2)][(nc1, nc2)] U2[nh2 + chi2 nc2][n2]; then
+// T^next[(n1, n2, c)][g] = sum_{nh1, nc1} U1[nh1 + chi1 nc1][n1] W[nh1][nc1][n2].
+template <class AT, class MT, class UT, bool ACC = false>
+__global__ __launch_bounds__(256) void k_nstage3c(const AT* __restrict__ C, long ldc, const UT* __restrict__ U1,
+                                                  const UT* __restrict__ U2, Dims dm, int g0, int gcount,
+                                                  MT* __restrict__ Tn) {
+  __shared__ AT u1s[256 * 16];   // [nh1 + chi1 nc1][n1]
+  __shared__ AT u2s[256 * 16];   // [nh2 + chi2 nc2][n2]
+  __shared__ AT W[256 * 16];     // [nh1 chi1 + nc1][n2]
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x / gcount, gl = blockIdx.x % gcount;
+  const int b = dm.b, chi1 = dm.chi1, chi2 = dm.chi2, k1 = dm.k1, k2 = dm.k2;
+  const int Hn = k1 * k2 * dm.chic;
+  for (int i = tid; i < chi1 * chi1 * k1; i += 256) u1s[i] = (AT)U1[i];
+  for (int i = tid; i < chi2 * chi2 * k2; i += 256) u2s[i] = (AT)U2[i];
+  __syncthreads();
+  if (tid < chi1 * chi1) {
+    const int nh1 = tid / chi1, nc1 = tid % chi1;
+    AT w[16];
+#pragma unroll
+    for (int n2 = 0; n2 < 16; ++n2) w[n2] = 0;
+    const AT* Cb = C + (long)(c * b + nh1 * chi2) * ldc + (long)gl * b + nc1 * chi2;
+    for (int nh2 = 0; nh2 < chi2; ++nh2) {
+      const AT* Cr = Cb + (long)nh2 * ldc;
+      for (int nc2 = 0; nc2 < chi2; ++nc2) {
+        const AT x = Cr[nc2];
+        const AT* u = &u2s[(nh2 + chi2 * nc2) * k2];
+#pragma unroll
+        for (int n2 = 0; n2 < 16; ++n2)
+          if (n2 < k2) w[n2] += x * u[n2];
+      }
+    }
+#pragma unroll
+    for (int n2 = 0; n2 < 16; ++n2)
+      if (n2 < k2) W[tid * k2 + n2] = w[n2];
+  }
+  __syncthreads();
+  if (tid < k1 * k2) {
+    const int n1 = tid / k2, n2 = tid % k2;
+    AT acc = 0;
+    for (int nh1 = 0; nh1 < chi1; ++nh1)
+      for (int nc1 = 0; nc1 < chi1; ++nc1)
+        acc += u1s[(nh1 + chi1 * nc1) * k1 + n1] * W[(nh1 * chi1 + nc1) * k2 + n2];
+    MT* o = &Tn[(long)((n1 * k2 + n2) * dm.chic + c) * Hn + (g0 + gl)];
+    if constexpr (ACC) *o += (MT)acc; else *o = (MT)acc;
   }
 }
 
