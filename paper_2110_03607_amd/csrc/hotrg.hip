@@ -87,8 +87,22 @@ GramGeo gram_geo(long H, long R) {
 
 // Byte sizes of every workspace region for given dims (max over the run is allocated).
 struct Need {
-  size_t T, Aop, Bop, Cc, X, part, G, Amat, w, Ut;
+  size_t T, Aop, Bop, Cc, X, part, G, Amat, w, Ut, comb;
 };
+
+// The third Gram step as a GEMM (large directions): P[(fh, gh)][(r, e)] from Gh, Q likewise
+// from Gc, S = P Q^T, then A[fh + chi fc][gh + chi gc] = S[(fh, gh)][(fc, gc)].
+constexpr long COMB_GEMM_N = 512;
+struct CombGeo {
+  long n, Mp, Kp;
+};
+inline CombGeo comb_geo(long chis, long chic) {
+  CombGeo c;
+  c.n = chis * chis;
+  c.Mp = roundup(c.n, 128);
+  c.Kp = roundup(chic * chic, 16);
+  return c;
+}
 
 // Derivative mode doubles the operand rows ([dT | T] and [C2 | dC2]) and the product chunk.
 inline int grad_mult(bool grad) { return grad ? 2 : 1; }
@@ -129,6 +143,10 @@ Need need_for(const LocalDims& ld, int chi, int form, int user_chunk, bool grad 
     G = std::max(G, (size_t)g.R * g.R * 8);
     const long nn = (long)ld.chi[j] * ld.chi[j];
     Am = std::max(Am, (size_t)nn * nn * 8);
+    if (nn >= COMB_GEMM_N) {
+      const CombGeo cg = comb_geo(ld.chi[j], ld.chi[0]);
+      n.comb = std::max(n.comb, (size_t)(2 * cg.Mp * cg.Kp + cg.Mp * cg.Mp) * 8);
+    }
   }
   n.X = X;
   n.part = part;
@@ -144,6 +162,7 @@ void need_max(Need& a, const Need& b) {
   a.Cc = std::max(a.Cc, b.Cc); a.X = std::max(a.X, b.X); a.part = std::max(a.part, b.part);
   a.G = std::max(a.G, b.G); a.Amat = std::max(a.Amat, b.Amat); a.w = std::max(a.w, b.w);
   a.Ut = std::max(a.Ut, b.Ut);
+  a.comb = std::max(a.comb, b.comb);
 }
 
 // All bond dimensions a run can reach: q, then min(x^2, chi) repeatedly.
@@ -161,7 +180,7 @@ std::vector<int> reachable_dims(int q, int chi) {
 struct Plan {
   Need need;
   size_t off_state, off_rec, off_T, off_Tn, off_Aop, off_Bop, off_Cc, off_X, off_part, off_Gh, off_Gc,
-      off_A, off_Vw, off_Vo, off_w, off_Ut, off_Ut32, total;
+      off_A, off_Vw, off_Vo, off_w, off_Ut, off_Ut32, off_comb, total;
   // derivative mode (0 when off)
   size_t off_dT, off_dTn, off_dCc, off_Xd, off_dGh, off_dGc, off_dA, off_dUt, off_dUt32, off_dUw;
   bool grad;
@@ -224,6 +243,7 @@ void place_scratch(Plan& P, size_t& o, const Need& nd, bool grad) {
   P.off_part = take_at(o, nd.part);
   P.off_Gh = take_at(o, nd.G);
   P.off_Gc = take_at(o, nd.G);
+  P.off_comb = take_at(o, nd.comb);
   if (grad) {
     P.off_dCc = take_at(o, nd.Cc);
     P.off_Xd = take_at(o, nd.X);
@@ -474,8 +494,38 @@ int enqueue_gram(hotrg_handle* h, const void* T, bool t_is_f64, const LocalDims&
     }
   }
   const long n = (long)ld.chi[j] * ld.chi[j];
-  hipLaunchKernelGGL(k_gram_combine, dim3(grid_for(n * n)), dim3(256), 0, h->s, (const double*)Gh,
-                     (const double*)Gc, ld.chi[j], ld.chi[0], A_out);
+  if (n >= COMB_GEMM_N) {
+    const long chis = ld.chi[j], chic = ld.chi[0];
+    const CombGeo cg = comb_geo(chis, chic);
+    double* Pm = h->at<double>(h->plan.off_comb);
+    double* Qm = Pm + cg.Mp * cg.Kp;
+    double* Sm = Qm + cg.Mp * cg.Kp;
+    PermSpec pq{};                      // P[(fh, gh)][(r, e)] = G[(fh chic + r) R + gh chic + e]
+    pq.nd = 4; pq.nrow = 2;
+    pq.od[0] = (int)chis; pq.sstride[0] = chic * R;
+    pq.od[1] = (int)chis; pq.sstride[1] = chic;
+    pq.od[2] = (int)chic; pq.sstride[2] = R;
+    pq.od[3] = (int)chic; pq.sstride[3] = 1;
+    pq.rows = n; pq.cols = chic * chic; pq.rows_p = cg.Mp; pq.ldd = cg.Kp;
+    hipLaunchKernelGGL((k_permute<double, double>), dim3(grid_for(cg.Mp * cg.Kp)), dim3(256), 0, h->s,
+                       (const double*)Gh, Pm, pq, 1.0);
+    hipLaunchKernelGGL((k_permute<double, double>), dim3(grid_for(cg.Mp * cg.Kp)), dim3(256), 0, h->s,
+                       (const double*)Gc, Qm, pq, 1.0);
+    launch_gemm<F_FP64>(Pm, cg.Kp, 0, Qm, cg.Kp, 0, Sm, cg.Mp, 0, cg.Mp, cg.Mp, cg.Kp, 1, cg.Kp, nullptr, 1.0,
+                        h->s);
+    PermSpec pa{};                      // A[(fc, fh)][(gc, gh)] = S[(fh, gh)][(fc, gc)]
+    pa.nd = 4; pa.nrow = 2;
+    pa.od[0] = (int)chis; pa.sstride[0] = chis;
+    pa.od[1] = (int)chis; pa.sstride[1] = chis * cg.Mp;
+    pa.od[2] = (int)chis; pa.sstride[2] = 1;
+    pa.od[3] = (int)chis; pa.sstride[3] = cg.Mp;
+    pa.rows = n; pa.cols = n; pa.rows_p = n; pa.ldd = n;
+    hipLaunchKernelGGL((k_permute<double, double>), dim3(grid_for(n * n)), dim3(256), 0, h->s, (const double*)Sm,
+                       A_out, pa, 1.0);
+  } else {
+    hipLaunchKernelGGL(k_gram_combine, dim3(grid_for(n * n)), dim3(256), 0, h->s, (const double*)Gh,
+                       (const double*)Gc, ld.chi[j], ld.chi[0], A_out);
+  }
   if (dT)
     hipLaunchKernelGGL(k_gram_combine_t, dim3(grid_for(n * n)), dim3(256), 0, h->s, (const double*)Gh,
                        (const double*)Gc, (const double*)h->at<double>(h->plan.off_dGh),
@@ -1231,6 +1281,7 @@ static Plan debug_plan(int d, const int* dims, const int* kdims, int form) {
   P.off_part = take(nd.part);
   P.off_Gh = take(nd.G);
   P.off_Gc = take(nd.G);
+  P.off_comb = take(nd.comb);
   P.off_A = take(EIG_SLOTS * nd.Amat);
   P.off_Vw = take(EIG_SLOTS * 2 * nd.Amat);
   P.off_Vo = take(EIG_SLOTS * nd.Amat);

@@ -1279,6 +1279,27 @@ __global__ __launch_bounds__(256) void k_nstage3c(const AT* __restrict__ C, long
 #pragma unroll
     for (int n2 = 0; n2 < 16; ++n2) w[n2] = 0;
     const AT* Cb = C + (long)(c * b + nh1 * chi2) * ldc + (long)gl * b + nc1 * chi2;
+    if constexpr (sizeof(AT) == 4) {
+      if (chi2 % 4 == 0) {
+        // the chi2 consecutive entries of a row of the sub-block as 16-byte loads (aligned:
+        // ldc, b and chi2 are multiples of 4)
+        for (int nh2 = 0; nh2 < chi2; ++nh2) {
+          const f4v* Cr = reinterpret_cast<const f4v*>(Cb + (long)nh2 * ldc);
+          for (int q4 = 0; q4 < chi2 / 4; ++q4) {
+            const f4v x4 = Cr[q4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const AT x = x4[e];
+              const AT* u = &u2s[(nh2 + chi2 * (4 * q4 + e)) * k2];
+#pragma unroll
+              for (int n2 = 0; n2 < 16; ++n2)
+                if (n2 < k2) w[n2] += x * u[n2];
+            }
+          }
+        }
+        goto contracted;
+      }
+    }
     for (int nh2 = 0; nh2 < chi2; ++nh2) {
       const AT* Cr = Cb + (long)nh2 * ldc;
       for (int nc2 = 0; nc2 < chi2; ++nc2) {
@@ -1289,6 +1310,7 @@ __global__ __launch_bounds__(256) void k_nstage3c(const AT* __restrict__ C, long
           if (n2 < k2) w[n2] += x * u[n2];
       }
     }
+  contracted:
 #pragma unroll
     for (int n2 = 0; n2 < 16; ++n2)
       if (n2 < k2) W[tid * k2 + n2] = w[n2];
