@@ -95,7 +95,9 @@ def run_batch(P, torch, form, steps=20, graphs=True):
     inst = [P.make_instance("ising", 3, 1.0 / T, 12) for T in np.linspace(4.0, 5.0, 64)]
     chis = (16, 24, 32)
     inst += [P.make_instance("ising", 2, float(b), chis[i % 3]) for i, b in enumerate(np.linspace(0.3, 0.6, 48))]
-    b = P.HOTRGBatch(inst, precision=form, max_steps=steps, graphs=graphs)
+    t_tune = time.perf_counter()
+    b = P.HOTRGBatch(inst, precision=form, max_steps=steps, graphs=graphs, tune=True)
+    tune_s = time.perf_counter() - t_tune
     t_start = time.perf_counter()
     first_timed = 9                      # 2D chi = 32 saturates at step 7; graphs recorded at steps 7, 8
     for p in range(1, steps + 1):
@@ -107,6 +109,7 @@ def run_batch(P, torch, form, steps=20, graphs=True):
     t1 = time.perf_counter()
     lnz = b.log_z()
     graphs, eager = b.graph_stats()
+    b_tuned = b.tuned
     b.close()
     timed = steps - first_timed + 1
     ms = (t1 - t0) * 1e3 / timed
@@ -116,6 +119,7 @@ def run_batch(P, torch, form, steps=20, graphs=True):
             "instance_steps_per_s": round(len(inst) * 1e3 / ms, 2),
             "contract_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
             "graph_launches": graphs, "eager_steps": eager, "wall_s_all_steps": round(t1 - t_start, 3),
+            "autotuner": {"seconds": round(tune_s, 3), "classes": b_tuned},
             "lnz_per_site_first_last": [lnz[0], lnz[63], lnz[64], lnz[-1]]}
 
 

@@ -245,6 +245,20 @@ int hotrg_batch_step(hotrg_batch* b);
  * (may be NULL).  Device errors of any instance surface here (HOTRG_E_NUMERIC, ...). */
 int hotrg_batch_log_z(hotrg_batch* b, double* lnz_per_site, int* steps_done);
 
+/* Autotuner (optional, before the first step; synchronises): for every distinct (d, chi)
+ * among the instances, times the saturated new-tensor contraction of one of them with each
+ * candidate launch shape (GEMM tiles of 256 x 256 or 128 x 128 for the 16-bit forms; column
+ * chunks of the planned size, 1/2 and 1/4 of it) and keeps the fastest for that class.
+ * *nclasses (may be NULL) receives the number of classes.  Errors: HOTRG_E_STATE after the
+ * first step, HOTRG_E_DEVICE. */
+int hotrg_batch_tune(hotrg_batch* b, int* nclasses);
+
+/* Result of the autotuner for class cls (0 .. nclasses-1): d, chi, the GEMM tile edge used
+ * (256 or 128; always 128 in the FP64 and FP32 forms), pair groups per chunk, and the
+ * contraction time in ms.  Any output pointer may be NULL.  HOTRG_E_ARG if cls is out of
+ * range. */
+int hotrg_batch_tuning(hotrg_batch* b, int cls, int* d, int* chi, int* gemm_tile, int* chunk_pairs, double* ms);
+
 /* Steps run as graph launches and steps enqueued kernel by kernel so far. */
 int hotrg_batch_info(hotrg_batch* b, int* graph_launches, int* eager_steps);
 

@@ -101,6 +101,10 @@ _SIGS = {
                                          ctypes.POINTER(ctypes.c_int)]),
     "hotrg_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "hotrg_batch_instance": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.c_int]),
+    "hotrg_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
+    "hotrg_batch_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
     "hotrg_batch_destroy": (None, [ctypes.c_void_p]),
     "hotrg_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "hotrg_debug_eigh": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
@@ -271,6 +275,21 @@ def hotrg_batch_info(b):
     return g.value, e.value
 
 
+def hotrg_batch_tune(b) -> int:
+    n = ctypes.c_int()
+    _check_batch(lib().hotrg_batch_tune(b, ctypes.byref(n)), b)
+    return n.value
+
+
+def hotrg_batch_tuning(b, cls: int) -> dict:
+    d, chi, tile, chunk = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    ms = ctypes.c_double()
+    _check_batch(lib().hotrg_batch_tuning(b, cls, ctypes.byref(d), ctypes.byref(chi), ctypes.byref(tile),
+                                          ctypes.byref(chunk), ctypes.byref(ms)), b)
+    return {"d": d.value, "chi": chi.value, "gemm_tile": tile.value, "chunk_pairs": chunk.value,
+            "contract_ms": ms.value}
+
+
 def hotrg_batch_instance(b, i: int):
     return ctypes.c_void_p(lib().hotrg_batch_instance(b, i))
 
@@ -402,7 +421,7 @@ class HOTRGBatch:
     """
 
     def __init__(self, instances, precision: str = "fp64", max_steps: int = 64, chunk: int = 0,
-                 graphs: bool = True):
+                 graphs: bool = True, tune: bool = False):
         import torch
 
         self.instances = list(instances)
@@ -425,6 +444,10 @@ class HOTRGBatch:
             stream_ptr = 0
         self.handle = hotrg_batch_init(self.instances, self.opts, aligned, nbytes, stream_ptr)
         self.steps = 0
+        self.tuned = []
+        if tune:
+            n = hotrg_batch_tune(self.handle)
+            self.tuned = [hotrg_batch_tuning(self.handle, c) for c in range(n)]
 
     def step(self) -> None:
         hotrg_batch_step(self.handle)

@@ -313,6 +313,10 @@ struct hotrg_handle {
   bool failed = false;
   bool no_fuse = false;   // force the separate non-prime kernel (tests of the fused epilogue)
   bool scalar_prime = false;   // force the one-element-per-thread prime chain (debug contraction)
+  // set by the batch autotuner: pair groups per chunk (0: the plan's) and the 128 x 128
+  // tile GEMM instead of the 256 x 256 one for the 16-bit forms
+  int tune_chunk = 0;
+  bool tune_small_tiles = false;
   bool grad = false;      // derivative mode: carry dT/dbeta through every step
   std::string err;
   // live timing: pairs of events recorded on the stream, resolved at hotrg_timings
@@ -346,6 +350,8 @@ struct hotrg_batch {
   bool use_graphs = true;
   int p = 0;
   int graph_launches = 0, eager_steps = 0;
+  struct Tuned { int d, chi, tile, chunk; double ms; };
+  std::vector<Tuned> tuned;
   bool failed = false;
   std::string err;
   template <class X> X* at(size_t off) { return reinterpret_cast<X*>(ws + off); }
@@ -410,11 +416,11 @@ template <> struct GemmCfg<F_SPLIT_FP16> { static constexpr int BK = 64; };
 template <int F>
 void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, long bplane, void* C, long ldc,
                  long czs, long Mp, long Np, long Kp, int Z, long kchunk, const double* scale_ptr, double smult,
-                 hipStream_t s, const FuseArgs* fuse = nullptr) {
+                 hipStream_t s, const FuseArgs* fuse = nullptr, bool small_tiles = false) {
   typedef typename OpOf<F>::type Op;
   constexpr int PL = FormInfo<F>::planes;
   if constexpr (F != F_FP64 && F != F_FP32) {
-    if (Z == 1 && smult == 1.0 && Mp % GB_BM == 0 && Np % GB_BN == 0 && Kp % GB_BK == 0) {
+    if (!small_tiles && Z == 1 && smult == 1.0 && Mp % GB_BM == 0 && Np % GB_BN == 0 && Kp % GB_BK == 0) {
       const int mt = (int)(Mp / GB_BM), nt = (int)(Np / GB_BN);
       constexpr int WAVES = 8;   // 2 waves per SIMD: one wave's LDS/barrier phase hides under the other's MFMAs
       if (fuse)
@@ -551,7 +557,8 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
   const Dims dm = make_dims(ld, k);
   const long H = dm.H, Mp = roundup(H, TILE_M), Kp = roundup(H, TILE_K);
   const long pairs_total = (ld.d == 3) ? (long)k[0] * k[1] : k[0];
-  const long cp = chunk_pairs_for(ld, k, h->form, h->opts.chunk);
+  long cp = chunk_pairs_for(ld, k, h->form, h->opts.chunk);
+  if (h->tune_chunk > 0) cp = std::min<long>(cp, h->tune_chunk);   // never above what the plan holds
   ST* Aop = h->at<ST>(h->plan.off_Aop);
   ST* Bop = h->at<ST>(h->plan.off_Bop);
   AT* Cc = h->at<AT>(h->plan.off_Cc);
@@ -593,7 +600,7 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     }
     // the non-prime chain runs in the GEMM epilogue when one 256 x 256 tile is one (c, g) block
     const bool fused = FormInfo<F>::fused_ok && ld.d == 3 && dm.chi1 == 16 && dm.chi2 == 16 && dm.k1 == 16 &&
-                       dm.k2 == 16 && h->opts.chunk >= 0 && !h->no_fuse;
+                       dm.k2 == 16 && h->opts.chunk >= 0 && !h->no_fuse && !h->tune_small_tiles;
     FuseArgs fa{};
     if (fused) {
       fa.U1 = (const float*)U1;
@@ -605,7 +612,7 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     }
     hipEvent_t t1 = tmark(h);
     launch_gemm<F>(Aop, Kp, aplane, Bop, Kp, bplane, Cc, Np, 0, Mp, Np, Kp, 1, Kp, sp, 1.0, h->s,
-                   fused ? &fa : nullptr);
+                   fused ? &fa : nullptr, h->tune_small_tiles);
     tclose(h, HOTRG_T_BOTTLENECK, t1);
     if (h->profiling) h->acc.flops_bottleneck += 2.0 * (double)H * (double)ncols * (double)H;
     if (fused) continue;
@@ -1582,6 +1589,77 @@ static int batch_enqueue(hotrg_batch* b, const std::vector<StepPlan>& sps, int n
     if (rc) return batch_fail(b, rc, "instance " + std::to_string(i) + ": " + b->inst[i]->err);
   }
   if (hipGetLastError() != hipSuccess) return batch_fail(b, HOTRG_E_DEVICE, "kernel launch failed");
+  return HOTRG_OK;
+}
+
+// Autotuner: for every distinct (d, chi) among the instances, time the saturated contraction
+// of one instance with each candidate (GEMM tile 256 x 256 or 128 x 128 for the 16-bit forms;
+// chunks of the plan's size, 1/2 and 1/4 of it) and keep the fastest for all instances of
+// that class.  The operands are whatever the buffers hold: the dense kernels' time does not
+// depend on the values, and the tensor written is the one the first step overwrites.
+int hotrg_batch_tune(hotrg_batch* b, int* nclasses) {
+  if (!b) return batch_fail(nullptr, HOTRG_E_ARG, "batch is NULL");
+  if (b->failed) return batch_fail(b, HOTRG_E_STATE, "batch is in the failed state");
+  if (b->p > 0) return batch_fail(b, HOTRG_E_STATE, "tune before the first step");
+  b->tuned.clear();
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return batch_fail(b, HOTRG_E_DEVICE, "event creation failed");
+  int rc = HOTRG_OK;
+  for (int i = 0; i < b->n && rc == HOTRG_OK; ++i) {
+    hotrg_handle* h = b->inst[i];
+    const int d = h->ld.d, chi = h->chi;
+    bool seen = false;
+    for (const auto& t : b->tuned) seen = seen || (t.d == d && t.chi == chi);
+    if (seen) continue;
+    LocalDims ld;
+    ld.d = d;
+    for (int j = 0; j < d; ++j) ld.chi[j] = chi;
+    int k[MAXD];
+    for (int j = 1; j < d; ++j) k[j - 1] = chi;
+    const long base = chunk_pairs_for(ld, k, h->form, h->opts.chunk);
+    const bool sixteen = h->form != HOTRG_FP64 && h->form != HOTRG_FP32;
+    hotrg_batch::Tuned best{d, chi, 0, 0, 1e300};   // tile: GEMM tile edge
+    for (int v = 0; v < (sixteen ? 2 : 1) && rc == HOTRG_OK; ++v)
+      for (int div = 1; div <= 4 && rc == HOTRG_OK; div *= 2) {
+        const long cp = std::max(1L, base / div);
+        if (div > 1 && cp == std::max(1L, base / (div / 2))) continue;
+        h->tune_small_tiles = v == 1;
+        h->tune_chunk = (int)cp;
+        float ms = 0.f;
+        for (int rep = 0; rep < 3 && rc == HOTRG_OK; ++rep) {   // first run warms up
+          if (rep == 1 && hipEventRecord(e0, b->s) != hipSuccess) rc = HOTRG_E_DEVICE;
+          if (rc == HOTRG_OK) rc = enqueue_contract(h, h->at<void>(h->plan.off_T), h->at<void>(h->plan.off_Tn), ld, k);
+        }
+        if (rc == HOTRG_OK && (hipEventRecord(e1, b->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                               hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = HOTRG_E_DEVICE;
+        if (rc == HOTRG_OK && ms / 2 < best.ms) best = {d, chi, (sixteen && v == 0) ? 256 : 128, (int)cp, ms / 2.0};
+      }
+    if (rc != HOTRG_OK) break;
+    b->tuned.push_back(best);
+    for (auto* x : b->inst)
+      if (x->ld.d == d && x->chi == chi) {
+        x->tune_small_tiles = best.tile == 128 && sixteen;
+        x->tune_chunk = best.chunk;
+      }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != HOTRG_OK) return batch_fail(b, rc, "autotuner: contraction run failed");
+  if (nclasses) *nclasses = (int)b->tuned.size();
+  return HOTRG_OK;
+}
+
+int hotrg_batch_tuning(hotrg_batch* b, int cls, int* d, int* chi, int* gemm_tile, int* chunk_pairs,
+                       double* ms) {
+  if (!b || cls < 0 || cls >= (int)b->tuned.size()) return batch_fail(b, HOTRG_E_ARG, "class out of range");
+  const auto& t = b->tuned[cls];
+  if (d) *d = t.d;
+  if (chi) *chi = t.chi;
+  if (gemm_tile) *gemm_tile = t.tile;
+  if (chunk_pairs) *chunk_pairs = t.chunk;
+  if (ms) *ms = t.ms;
   return HOTRG_OK;
 }
 

@@ -116,3 +116,28 @@ def test_config4_sweep_against_oracle(precision, bound):
     print(f"config4 {precision}: {graphs} graph launches, {eager} eager steps; worst {worst:.2e}")
     assert all(np.isfinite(v) for row in lnz for v in row)
     assert worst < bound
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split_fp16"])
+def test_autotuned_batch_matches_untuned(precision):
+    """The autotuner picks a GEMM tile and chunk size per (d, chi) class; FP64 results do not
+    depend on that choice (bitwise), split FP16 ones only through the MFMA summation order."""
+    steps = 10
+    inst = [P.make_instance(k, d, b, c, q=q) for k, d, b, c, q in MIXED]
+    plain = P.HOTRGBatch(inst, precision=precision, max_steps=steps)
+    plain.run(steps)
+    ref = plain.log_z()
+    plain.close()
+    tuned = P.HOTRGBatch(inst, precision=precision, max_steps=steps, tune=True)
+    print(f"{precision} tuning:", tuned.tuned)
+    classes = {(i.model.d, i.chi) for i in inst}
+    assert {(t["d"], t["chi"]) for t in tuned.tuned} == classes
+    assert all(t["chunk_pairs"] >= 1 and t["contract_ms"] > 0 for t in tuned.tuned)
+    tuned.run(steps)
+    got = tuned.log_z()
+    tuned.close()
+    for g, r in zip(got, ref):
+        if precision == "fp64":
+            assert g == r
+        else:
+            assert abs(g - r) <= 1e-6 * abs(r)
