@@ -581,8 +581,11 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     hipEvent_t t0 = tmark(h);
     hipLaunchKernelGGL((k_zero_pad<ST>), dim3(grid_for((Np - ncols) * Kp + ncols * (Kp - H) + 1)), dim3(256), 0,
                        h->s, Bop, ncols, Np, H, Kp, bplane, FormInfo<F>::planes, 1);
-    if (ld.d == 3 && dm.chi2 % 4 == 0 && !h->scalar_prime)
-      hipLaunchKernelGGL((k_pstage3v<MT, UT, F>), dim3((unsigned)H), dim3(256), 0, h->s, T, (const UT*)U1,
+    if (ld.d == 3 && dm.chi2 % 8 == 0 && !h->scalar_prime)
+      hipLaunchKernelGGL((k_pstage3v<MT, UT, F, 8>), dim3((unsigned)H), dim3(256), 0, h->s, T, (const UT*)U1,
+                         (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane, (const DevState*)st);
+    else if (ld.d == 3 && dm.chi2 % 4 == 0 && !h->scalar_prime)
+      hipLaunchKernelGGL((k_pstage3v<MT, UT, F, 4>), dim3((unsigned)H), dim3(256), 0, h->s, T, (const UT*)U1,
                          (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane, (const DevState*)st);
     else if (ld.d == 3)
       hipLaunchKernelGGL((k_pstage3<MT, UT, F>), dim3((unsigned)H), dim3(256), 0, h->s, T, (const UT*)U1,
@@ -786,6 +789,7 @@ int collect_eig(hotrg_handle* h, const LocalDims& ld, EigDesc* out) {
       e.w = h->at<double>(h->plan.off_w) + slot * wn;
       e.V = h->at<double>(h->plan.off_Vo) + slot * am;
       e.scratch = h->at<double>(h->plan.off_Vw) + slot * 2 * am;
+      e.tail = e.w + n;   // the w slot holds chi^2 + 8 values
       out[count++] = e;
     }
   }
@@ -1131,7 +1135,7 @@ int hotrg_step(hotrg_handle* h, int axis) {
     eb.count = ne;
     for (int i = 0; i < ne; ++i) {
       eb.n[i] = eig[i].n; eb.kvec[i] = eig[i].kvec; eb.A[i] = eig[i].A; eb.w[i] = eig[i].w;
-      eb.V[i] = eig[i].V; eb.scratch[i] = eig[i].scratch;
+      eb.V[i] = eig[i].V; eb.scratch[i] = eig[i].scratch; eb.tail[i] = eig[i].tail;
     }
     enqueue_tri_steps(eb, h->s);
     hipLaunchKernelGGL(k_eigh_tri, dim3(ne), dim3(EIG_THREADS), 0, h->s, eb);
@@ -1536,7 +1540,7 @@ static bool desc_equal(const std::vector<EigDesc>& a, const std::vector<EigDesc>
   if (a.size() != c.size()) return false;
   for (size_t i = 0; i < a.size(); ++i)
     if (a[i].n != c[i].n || a[i].kvec != c[i].kvec || a[i].A != c[i].A || a[i].w != c[i].w || a[i].V != c[i].V ||
-        a[i].scratch != c[i].scratch)
+        a[i].scratch != c[i].scratch || a[i].tail != c[i].tail)
       return false;
   return true;
 }

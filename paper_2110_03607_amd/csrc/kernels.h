@@ -75,6 +75,28 @@ typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 template <int F> struct Store;
+
+// VEC (4 or 8) consecutive elements starting at a multiple of VEC: 4-element stores, or one
+// 16-byte store per plane for eight FP16 values.
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+template <int F, int VEC>
+__device__ inline void store_vec(typename Store<F>::T* p, long i, long plane, const double* x) {
+  if constexpr (VEC == 8 && (F == F_FP16 || F == F_SPLIT_FP16)) {
+    h8v h, l;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float xf = (float)x[j];
+      const _Float16 hi = (_Float16)xf;
+      h[j] = hi;
+      l[j] = (_Float16)(xf - (float)hi);
+    }
+    *reinterpret_cast<h8v*>(p + i) = h;
+    if constexpr (F == F_SPLIT_FP16) *reinterpret_cast<h8v*>(p + i + plane) = l;
+  } else {
+#pragma unroll
+    for (int q = 0; q < VEC; q += 4) Store<F>::put4(p, i + q, plane, x + q);
+  }
+}
 template <> struct Store<F_FP64> {
   typedef double T;
   __device__ static void put(T* p, long i, long, double x) { p[i] = x; }
@@ -590,6 +612,8 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+constexpr int EIG_ALL_N = 256;   // every eigenvalue resolved up to this size (see eigh_tri_body)
+
 struct EigBatch {
   int count;
   int n[4], kvec[4];
@@ -597,6 +621,7 @@ struct EigBatch {
   double* w[4];
   double* V[4];
   double* scratch[4];
+  double* tail[4];   // may be null: where the sum of the eigenvalues not resolved one by one goes
 };
 
 // zs -= sum_{j0 <= j < j1} (Z_j . zs) Z_j: all coefficients first (a wave per vector,
@@ -629,12 +654,14 @@ struct EigDesc {
   double* w;
   double* V;
   double* scratch;
+  double* tail;   // may be null
 };
 
 // tridiag_done: the tridiagonal form was built by k_tri_step (multi-workgroup, large n):
 // reflectors in R, diagonal and subdiagonal at Z[0, n) and Z[n, 2n).
 __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ A, double* __restrict__ w,
-                              double* __restrict__ V, double* __restrict__ R, const bool tridiag_done) {
+                              double* __restrict__ V, double* __restrict__ R, const bool tridiag_done,
+                              double* __restrict__ tail_out) {
   __shared__ double d[EIG_MAXN], e[EIG_MAXN], vv[EIG_MAXN], qv[EIG_MAXN];
   __shared__ double red[EIG_THREADS / 64];
   double* Z = R + (long)n * n;                          // reflector k at R[k n ..]; tridiagonal eigenvector i at Z[i n ..)
@@ -724,25 +751,70 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
     (void)emax;
   }
   const double pivmin = fmax(1e-290, 2.2e-16 * 2.2e-16 * tnorm * tnorm);
-  for (int i = tid; i < n; i += nt) {
-    const int target = n - 1 - i;     // 0-based index in ascending order
+  // Large matrices without the derivative: only the leading eigenvalues are resolved one by
+  // one (the kept ones, the first discarded one for the multiplet rule, and the recorded
+  // spectrum); the sum of all the others, which epsilon needs, is the trace minus theirs
+  // (*tail_out).  Up to EIG_ALL_N every eigenvalue is resolved: there epsilon can be of the
+  // order of the rounding of the trace (late steps of a disordered run), and the sum of the
+  // individually resolved small eigenvalues decides U against U' the way the oracle does.
+  const int nev = (kvec >= n || n <= EIG_ALL_N) ? n : min(n, max(kvec + 1, NSPEC));
+  // Multisection: G lanes per eigenvalue each count at one of G interior points, so an
+  // interval shrinks by G + 1 per Sturm sweep instead of 2.
+  int G = 1;
+  while (G < 16 && 2 * G * nev <= nt) G *= 2;
+  double* e2 = qv;                                        // squared subdiagonal
+  for (int i = tid; i < n; i += nt) e2[i] = e[i] * e[i];
+  __syncthreads();
+  for (int base = 0; base < nev; base += nt / G) {
+    const int idx = base + tid / G, jl = tid % G;
+    const bool act = idx < nev;
+    const int target = n - 1 - idx;                       // 0-based index in ascending order
+    const int gbase = (lane / G) * G;                     // first lane of this group in the wave
     double a = lo, b = hi;
+    bool done = !act;
     for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (a + b);
-      if (!(mid > a && mid < b)) break;
-      if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin) break;
+      if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin) done = true;
+      const double x = a + (b - a) * (double)(jl + 1) / (double)(G + 1);
       int cnt = 0;
-      double q = d[0] - mid;
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
-      for (int r = 1; r < n; ++r) {
-        q = d[r] - mid - e[r - 1] * e[r - 1] / q;
+      if (!done) {
+        double q = d[0] - x;
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
+        for (int r = 1; r < n; ++r) {
+          q = d[r] - x - e2[r - 1] / q;
+          if (fabs(q) < pivmin) q = -pivmin;
+          cnt += q < 0.0;
+        }
       }
-      if (cnt > target) b = mid; else a = mid;
+      const unsigned long long m = __ballot(!done && cnt > target);
+      if (__all(done)) break;
+      if (!done) {
+        const unsigned bits = (unsigned)((m >> gbase) & ((1ull << G) - 1ull));
+        const int js = bits ? __ffs(bits) - 1 : G;        // first point above lambda
+        const double na = js == 0 ? a : a + (b - a) * (double)js / (double)(G + 1);
+        const double nb = js == G ? b : a + (b - a) * (double)(js + 1) / (double)(G + 1);
+        if (!(na >= a && nb <= b && (na > a || nb < b))) done = true;   // no progress left
+        a = na;
+        b = nb;
+      }
     }
-    w[i] = 0.5 * (a + b);
+    if (act && jl == 0) w[idx] = 0.5 * (a + b);
+  }
+  __syncthreads();
+  {
+    double tp = 0.0;
+    for (int i = tid; i < n; i += nt) tp += d[i];
+    const double tr = block_sum(tp, red);
+    if (tid == 0 && tail_out) {
+      double tail = 0.0;
+      if (nev < n) {
+        double lead = 0.0;
+        for (int i = 0; i < nev; ++i) lead += w[i];
+        tail = fmax(tr - lead, 0.0);
+      }
+      *tail_out = tail;
+    }
+    for (int i = nev + tid; i < n; i += nt) w[i] = 0.0;
   }
   __syncthreads();
 
@@ -859,14 +931,14 @@ constexpr int TRI_MULTI_N = 128;
 // Up to four matrices passed by value (one coarse-graining step of one instance).
 __global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
   const int b = blockIdx.x;
-  eigh_tri_body(eb.n[b], eb.kvec[b], eb.A[b], eb.w[b], eb.V[b], eb.scratch[b], eb.n[b] >= TRI_MULTI_N);
+  eigh_tri_body(eb.n[b], eb.kvec[b], eb.A[b], eb.w[b], eb.V[b], eb.scratch[b], eb.n[b] >= TRI_MULTI_N, eb.tail[b]);
 }
 
 // Any number of matrices from a descriptor table in device memory (a step of a batch of
 // instances: one launch for all their decompositions).
 __global__ __launch_bounds__(EIG_THREADS) void k_eigh_list(const EigDesc* __restrict__ list) {
   const EigDesc ds = list[blockIdx.x];
-  eigh_tri_body(ds.n, ds.kvec, ds.A, ds.w, ds.V, ds.scratch, ds.n >= TRI_MULTI_N);
+  eigh_tri_body(ds.n, ds.kvec, ds.A, ds.w, ds.V, ds.scratch, ds.n >= TRI_MULTI_N, ds.tail);
 }
 
 // ---------------------------------------------------------------------------
@@ -1017,6 +1089,8 @@ __global__ void k_choose(const double* __restrict__ w0, const double* __restrict
     const double* ws = tid == 0 ? w0 : w1;
     double e = 0.0;
     for (int l = chi_new; l < n; ++l) e += fmax(ws[l], 0.0);
+    e += ws[n];   // eigenvalues not resolved one by one: their sum (the trace minus the rest;
+                  // 0 when all were resolved)
     eps_s[tid] = e;
   }
   __syncthreads();
@@ -1186,7 +1260,7 @@ __global__ __launch_bounds__(256) void k_pstage3(const MT* __restrict__ T, const
 // consecutive output columns r = (nh1', nh2' .. nh2' + 3) of one row and writes them with one
 // vector store per plane; its 16 Z values (fixed nh1') stay in registers over the pair groups
 // of the chunk, and U2 comes from LDS four columns at a time.
-template <class MT, class UT, int F>
+template <class MT, class UT, int F, int VEC>
 __global__ __launch_bounds__(256) void k_pstage3v(const MT* __restrict__ T, const UT* __restrict__ U1,
                                                   const UT* __restrict__ U2, Dims dm, int pr0, int pr1,
                                                   typename Store<F>::T* __restrict__ B, long ldb, long bplane,
@@ -1210,11 +1284,11 @@ __global__ __launch_bounds__(256) void k_pstage3v(const MT* __restrict__ T, cons
     const int n1 = n1lo + i / c1sq, rem = i % c1sq, nc1 = rem / chi1, nh1 = rem % chi1;
     u1t[i] = (MT)U1[(nh1 + chi1 * nc1) * k1 + n1];
   }
-  const int G = b / 4;                       // column groups of four
+  const int G = b / VEC;                     // column groups of VEC
   const int lanes = 256 / G;                 // pair groups handled side by side
   const int g = tid % G, prl = tid / G;
   const bool active = prl < lanes;
-  const int r0 = 4 * g, nh1 = r0 / chi2, nh2 = r0 % chi2;
+  const int r0 = VEC * g, nh1 = r0 / chi2, nh2 = r0 % chi2;
   for (int cp = 0; cp < dm.chic; ++cp) {
     __syncthreads();
     for (int i = tid; i < b; i += 256) X[i] = T[(long)h * dm.H + (long)cp * b + i];
@@ -1236,19 +1310,21 @@ __global__ __launch_bounds__(256) void k_pstage3v(const MT* __restrict__ T, cons
       const int pb = (n1 + 1) * k2 < pr1 ? (n1 + 1) * k2 : pr1;
       for (int pr = pa + prl; pr < pb; pr += lanes) {
         const MT* u = &u2t[(pr % k2) * c2sq + nh2];
-        MT s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        MT sv[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) sv[e] = 0;
 #pragma unroll
         for (int nc2 = 0; nc2 < 16; ++nc2)
           if (nc2 < chi2) {
             const MT* uu = u + nc2 * chi2;
-            s0 += z[nc2] * uu[0];
-            s1 += z[nc2] * uu[1];
-            s2 += z[nc2] * uu[2];
-            s3 += z[nc2] * uu[3];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) sv[e] += z[nc2] * uu[e];
           }
-        const double v[4] = {(double)s0 * sB, (double)s1 * sB, (double)s2 * sB, (double)s3 * sB};
+        double v[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[e] = (double)sv[e] * sB;
         const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
-        Store<F>::put4(B, row * ldb + (long)rho * b + r0, bplane, v);
+        store_vec<F, VEC>(B, row * ldb + (long)rho * b + r0, bplane, v);
       }
     }
   }
