@@ -657,6 +657,58 @@ struct EigDesc {
   double* tail;   // may be null
 };
 
+// LU with partial pivoting of the tridiagonal T - lam I (diagonal d, subdiagonal e), one
+// thread: U has three diagonals (reciprocal pivot ri, superdiagonals u1, u2), L the
+// multipliers l, pv[r] = 1 when rows r and r + 1 were swapped.  Pivots are floored at pivlu.
+__device__ inline void lu_shifted(const double* d, const double* e, int n, double lam, double pivlu, double* ri,
+                                  double* u1, double* u2, double* lq, int* pv) {
+  double a0 = d[0] - lam, b0 = n > 1 ? e[0] : 0.0, c0 = 0.0;   // current row: diag, super, super2
+  for (int r = 0; r < n; ++r) {
+    if (r + 1 < n) {
+      const double sub = e[r];
+      const double dn = d[r + 1] - lam, en = r + 2 < n ? e[r + 1] : 0.0;
+      if (fabs(sub) > fabs(a0)) {
+        const double l = a0 / sub;
+        pv[r] = 1; lq[r] = l;
+        ri[r] = 1.0 / sub; u1[r] = dn; u2[r] = en;
+        a0 = b0 - l * dn;
+        b0 = c0 - l * en;
+      } else {
+        const double piv = fabs(a0) < pivlu ? (a0 < 0.0 ? -pivlu : pivlu) : a0;
+        const double l = sub / piv;
+        pv[r] = 0; lq[r] = l;
+        ri[r] = 1.0 / piv; u1[r] = b0; u2[r] = c0;
+        a0 = dn - l * b0;
+        b0 = en - l * c0;
+      }
+      c0 = 0.0;
+    } else {
+      const double piv = fabs(a0) < pivlu ? (a0 < 0.0 ? -pivlu : pivlu) : a0;
+      pv[r] = 0; lq[r] = 0.0;
+      ri[r] = 1.0 / piv; u1[r] = 0.0; u2[r] = 0.0;
+    }
+  }
+}
+
+// z <- (T - lam I)^{-1} z with the factors of lu_shifted, one thread.
+__device__ inline void lu_solve(double* z, int n, const double* ri, const double* u1, const double* u2,
+                                const double* lq, const int* pv) {
+  double cur = z[0];
+  for (int r = 0; r + 1 < n; ++r) {        // row operations, value of row r carried in cur
+    const double nxt = z[r + 1], l = lq[r];
+    if (pv[r]) { z[r] = nxt; cur = cur - l * nxt; }
+    else { z[r] = cur; cur = nxt - l * cur; }
+  }
+  z[n - 1] = cur;
+  double x1 = 0.0, x2 = 0.0;               // x_{r+1}, x_{r+2}
+  for (int r = n - 1; r >= 0; --r) {
+    const double x = (z[r] - u1[r] * x1 - u2[r] * x2) * ri[r];
+    z[r] = x;
+    x2 = x1;
+    x1 = x;
+  }
+}
+
 // tridiag_done: the tridiagonal form was built by k_tri_step (multi-workgroup, large n):
 // reflectors in R, diagonal and subdiagonal at Z[0, n) and Z[n, 2n).
 __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ A, double* __restrict__ w,
@@ -765,6 +817,11 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
   double* e2 = qv;                                        // squared subdiagonal
   for (int i = tid; i < n; i += nt) e2[i] = e[i] * e[i];
   __syncthreads();
+  // The leading eigenvalues (and all of them with the derivative, which divides by their
+  // differences) to full relative precision; the others, which only enter the sum epsilon, to
+  // an absolute 4 u |T|, the accuracy the reduction to tridiagonal form leaves them anyway.
+  const int nlead = kvec >= n ? n : min(n, max(kvec + 1, NSPEC));
+  const double abs_tol = 4.0 * 2.2e-16 * tnorm;
   for (int base = 0; base < nev; base += nt / G) {
     const int idx = base + tid / G, jl = tid % G;
     const bool act = idx < nev;
@@ -773,7 +830,7 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
     double a = lo, b = hi;
     bool done = !act;
     for (int it = 0; it < 200; ++it) {
-      if (b - a <= 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin) done = true;
+      if (b - a <= (idx < nlead ? 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin : abs_tol)) done = true;
       const double x = a + (b - a) * (double)(jl + 1) / (double)(G + 1);
       int cnt = 0;
       if (!done) {
@@ -820,73 +877,75 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
 
   // ---- 3. inverse iteration for the leading kvec eigenvectors -----------------
   // LU of (T - lambda I) with partial pivoting (rows r, r+1 may swap); U has three
-  // diagonals, stored as reciprocal pivot, first and second superdiagonal.
-  __shared__ double lu_ri[EIG_MAXN], lu_u1[EIG_MAXN], lu_u2[EIG_MAXN], lu_l[EIG_MAXN];
-  __shared__ int lu_p[EIG_MAXN];
+  // diagonals, stored as reciprocal pivot, first and second superdiagonal.  Vectors with no
+  // earlier eigenvalue within ortol ("independent") are computed side by side, one wave
+  // each (lane 0 runs the serial factorisation and solves on the wave's own LDS arrays);
+  // then the others in order, each orthogonalised against the earlier members of its
+  // cluster.  Both paths run the same arithmetic.
+  constexpr int PW_WAVES = 8, PW_MAXN = 256;
+  __shared__ double lu_raw[PW_WAVES * PW_MAXN * 5 + PW_WAVES * PW_MAXN / 2];   // 88 KB
+  double* lu_ri = lu_raw;                       // single-vector arrays (n <= EIG_MAXN)
+  double* lu_u1 = lu_ri + EIG_MAXN;
+  double* lu_u2 = lu_u1 + EIG_MAXN;
+  double* lu_l = lu_u2 + EIG_MAXN;
+  int* lu_p = (int*)(lu_l + EIG_MAXN);
   const double ortol = 1e-3 * tnorm;
   const double pivlu = fmax(1e-290, 2.2e-16 * tnorm);   // pivot floor: bounded growth, no overflow
   double* zs = vv;                                       // LDS copy of the current vector
   double* coef = qv;                                     // Gram-Schmidt coefficients (qv is free now)
-  for (int iv = 0; iv < kvec; ++iv) {
-    const double lam = w[iv];
-    if (tid == 0) {
-      double a0 = d[0] - lam, b0 = n > 1 ? e[0] : 0.0, c0 = 0.0;   // current row: diag, super, super2
-      for (int r = 0; r < n; ++r) {
-        if (r + 1 < n) {
-          const double sub = e[r];
-          const double dn = d[r + 1] - lam, en = r + 2 < n ? e[r + 1] : 0.0;
-          if (fabs(sub) > fabs(a0)) {
-            const double l = a0 / sub;
-            lu_p[r] = 1; lu_l[r] = l;
-            lu_ri[r] = 1.0 / sub; lu_u1[r] = dn; lu_u2[r] = en;
-            a0 = b0 - l * dn;
-            b0 = c0 - l * en;
-          } else {
-            const double piv = fabs(a0) < pivlu ? (a0 < 0.0 ? -pivlu : pivlu) : a0;
-            const double l = sub / piv;
-            lu_p[r] = 0; lu_l[r] = l;
-            lu_ri[r] = 1.0 / piv; lu_u1[r] = b0; lu_u2[r] = c0;
-            a0 = dn - l * b0;
-            b0 = en - l * c0;
-          }
-          c0 = 0.0;
-        } else {
-          const double piv = fabs(a0) < pivlu ? (a0 < 0.0 ? -pivlu : pivlu) : a0;
-          lu_p[r] = 0; lu_l[r] = 0.0;
-          lu_ri[r] = 1.0 / piv; lu_u1[r] = 0.0; lu_u2[r] = 0.0;
-        }
-      }
-    }
-    for (int i = tid; i < n; i += nt) {      // deterministic start vector, zero-mean entries
+  auto start_vector = [&](double* z, int iv, int i0, int step) {   // deterministic, zero-mean entries
+    for (int i = i0; i < n; i += step) {
       const unsigned hsh = (unsigned)(i + 1) * 2654435761u ^ (unsigned)(iv + 7) * 40503u;
-      zs[i] = (double)(hsh & 0xFFFFu) / 32768.0 - 1.0;
+      z[i] = (double)(hsh & 0xFFFFu) / 32768.0 - 1.0;
     }
-    __syncthreads();
-    // vectors already found in this cluster (consecutive eigenvalues within ortol)
+  };
+  auto first_in_cluster = [&](int iv) {
     int j0 = iv;
-    while (j0 > 0 && fabs(w[j0 - 1] - lam) <= ortol) --j0;
-    // the start vector is made orthogonal to them first, so that the solve amplifies the
-    // directions not found yet (inside a cluster of equal eigenvalues all of them grow alike)
+    while (j0 > 0 && fabs(w[j0 - 1] - w[iv]) <= ortol) --j0;
+    return j0;
+  };
+  // independent vectors, a wave each
+  const bool side_by_side = n <= PW_MAXN;
+  if (side_by_side && wv < PW_WAVES) {
+    double* base = lu_raw + wv * (PW_MAXN * 5 + PW_MAXN / 2);
+    double *ri = base, *u1 = ri + PW_MAXN, *u2 = u1 + PW_MAXN, *lq = u2 + PW_MAXN, *z = lq + PW_MAXN;
+    int* pv = (int*)(z + PW_MAXN);
+    int rank = 0;                                        // position among the independent vectors
+    for (int iv = 0; iv < kvec; ++iv) {
+      if (first_in_cluster(iv) != iv) continue;
+      if (rank++ % PW_WAVES != wv) continue;
+      if (lane == 0) lu_shifted(d, e, n, w[iv], pivlu, ri, u1, u2, lq, pv);
+      start_vector(z, iv, lane, 64);
+      __threadfence_block();
+      for (int it = 0; it < 3; ++it) {
+        if (lane == 0) lu_solve(z, n, ri, u1, u2, lq, pv);
+        __threadfence_block();
+        double np = 0.0;
+        for (int i = lane; i < n; i += 64) np += z[i] * z[i];
+        for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
+        const double inv = 1.0 / sqrt(np);
+        for (int i = lane; i < n; i += 64) z[i] *= inv;
+        __threadfence_block();
+      }
+      for (int i = lane; i < n; i += 64) Z[(long)iv * n + i] = z[i];
+    }
+  }
+  __syncthreads();
+  for (int iv = 0; iv < kvec; ++iv) {
+    const int j0 = first_in_cluster(iv);
+    if (side_by_side && j0 == iv) continue;            // done above
+    const double lam = w[iv];
+    if (tid == 0) lu_shifted(d, e, n, lam, pivlu, lu_ri, lu_u1, lu_u2, lu_l, lu_p);
+    start_vector(zs, iv, tid, nt);
+    __syncthreads();
+    // the start vector is made orthogonal to the earlier members of its cluster first, so
+    // that the solve amplifies the directions not found yet (inside a cluster of equal
+    // eigenvalues all of them grow alike)
     cgs_cluster(zs, Z, n, j0, iv, coef, tid, nt, lane, wv, nw);
     // three solves: inside a large cluster of (numerically) zero eigenvalues the first two
     // still leave components of the order 1e-9 along eigenvalues outside the cluster
     for (int it = 0; it < 3; ++it) {
-      if (tid == 0) {
-        double cur = zs[0];
-        for (int r = 0; r + 1 < n; ++r) {        // row operations, value of row r carried in cur
-          const double nxt = zs[r + 1], l = lu_l[r];
-          if (lu_p[r]) { zs[r] = nxt; cur = cur - l * nxt; }
-          else { zs[r] = cur; cur = nxt - l * cur; }
-        }
-        zs[n - 1] = cur;
-        double x1 = 0.0, x2 = 0.0;               // x_{r+1}, x_{r+2}
-        for (int r = n - 1; r >= 0; --r) {
-          const double x = (zs[r] - lu_u1[r] * x1 - lu_u2[r] * x2) * lu_ri[r];
-          zs[r] = x;
-          x2 = x1;
-          x1 = x;
-        }
-      }
+      if (tid == 0) lu_solve(zs, n, lu_ri, lu_u1, lu_u2, lu_l, lu_p);
       __syncthreads();
       // same cluster: classical Gram-Schmidt, twice (one pass leaves the rounding of a
       // vector dominated by found directions unorthogonalised)
