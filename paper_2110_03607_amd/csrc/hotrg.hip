@@ -434,6 +434,16 @@ void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, 
       return;
     }
   }
+  if constexpr (F == F_FP64) {
+    // (falls back to the 128 x 128 kernel when the large tiles would leave most CUs idle)
+    if (!small_tiles && Mp % GD_BM == 0 && Np % GD_BN == 0 && kchunk % GD_BK == 0 && lda % 2 == 0 &&
+        ldb % 2 == 0 && (Mp / GD_BM) * (Np / GD_BN) * Z >= 128) {
+      const int mt = (int)(Mp / GD_BM), nt = (int)(Np / GD_BN);
+      hipLaunchKernelGGL(k_gemm_f64, dim3((unsigned)(mt * nt), 1, (unsigned)Z), dim3(512), 0, s, (const double*)A,
+                         lda, (const double*)B, ldb, (double*)C, ldc, czs, (int)kchunk, mt, nt, scale_ptr, smult);
+      return;
+    }
+  }
   constexpr long T = 128;
   dim3 grid((unsigned)(Mp / T), (unsigned)(Np / T), (unsigned)Z);
   hipLaunchKernelGGL((k_gemm_tn<Op, PL, T, T, GemmCfg<F>::BK>), grid, dim3(256), 0, s,

@@ -432,6 +432,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
 #pragma unroll
       for (int j = 0; j < NB; ++j)
         b[p][j] = *(const Frag*)(base + p * (GB_BM + GB_BN) * 64 + GB_BM * 64 + swz(wn * WTN + j * 16 + fr, fc));
+    // MFMA phase at raised wave priority: the other wave of the SIMD issues its loads and LDS
+    // stores in the gaps instead of competing for issue with these MFMAs
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       Frag a[PLANES];
@@ -447,6 +450,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
         acc[i][j] = Op::mma(a[0], b[0][j], acc[i][j]);
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     if (kt + 1 < nk) { GB_LSTORE((kt + 1) & 1); }
     __syncthreads();
   }
@@ -511,6 +515,94 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
           C[row * ldc + col] = acc[i][j][r] * sc;
         }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Large-tile FP64 GEMM: C_z[m][n] = s * sum_{k in slice z} A[m][k] B[n][k], tile 256 x 128,
+// BK = 8, 512 threads: 8 waves in a 2 (M) x 4 (N) grid, 128 x 32 per wave (8 x 2 blocks of
+// 16 x 16, v_mfma_f64_16x16x4f64).  An LDS row of the tile is 8 doubles = 64 bytes, the same
+// geometry as k_gemm_big (four 16-byte chunks, XOR-swizzled), double-buffered with register
+// staging; the 16 rows x 1 double read by a quarter-wave for a fragment hit 32 distinct banks.
+// Split-K: slice z = blockIdx.z covers K range [z kchunk, (z + 1) kchunk).
+// ---------------------------------------------------------------------------
+constexpr int GD_BM = 256, GD_BN = 128, GD_BK = 8;
+
+__global__ __launch_bounds__(512) void k_gemm_f64(const double* __restrict__ A, long lda,
+                                                  const double* __restrict__ B, long ldb, double* __restrict__ C,
+                                                  long ldc, long czs, int kchunk, int mtiles, int ntiles,
+                                                  const double* __restrict__ scale_ptr, double smult) {
+  constexpr int STAGE = (GD_BM + GD_BN) * 64;   // bytes per stage
+  __shared__ __attribute__((aligned(16))) char lds[2 * STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;
+  int tm, tn;
+  tile_of(blockIdx.x, mtiles, ntiles, tm, tn);
+  const long m0 = (long)tm * GD_BM, n0 = (long)tn * GD_BN;
+  const long kbeg = (long)blockIdx.z * kchunk;
+  // staging: A chunks q = tid and tid + 512, B chunk q = tid (row q / 4, 16-byte chunk q % 4)
+  const int qr = tid >> 2, qc = tid & 3;
+  const double* Ap0 = A + (m0 + qr) * lda + 2 * qc;
+  const double* Ap1 = A + (m0 + qr + 128) * lda + 2 * qc;
+  const double* Bp0 = B + (n0 + qr) * ldb + 2 * qc;
+  const int so0 = swz(qr, qc), so1 = swz(qr + 128, qc), sob = GD_BM * 64 + swz(qr, qc);
+  uint4 sa0, sa1, sb0;
+#define GD_GLOAD(k0)                           \
+  {                                            \
+    sa0 = *(const uint4*)(Ap0 + (k0));         \
+    sa1 = *(const uint4*)(Ap1 + (k0));         \
+    sb0 = *(const uint4*)(Bp0 + (k0));         \
+  }
+#define GD_LSTORE(st)                                    \
+  {                                                      \
+    char* b_ = lds + (st) * STAGE;                       \
+    *(uint4*)(b_ + so0) = sa0;                           \
+    *(uint4*)(b_ + so1) = sa1;                           \
+    *(uint4*)(b_ + sob) = sb0;                           \
+  }
+  d4 acc[8][2];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0, 0, 0, 0};
+
+  const int nk = kchunk / GD_BK;
+  const int fr = lane & 15, fc = lane >> 4;
+  GD_GLOAD(kbeg);
+  GD_LSTORE(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) GD_GLOAD(kbeg + (long)(kt + 1) * GD_BK);
+    const char* base = lds + (kt & 1) * STAGE;
+#pragma unroll
+    for (int kk = 0; kk < GD_BK; kk += 4) {
+      const int k = kk + fc, kc = k >> 1, ko = (k & 1) * 8;
+      double b[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = *(const double*)(base + GD_BM * 64 + swz(wn * 32 + j * 16 + fr, kc) + ko);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const double a = *(const double*)(base + swz(wm * 128 + i * 16 + fr, kc) + ko);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (kt + 1 < nk) GD_LSTORE((kt + 1) & 1);
+    __syncthreads();
+  }
+#undef GD_GLOAD
+#undef GD_LSTORE
+  const double s = (scale_ptr ? *scale_ptr : 1.0) * smult;
+  double* Cz = C + (long)blockIdx.z * czs;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long row = m0 + wm * 128 + i * 16 + OpF64::out_row(lane, r);
+        const long col = n0 + wn * 32 + j * 16 + fr;
+        Cz[row * ldc + col] = acc[i][j][r] * s;
+      }
 }
 
 // Fixed-order reduction of split-K slices: out[r][c] = sum_z part[z][r][c] for r < R, c < R.
@@ -1348,10 +1440,14 @@ __global__ __launch_bounds__(256) void k_pstage3v(const MT* __restrict__ T, cons
   const int g = tid % G, prl = tid / G;
   const bool active = prl < lanes;
   const int r0 = VEC * g, nh1 = r0 / chi2, nh2 = r0 % chi2;
+  // the T row segment of the next cp is fetched into a register while this one is used
+  // (b <= 256 in 3D: one element per thread)
+  MT xn = tid < b ? T[(long)h * dm.H + tid] : (MT)0;
   for (int cp = 0; cp < dm.chic; ++cp) {
     __syncthreads();
-    for (int i = tid; i < b; i += 256) X[i] = T[(long)h * dm.H + (long)cp * b + i];
+    if (tid < b) X[tid] = xn;
     __syncthreads();
+    if (cp + 1 < dm.chic && tid < b) xn = T[(long)h * dm.H + (long)(cp + 1) * b + tid];
     for (int i = tid; i < nn1 * b; i += 256) {
       const int n1l = i / b, r = i % b, zh1 = r / chi2, nc2 = r % chi2;
       const MT* u = &u1t[n1l * c1sq + zh1];

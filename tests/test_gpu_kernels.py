@@ -117,9 +117,10 @@ def test_contract_forms_full_size_sampled(form):
         assert err < tol(form, 4096)
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 4), (3, 5, 2), (8, 8, 8), (8, 8), (16, 24), (32, 32)])
+@pytest.mark.parametrize("dims", [(4, 4, 4), (3, 5, 2), (8, 8, 8), (12, 12, 12), (8, 8), (16, 24), (32, 32)])
 def test_gram_matches_oracle(dims):
-    # (16, 24) and (32, 32): Gram matrices of size 576 and 1024, third step as a GEMM
+    # (16, 24) and (32, 32): Gram matrices of size 576 and 1024, third step as a GEMM;
+    # (12, 12, 12) and (32, 32): first two steps on the 256 x 128 FP64 tiles (ragged rows: 144 of 256)
     d = len(dims)
     Ts = SI.random_tensor(tuple(dims) * 2, seed=5)
     Tp = LY.to_paper(Ts)
