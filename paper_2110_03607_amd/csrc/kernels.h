@@ -330,15 +330,19 @@ __global__ __launch_bounds__(256) void k_gemm_tn(
 // 8 waves in a 2 (M) x 4 (N) grid, 128 x 64 per wave (8 x 4 blocks of 16 x 16).
 // Global -> registers -> LDS, double-buffered; the next K-slice is fetched while the
 // current one feeds the MFMAs.  LDS rows are 64 bytes (four 16-byte k-chunks); chunk c of
-// row r sits at slot c ^ ((r >> 2) & 3), so the 16 rows x 1 chunk read by a quarter-wave
-// for an MFMA fragment cover all 64 banks once.
+// row r sits at slot c ^ ((r >> 1) & 3).  With this placement the fragment reads (16 rows x
+// one chunk per quarter-wave) and the stores count no LDS bank-conflict cycles
+// (SQ_LDS_BANK_CONFLICT = 0); with c ^ ((r >> 2) & 3), c ^ (r & 3) or no swizzle they do, and
+// the bottleneck GEMM takes about 2% longer.
 // Tiles are ordered so that the workgroups resident on one XCD at a time (consecutive
 // workgroups go to consecutive XCDs) form compact 4 x 8 groups of tiles sharing A and B
 // panels in that XCD's L2.
 // ---------------------------------------------------------------------------
 constexpr int GB_BM = 256, GB_BN = 256, GB_BK = 32;
 
-__device__ inline int swz(int r, int c) { return r * 64 + ((c ^ ((r >> 2) & 3)) << 4); }
+__device__ inline int swz(int r, int c) {
+  return r * 64 + ((c ^ ((r >> 1) & 3)) << 4);
+}
 
 __device__ inline void tile_of(int b, int mt, int nt, int& tm, int& tn) {
   if (mt % 4 == 0 && nt % 8 == 0 && (mt / 4) * (nt / 8) % 8 == 0) {
@@ -526,6 +530,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
 // Split-K: slice z = blockIdx.z covers K range [z kchunk, (z + 1) kchunk).
 // ---------------------------------------------------------------------------
 constexpr int GD_BM = 256, GD_BN = 128, GD_BK = 8;
+__device__ inline int swz_f64(int r, int c) { return r * 64 + ((c ^ ((r >> 1) & 3)) << 4); }
 
 __global__ __launch_bounds__(512) void k_gemm_f64(const double* __restrict__ A, long lda,
                                                   const double* __restrict__ B, long ldb, double* __restrict__ C,
@@ -544,7 +549,7 @@ __global__ __launch_bounds__(512) void k_gemm_f64(const double* __restrict__ A, 
   const double* Ap0 = A + (m0 + qr) * lda + 2 * qc;
   const double* Ap1 = A + (m0 + qr + 128) * lda + 2 * qc;
   const double* Bp0 = B + (n0 + qr) * ldb + 2 * qc;
-  const int so0 = swz(qr, qc), so1 = swz(qr + 128, qc), sob = GD_BM * 64 + swz(qr, qc);
+  const int so0 = swz_f64(qr, qc), so1 = swz_f64(qr + 128, qc), sob = GD_BM * 64 + swz_f64(qr, qc);
   uint4 sa0, sa1, sb0;
 #define GD_GLOAD(k0)                           \
   {                                            \
@@ -578,10 +583,10 @@ __global__ __launch_bounds__(512) void k_gemm_f64(const double* __restrict__ A, 
       const int k = kk + fc, kc = k >> 1, ko = (k & 1) * 8;
       double b[2];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = *(const double*)(base + GD_BM * 64 + swz(wn * 32 + j * 16 + fr, kc) + ko);
+      for (int j = 0; j < 2; ++j) b[j] = *(const double*)(base + GD_BM * 64 + swz_f64(wn * 32 + j * 16 + fr, kc) + ko);
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const double a = *(const double*)(base + swz(wm * 128 + i * 16 + fr, kc) + ko);
+        const double a = *(const double*)(base + swz_f64(wm * 128 + i * 16 + fr, kc) + ko);
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[j], acc[i][j], 0, 0, 0);
       }
