@@ -552,6 +552,13 @@ int enqueue_gram(hotrg_handle* h, const void* T, bool t_is_f64, const LocalDims&
 
 // The one-workgroup-per-(c, g) non-prime chain holds a thread per (nh1, nc1) pair and
 // chi2 x chi2 x k2 <= 16 x 16 x 16 register/LDS blocks.
+// The MFMA prime chain is written for the saturated chi = 16 step: chi_c = chi_1 = chi_2 = k_1 =
+// k_2 = 16 (H = 4096, b = 256) and a pair range made of whole n1' blocks.
+inline bool prime_mfma_ok(const Dims& dm, long pr0, long pr1) {
+  return dm.chic == 16 && dm.chi1 == 16 && dm.chi2 == 16 && dm.k1 == 16 && dm.k2 == 16 && dm.H == 4096 &&
+         dm.b == 256 && pr0 % 16 == 0 && pr1 % 16 == 0 && pr1 > pr0;
+}
+
 inline bool nstage3c_ok(const Dims& dm) {
   return dm.chi1 <= 16 && dm.chi2 <= 16 && dm.k1 <= 16 && dm.k2 <= 16;
 }
@@ -591,6 +598,14 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     hipEvent_t t0 = tmark(h);
     hipLaunchKernelGGL((k_zero_pad<ST>), dim3(grid_for((Np - ncols) * Kp + ncols * (Kp - H) + 1)), dim3(256), 0,
                        h->s, Bop, ncols, Np, H, Kp, bplane, FormInfo<F>::planes, 1);
+    if constexpr (F != F_FP64) {
+      if (ld.d == 3 && prime_mfma_ok(dm, pr0, pr1) && !h->scalar_prime) {
+        hipLaunchKernelGGL((k_pstage3m<F>), dim3((unsigned)H), dim3(256), 0, h->s, (const float*)T,
+                           (const float*)U1, (const float*)U2, (int)pr0, (int)pr1, Bop, Kp, bplane,
+                           (const DevState*)st);
+        goto prime_done;
+      }
+    }
     if (ld.d == 3 && dm.chi2 % 8 == 0 && !h->scalar_prime)
       hipLaunchKernelGGL((k_pstage3v<MT, UT, F, 8>), dim3((unsigned)H), dim3(256), 0, h->s, T, (const UT*)U1,
                          (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane, (const DevState*)st);
@@ -604,6 +619,7 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
       hipLaunchKernelGGL((k_pstage<MT, UT, F>), dim3((unsigned)(H * dm.chic)), dim3(256), 0, h->s, T,
                          (const UT*)U1, (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane,
                          (const DevState*)st);
+  prime_done:
     tclose(h, HOTRG_T_PRIME, t0);
     const double* sp = nullptr;
     if (FormInfo<F>::fp16) {

@@ -1490,6 +1490,79 @@ __global__ __launch_bounds__(256) void k_pstage3v(const MT* __restrict__ T, cons
   }
 }
 
+// Prime chain (3D) on FP32 MFMA for chi_c = chi_1 = chi_2 = k_1 = k_2 = 16 and chunks of whole
+// n1' blocks (the saturated chi = 16 step).  For the workgroup's row h = (rho, nc) of the hat
+// copy and one n1', the U2 contraction of all 16 c' is one 256 x 256 x 16 product
+//   OUT[(n2', nh2')][(c', nh1')] = sum_{nc2'} U2[nh2' + 16 nc2'][n2'] Z[c'][nh1'][nc2'],
+// with Z[c'][nh1'][nc2'] = sum_{nc1'} U1[nh1' + 16 nc1'][n1'] T[h][(c', nc1', nc2')] on the VALU.
+// Wave w owns the M blocks n2' = 4w .. 4w + 3 and keeps their U2 fragments in registers; at
+// k-step s lane l stands for nc2' = 4 (l / 16) + s, so its B fragment (Z) for one c' is one
+// 16-byte LDS read (chunk nc2' / 4 of row (c', nh1') sits at slot (nc2' / 4) ^ ((nh1' >> 1) & 3)).
+// An accumulator lane holds four consecutive nh2' of one nh1', so each output row (n2', c') is
+// written as 512 contiguous bytes per plane.
+template <int F>
+__global__ __launch_bounds__(256) void k_pstage3m(const float* __restrict__ T, const float* __restrict__ U1,
+                                                  const float* __restrict__ U2, int pr0, int pr1,
+                                                  typename Store<F>::T* __restrict__ B, long ldb, long bplane,
+                                                  const DevState* __restrict__ st) {
+  __shared__ __attribute__((aligned(16))) float X[4096];   // row h of T: [c'][nc1'][nc2']
+  __shared__ __attribute__((aligned(16))) float Z[4096];   // [c'][nh1'][16-byte chunks of nc2']
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = blockIdx.x;
+  const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * 16.0) : 1.0;   // sqrt(b) = 16
+  const int rho = h >> 8, nc = h & 255;
+  {
+    const f4v* src = reinterpret_cast<const f4v*>(T + (long)h * 4096);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) reinterpret_cast<f4v*>(X)[tid + 256 * i] = src[tid + 256 * i];
+  }
+  float ua[4][4];   // [M block j][k-step s] = U2[(lane & 15) + 16 (4 (lane >> 4) + s)][4 wave + j]
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) ua[j][s] = U2[((lane & 15) + 16 * (4 * (lane >> 4) + s)) * 16 + 4 * wave + j];
+  // Z entries of this thread: c' = 4 cg + i (i < 4), nh1' = zh1, nc2' = 4 q .. 4 q + 3
+  const int q = tid & 3, zh1 = (tid >> 2) & 15, cg = tid >> 6;
+  const int zslot = ((q ^ ((zh1 >> 1) & 3)) << 2);
+  const int bq = lane >> 4, bn = lane & 15;                  // B fragment lane: nh1' = bn
+  const int bslot = ((bq ^ ((bn >> 1) & 3)) << 2);
+  for (int n1 = pr0 >> 4; n1 <= (pr1 - 1) >> 4; ++n1) {
+    float u1[16];
+#pragma unroll
+    for (int nc1 = 0; nc1 < 16; ++nc1) u1[nc1] = U1[(zh1 + 16 * nc1) * 16 + n1];
+    __syncthreads();                                         // X staged / previous Z consumed
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int cp = 4 * cg + i;
+      f4v z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int nc1 = 0; nc1 < 16; ++nc1) {
+        const f4v x = *reinterpret_cast<const f4v*>(&X[cp * 256 + nc1 * 16 + 4 * q]);
+        z += u1[nc1] * x;
+      }
+      *reinterpret_cast<f4v*>(&Z[cp * 256 + zh1 * 16 + zslot]) = z;
+    }
+    __syncthreads();
+    for (int cp = 0; cp < 16; ++cp) {
+      const f4v zb = *reinterpret_cast<const f4v*>(&Z[cp * 256 + bn * 16 + bslot]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int pr = n1 * 16 + 4 * wave + j;
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[j][s], zb[s], acc, 0, 0, 0);
+        if (pr < pr0 || pr >= pr1) continue;
+        // acc[i] = OUT[nh2' = 4 bq + i][nh1' = bn]
+        double v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = (double)acc[i] * sB;
+        const long row = (long)((pr - pr0) * 16 + cp) * 256 + nc;
+        store_vec<F, 4>(B, row * ldb + (long)rho * 256 + bn * 16 + 4 * bq, bplane, v);
+      }
+    }
+  }
+}
+
 // Non-prime chain (3D), one workgroup per (c, g), for chi_1^2 <= 256: thread (nh1', nc1')
 // reads its chi_2 x chi_2 sub-block of C straight from memory (each element once) and
 // contracts it with U2 (from LDS, the same address for every lane) into registers
