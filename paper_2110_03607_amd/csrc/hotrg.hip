@@ -284,6 +284,10 @@ unsigned grid_for(long n, int block = 256) {
   return (unsigned)std::max(1L, std::min(g, 65536L));
 }
 
+// Grid of the kernels that end in one atomic per workgroup on a single device scalar
+// (max|T|): a grid-stride loop over at most 1024 workgroups keeps those atomics few.
+unsigned grid_reduce(long n) { return std::min(grid_for(n), 1024u); }
+
 // Multi-workgroup tridiagonalisation of the large matrices of an eigensolver batch (one
 // launch per reflector); k_eigh_tri then finishes every matrix.
 void enqueue_tri_steps(const EigBatch& eb, hipStream_t s) {
@@ -552,11 +556,11 @@ int enqueue_gram(hotrg_handle* h, const void* T, bool t_is_f64, const LocalDims&
 
 // The one-workgroup-per-(c, g) non-prime chain holds a thread per (nh1, nc1) pair and
 // chi2 x chi2 x k2 <= 16 x 16 x 16 register/LDS blocks.
-// The MFMA prime chain is written for the saturated chi = 16 step: chi_c = chi_1 = chi_2 = k_1 =
-// k_2 = 16 (H = 4096, b = 256) and a pair range made of whole n1' blocks.
-inline bool prime_mfma_ok(const Dims& dm, long pr0, long pr1) {
-  return dm.chic == 16 && dm.chi1 == 16 && dm.chi2 == 16 && dm.k1 == 16 && dm.k2 == 16 && dm.H == 4096 &&
-         dm.b == 256 && pr0 % 16 == 0 && pr1 % 16 == 0 && pr1 > pr0;
+// Shapes of the MFMA prime chain: every bond dimension and k_j <= 16, chi_2 a multiple of 4
+// (H <= 4096 and b <= 256 follow).
+inline bool prime_mfma_ok(const Dims& dm) {
+  return dm.chic <= 16 && dm.chi1 <= 16 && dm.chi2 <= 16 && dm.k1 <= 16 && dm.k2 <= 16 && dm.chi2 % 4 == 0 &&
+         dm.chi2 >= 4 && dm.H <= 4096 && dm.b <= 256 && dm.H % 4 == 0;
 }
 
 inline bool nstage3c_ok(const Dims& dm) {
@@ -599,10 +603,19 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     hipLaunchKernelGGL((k_zero_pad<ST>), dim3(grid_for((Np - ncols) * Kp + ncols * (Kp - H) + 1)), dim3(256), 0,
                        h->s, Bop, ncols, Np, H, Kp, bplane, FormInfo<F>::planes, 1);
     if constexpr (F != F_FP64) {
-      if (ld.d == 3 && prime_mfma_ok(dm, pr0, pr1) && !h->scalar_prime) {
-        hipLaunchKernelGGL((k_pstage3m<F>), dim3((unsigned)H), dim3(256), 0, h->s, (const float*)T,
-                           (const float*)U1, (const float*)U2, (int)pr0, (int)pr1, Bop, Kp, bplane,
-                           (const DevState*)st);
+      if (ld.d == 3 && prime_mfma_ok(dm) && !h->scalar_prime) {
+        const dim3 g((unsigned)H), t(256);
+        const float *Tf = (const float*)T, *U1f = (const float*)U1, *U2f = (const float*)U2;
+        switch (dm.chi2 / 4) {
+          case 1: hipLaunchKernelGGL((k_pstage3m<F, 1>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
+                                     Kp, bplane, (const DevState*)st); break;
+          case 2: hipLaunchKernelGGL((k_pstage3m<F, 2>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
+                                     Kp, bplane, (const DevState*)st); break;
+          case 3: hipLaunchKernelGGL((k_pstage3m<F, 3>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
+                                     Kp, bplane, (const DevState*)st); break;
+          default: hipLaunchKernelGGL((k_pstage3m<F, 4>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
+                                      Kp, bplane, (const DevState*)st); break;
+        }
         goto prime_done;
       }
     }
@@ -996,10 +1009,10 @@ int enqueue_step_back(hotrg_handle* h, const StepPlan& sp, hipEvent_t t_dec) {
       hipLaunchKernelGGL((k_trace_t<double>), dim3(1), dim3(256), 0, h->s, (const double*)dTn, (int)Hn, st);
     hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, h->s, st);
     if (h->grad)
-      hipLaunchKernelGGL((k_scale_t<double>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (double*)Tn,
+      hipLaunchKernelGGL((k_scale_t<double>), dim3(grid_reduce(Hn * Hn)), dim3(256), 0, h->s, (double*)Tn,
                          (double*)dTn, Hn * Hn, st);
     else
-      hipLaunchKernelGGL((k_scale<double>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (double*)Tn, Hn * Hn, st);
+      hipLaunchKernelGGL((k_scale<double>), dim3(grid_reduce(Hn * Hn)), dim3(256), 0, h->s, (double*)Tn, Hn * Hn, st);
   } else {
     hipLaunchKernelGGL((k_trace_lnz<float>), dim3(1), dim3(256), 0, h->s, (const float*)Tn, (int)Hn, chic, st,
                        h->rec(0));
@@ -1007,10 +1020,10 @@ int enqueue_step_back(hotrg_handle* h, const StepPlan& sp, hipEvent_t t_dec) {
       hipLaunchKernelGGL((k_trace_t<float>), dim3(1), dim3(256), 0, h->s, (const float*)dTn, (int)Hn, st);
     hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, h->s, st);
     if (h->grad)
-      hipLaunchKernelGGL((k_scale_t<float>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (float*)Tn, (float*)dTn,
+      hipLaunchKernelGGL((k_scale_t<float>), dim3(grid_reduce(Hn * Hn)), dim3(256), 0, h->s, (float*)Tn, (float*)dTn,
                          Hn * Hn, st);
     else
-      hipLaunchKernelGGL((k_scale<float>), dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (float*)Tn, Hn * Hn, st);
+      hipLaunchKernelGGL((k_scale<float>), dim3(grid_reduce(Hn * Hn)), dim3(256), 0, h->s, (float*)Tn, Hn * Hn, st);
   }
   tclose(h, HOTRG_T_TRACE, t_tr);
   HIPCHK(h, hipGetLastError());
@@ -1395,7 +1408,7 @@ int hotrg_debug_contract(int d, const int* dims, const int* kdims, int precision
   }
   void* T = h->at<void>(P.off_T);
   void* Tn = h->at<void>(P.off_Tn);
-  hipLaunchKernelGGL(k_maxabs_f64, dim3(grid_for(H * H)), dim3(256), 0, h->s, T_dev, H * H, h->st());
+  hipLaunchKernelGGL(k_maxabs_f64, dim3(grid_reduce(H * H)), dim3(256), 0, h->s, T_dev, H * H, h->st());
   if (precision == HOTRG_FP64) {
     hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(H * H)), dim3(256), 0, h->s, T_dev, (double*)T, H * H);
   } else {
