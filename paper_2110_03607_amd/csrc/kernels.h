@@ -1490,74 +1490,82 @@ __global__ __launch_bounds__(256) void k_pstage3v(const MT* __restrict__ T, cons
   }
 }
 
-// Prime chain (3D) on FP32 MFMA for chi_c = chi_1 = chi_2 = k_1 = k_2 = 16 and chunks of whole
-// n1' blocks (the saturated chi = 16 step).  For the workgroup's row h = (rho, nc) of the hat
-// copy and one n1', the U2 contraction of all 16 c' is one 256 x 256 x 16 product
-//   OUT[(n2', nh2')][(c', nh1')] = sum_{nc2'} U2[nh2' + 16 nc2'][n2'] Z[c'][nh1'][nc2'],
-// with Z[c'][nh1'][nc2'] = sum_{nc1'} U1[nh1' + 16 nc1'][n1'] T[h][(c', nc1', nc2')] on the VALU.
-// Wave w owns the M blocks n2' = 4w .. 4w + 3 and keeps their U2 fragments in registers; at
-// k-step s lane l stands for nc2' = 4 (l / 16) + s, so its B fragment (Z) for one c' is one
-// 16-byte LDS read (chunk nc2' / 4 of row (c', nh1') sits at slot (nc2' / 4) ^ ((nh1' >> 1) & 3)).
-// An accumulator lane holds four consecutive nh2' of one nh1', so each output row (n2', c') is
-// written as 512 contiguous bytes per plane.
-template <int F>
+// Prime chain (3D) on FP32 MFMA, for chi_c, chi_1, chi_2, k_1, k_2 <= 16 with chi_2 % 4 == 0
+// (H <= 4096, b <= 256).  For the workgroup's row h = (rho, nc) of the hat copy and one n1',
+// the U2 contraction of all chi_c values of c' is the product
+//   OUT[(n2', nh2')][(c', nh1')] = sum_{nc2'} U2[nh2' + chi2 nc2'][n2'] Z[c'][nh1'][nc2'],
+// M = k2 chi2 <= 256 rows in blocks of 16, N = 16 columns per c' (nh1' < chi1, the rest zero),
+// K = chi2 in KS = chi2 / 4 k-steps of v_mfma_f32_16x16x4f32; Z[c'][nh1'][nc2'] =
+// sum_{nc1'} U1[nh1' + chi1 nc1'][n1'] T[h][(c', nc1', nc2')] is formed on the VALU.
+// Wave w owns the M blocks w, w + 4, ... and keeps their U2 fragments in registers.  At k-step
+// s lane l stands for nc2' = KS (l / 16) + s, so its B fragment for one c' is one 16-byte LDS
+// read: Z is stored as [c'][nh1'][4 chunks of 4], nc2' = KS q + s at chunk q, element s (zero
+// for s >= KS), chunk q of row nh1' at slot q ^ ((nh1' >> 1) & 3).  Four consecutive rows of
+// an accumulator lane are four consecutive nh2' of one n2' (chi2 % 4 == 0), so a lane writes
+// four adjacent B entries per plane and a wave covers whole rows of its block.
+template <int F, int KS>
 __global__ __launch_bounds__(256) void k_pstage3m(const float* __restrict__ T, const float* __restrict__ U1,
-                                                  const float* __restrict__ U2, int pr0, int pr1,
+                                                  const float* __restrict__ U2, Dims dm, int pr0, int pr1,
                                                   typename Store<F>::T* __restrict__ B, long ldb, long bplane,
                                                   const DevState* __restrict__ st) {
   __shared__ __attribute__((aligned(16))) float X[4096];   // row h of T: [c'][nc1'][nc2']
-  __shared__ __attribute__((aligned(16))) float Z[4096];   // [c'][nh1'][16-byte chunks of nc2']
+  __shared__ __attribute__((aligned(16))) float Z[4096];   // [c'][nh1' < 16][16]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = blockIdx.x;
-  const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * 16.0) : 1.0;   // sqrt(b) = 16
-  const int rho = h >> 8, nc = h & 255;
+  const int b = dm.b, chi1 = dm.chi1, chi2 = dm.chi2, k1 = dm.k1, k2 = dm.k2, chic = dm.chic;
+  const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * sqrt((double)b)) : 1.0;
+  const int rho = h / b, nc = h % b;
+  const int mtot = k2 * chi2, nmb = (mtot + 15) >> 4;
   {
-    const f4v* src = reinterpret_cast<const f4v*>(T + (long)h * 4096);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) reinterpret_cast<f4v*>(X)[tid + 256 * i] = src[tid + 256 * i];
+    const f4v* src = reinterpret_cast<const f4v*>(T + (long)h * dm.H);
+    for (int i = tid; i < dm.H / 4; i += 256) reinterpret_cast<f4v*>(X)[i] = src[i];
+    for (int i = tid; i < 1024; i += 256) reinterpret_cast<f4v*>(Z)[i] = f4v{0.f, 0.f, 0.f, 0.f};
   }
-  float ua[4][4];   // [M block j][k-step s] = U2[(lane & 15) + 16 (4 (lane >> 4) + s)][4 wave + j]
+  const int bq = lane >> 4, bn = lane & 15;                  // fragment lane: k group bq, row/col bn
+  float ua[4][KS];                                           // U2 fragments of blocks wave + 4 jb
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+  for (int jb = 0; jb < 4; ++jb) {
+    const int m = 16 * (wave + 4 * jb) + bn, n2 = m / chi2, nh2 = m % chi2;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) ua[j][s] = U2[((lane & 15) + 16 * (4 * (lane >> 4) + s)) * 16 + 4 * wave + j];
-  // Z entries of this thread: c' = 4 cg + i (i < 4), nh1' = zh1, nc2' = 4 q .. 4 q + 3
-  const int q = tid & 3, zh1 = (tid >> 2) & 15, cg = tid >> 6;
-  const int zslot = ((q ^ ((zh1 >> 1) & 3)) << 2);
-  const int bq = lane >> 4, bn = lane & 15;                  // B fragment lane: nh1' = bn
+    for (int s = 0; s < KS; ++s)
+      ua[jb][s] = m < mtot ? U2[(nh2 + chi2 * (KS * bq + s)) * k2 + n2] : 0.f;
+  }
   const int bslot = ((bq ^ ((bn >> 1) & 3)) << 2);
-  for (int n1 = pr0 >> 4; n1 <= (pr1 - 1) >> 4; ++n1) {
-    float u1[16];
-#pragma unroll
-    for (int nc1 = 0; nc1 < 16; ++nc1) u1[nc1] = U1[(zh1 + 16 * nc1) * 16 + n1];
+  const int nzq = chic * chi1 * KS;                          // Z entries in groups of four nc2'
+  for (int n1 = pr0 / k2; n1 <= (pr1 - 1) / k2; ++n1) {
     __syncthreads();                                         // X staged / previous Z consumed
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int cp = 4 * cg + i;
+    for (int e = tid; e < nzq; e += 256) {
+      const int q = e % KS, zh1 = (e / KS) % chi1, cp = e / (KS * chi1);
       f4v z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int nc1 = 0; nc1 < 16; ++nc1) {
-        const f4v x = *reinterpret_cast<const f4v*>(&X[cp * 256 + nc1 * 16 + 4 * q]);
-        z += u1[nc1] * x;
+      for (int nc1 = 0; nc1 < chi1; ++nc1) {
+        const float u = U1[(zh1 + chi1 * nc1) * k1 + n1];
+        z += u * *reinterpret_cast<const f4v*>(&X[cp * b + nc1 * chi2 + 4 * q]);
       }
-      *reinterpret_cast<f4v*>(&Z[cp * 256 + zh1 * 16 + zslot]) = z;
+      // nc2' = 4 q + t goes to chunk (4 q + t) / KS, element (4 q + t) % KS
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int nc2 = 4 * q + t, cq = nc2 / KS, cs = nc2 % KS;
+        Z[cp * 256 + zh1 * 16 + ((cq ^ ((zh1 >> 1) & 3)) << 2) + cs] = z[t];
+      }
     }
     __syncthreads();
-    for (int cp = 0; cp < 16; ++cp) {
+    for (int cp = 0; cp < chic; ++cp) {
       const f4v zb = *reinterpret_cast<const f4v*>(&Z[cp * 256 + bn * 16 + bslot]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int pr = n1 * 16 + 4 * wave + j;
+      for (int jb = 0; jb < 4; ++jb) {
+        const int mb = wave + 4 * jb;
+        if (mb >= nmb) break;
         f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[j][s], zb[s], acc, 0, 0, 0);
-        if (pr < pr0 || pr >= pr1) continue;
-        // acc[i] = OUT[nh2' = 4 bq + i][nh1' = bn]
+        for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[jb][s], zb[s], acc, 0, 0, 0);
+        // acc[i] = OUT[m = 16 mb + 4 bq + i][nh1' = bn]
+        const int m = 16 * mb + 4 * bq, n2 = m / chi2, nh2 = m % chi2, pr = n1 * k2 + n2;
+        if (m >= mtot || bn >= chi1 || pr < pr0 || pr >= pr1) continue;
         double v[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) v[i] = (double)acc[i] * sB;
-        const long row = (long)((pr - pr0) * 16 + cp) * 256 + nc;
-        store_vec<F, 4>(B, row * ldb + (long)rho * 256 + bn * 16 + 4 * bq, bplane, v);
+        const long row = (long)((pr - pr0) * chic + cp) * b + nc;
+        store_vec<F, 4>(B, row * ldb + (long)rho * b + bn * chi2 + nh2, bplane, v);
       }
     }
   }
