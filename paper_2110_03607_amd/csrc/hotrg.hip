@@ -606,15 +606,18 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
       if (ld.d == 3 && prime_mfma_ok(dm) && !h->scalar_prime) {
         const dim3 g((unsigned)H), t(256);
         const float *Tf = (const float*)T, *U1f = (const float*)U1, *U2f = (const float*)U2;
-        switch (dm.chi2 / 4) {
-          case 1: hipLaunchKernelGGL((k_pstage3m<F, 1>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
-                                     Kp, bplane, (const DevState*)st); break;
-          case 2: hipLaunchKernelGGL((k_pstage3m<F, 2>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
-                                     Kp, bplane, (const DevState*)st); break;
-          case 3: hipLaunchKernelGGL((k_pstage3m<F, 3>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
-                                     Kp, bplane, (const DevState*)st); break;
-          default: hipLaunchKernelGGL((k_pstage3m<F, 4>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
-                                      Kp, bplane, (const DevState*)st); break;
+        const bool all16 = dm.chic == 16 && dm.chi1 == 16 && dm.chi2 == 16 && dm.k1 == 16 && dm.k2 == 16;
+        switch (all16 ? 0 : dm.chi2 / 4) {
+          case 0: hipLaunchKernelGGL((k_pstage3m<F, 4, true>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1,
+                                     Bop, Kp, bplane, (const DevState*)st); break;
+          case 1: hipLaunchKernelGGL((k_pstage3m<F, 1, false>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1,
+                                     Bop, Kp, bplane, (const DevState*)st); break;
+          case 2: hipLaunchKernelGGL((k_pstage3m<F, 2, false>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1,
+                                     Bop, Kp, bplane, (const DevState*)st); break;
+          case 3: hipLaunchKernelGGL((k_pstage3m<F, 3, false>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1,
+                                     Bop, Kp, bplane, (const DevState*)st); break;
+          default: hipLaunchKernelGGL((k_pstage3m<F, 4, false>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0,
+                                      (int)pr1, Bop, Kp, bplane, (const DevState*)st); break;
         }
         goto prime_done;
       }

@@ -1503,7 +1503,8 @@ __global__ __launch_bounds__(256) void k_pstage3v(const MT* __restrict__ T, cons
 // for s >= KS), chunk q of row nh1' at slot q ^ ((nh1' >> 1) & 3).  Four consecutive rows of
 // an accumulator lane are four consecutive nh2' of one n2' (chi2 % 4 == 0), so a lane writes
 // four adjacent B entries per plane and a wave covers whole rows of its block.
-template <int F, int KS>
+// ALL16: every dimension is 16 (the saturated chi = 16 step), folded in at compile time.
+template <int F, int KS, bool ALL16>
 __global__ __launch_bounds__(256) void k_pstage3m(const float* __restrict__ T, const float* __restrict__ U1,
                                                   const float* __restrict__ U2, Dims dm, int pr0, int pr1,
                                                   typename Store<F>::T* __restrict__ B, long ldb, long bplane,
@@ -1512,6 +1513,7 @@ __global__ __launch_bounds__(256) void k_pstage3m(const float* __restrict__ T, c
   __shared__ __attribute__((aligned(16))) float Z[4096];   // [c'][nh1' < 16][16]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = blockIdx.x;
+  if constexpr (ALL16) dm = Dims{3, 16, 16, 16, 16, 16, 256, 4096};
   const int b = dm.b, chi1 = dm.chi1, chi2 = dm.chi2, k1 = dm.k1, k2 = dm.k2, chic = dm.chic;
   const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * sqrt((double)b)) : 1.0;
   const int rho = h / b, nc = h % b;
