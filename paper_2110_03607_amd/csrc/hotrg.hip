@@ -664,8 +664,18 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     hipEvent_t t2 = tmark(h);
     const long ncell = (long)dm.chic * (pr1 - pr0) * dm.chic;   // (c, g) blocks
     const int g0 = (int)(pr0 * dm.chic), gcount = (int)((pr1 - pr0) * dm.chic);
-    if (ld.d == 3 && nstage3c_ok(dm))
-      hipLaunchKernelGGL((k_nstage3c<AT, MT, UT>), dim3((unsigned)(dm.chic * gcount)), dim3(256), 0, h->s,
+    const dim3 gnc((unsigned)(dm.chic * gcount));
+    if (ld.d == 3 && nstage3c_ok(dm) && dm.chi2 == 16)
+      hipLaunchKernelGGL((k_nstage3p<AT, MT, UT, 16>), gnc, dim3(256), 0, h->s, (const AT*)Cc, Np, (const UT*)U1,
+                         (const UT*)U2, dm, g0, gcount, Tn);
+    else if (ld.d == 3 && nstage3c_ok(dm) && dm.chi2 == 12)
+      hipLaunchKernelGGL((k_nstage3p<AT, MT, UT, 12>), gnc, dim3(256), 0, h->s, (const AT*)Cc, Np, (const UT*)U1,
+                         (const UT*)U2, dm, g0, gcount, Tn);
+    else if (ld.d == 3 && nstage3c_ok(dm) && dm.chi2 == 8)
+      hipLaunchKernelGGL((k_nstage3p<AT, MT, UT, 8>), gnc, dim3(256), 0, h->s, (const AT*)Cc, Np, (const UT*)U1,
+                         (const UT*)U2, dm, g0, gcount, Tn);
+    else if (ld.d == 3 && nstage3c_ok(dm))
+      hipLaunchKernelGGL((k_nstage3c<AT, MT, UT>), gnc, dim3(256), 0, h->s,
                          (const AT*)Cc, Np, (const UT*)U1, (const UT*)U2, dm, g0, gcount, Tn);
     else if (ld.d == 3)
       hipLaunchKernelGGL((k_nstage3b<AT, MT, UT>), dim3((unsigned)(dm.chic * ((gcount + 7) / 8))), dim3(256), 0,

@@ -1646,6 +1646,77 @@ __global__ __launch_bounds__(256) void k_nstage3c(const AT* __restrict__ C, long
   }
 }
 
+// Non-prime chain (3D) as k_nstage3c for a compile-time chi_2 (8, 12 or 16, so chi_2 x 4 or 8
+// bytes is a whole number of 16-byte vectors): the loops over the thread's chi_2 rows are
+// unrolled and the rows are fetched PD rows ahead of their use, so each thread keeps several
+// loads in flight instead of one.
+template <class AT, class MT, class UT, int CHI2>
+__global__ __launch_bounds__(256) void k_nstage3p(const AT* __restrict__ C, long ldc, const UT* __restrict__ U1,
+                                                  const UT* __restrict__ U2, Dims dm, int g0, int gcount,
+                                                  MT* __restrict__ Tn) {
+  constexpr int VE = 16 / sizeof(AT), NV = CHI2 / VE, PD = sizeof(AT) == 4 ? 2 : 1;
+  typedef AT vec __attribute__((ext_vector_type(VE)));
+  static_assert(CHI2 % VE == 0, "rows of whole 16-byte vectors");
+  __shared__ AT u1s[256 * 16];   // [nh1 + chi1 nc1][n1]
+  __shared__ AT u2s[256 * 16];   // [nh2 + chi2 nc2][n2]
+  __shared__ AT W[256 * 16];     // [nh1 chi1 + nc1][n2]
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x / gcount, gl = blockIdx.x % gcount;
+  const int b = dm.b, chi1 = dm.chi1, k1 = dm.k1, k2 = dm.k2;
+  const int Hn = k1 * k2 * dm.chic;
+  for (int i = tid; i < chi1 * chi1 * k1; i += 256) u1s[i] = (AT)U1[i];
+  for (int i = tid; i < CHI2 * CHI2 * k2; i += 256) u2s[i] = (AT)U2[i];
+  __syncthreads();
+  if (tid < chi1 * chi1) {
+    const int nh1 = tid / chi1, nc1 = tid % chi1;
+    AT w[16];
+#pragma unroll
+    for (int n2 = 0; n2 < 16; ++n2) w[n2] = 0;
+    const AT* Cb = C + (long)(c * b + nh1 * CHI2) * ldc + (long)gl * b + nc1 * CHI2;
+    // rows nh2 (r0), nh2 + 1 (r1) and, for 4-byte types, nh2 + 2 (r2) are in registers
+    vec r0[NV], r1[NV], r2[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      r0[v] = reinterpret_cast<const vec*>(Cb)[v];
+      if constexpr (PD == 2) r1[v] = reinterpret_cast<const vec*>(Cb + ldc)[v];
+    }
+    for (int nh2 = 0; nh2 < CHI2; ++nh2) {
+      vec* nx = PD == 2 ? r2 : r1;
+      if (nh2 + PD < CHI2) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) nx[v] = reinterpret_cast<const vec*>(Cb + (long)(nh2 + PD) * ldc)[v];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < VE; ++e) {
+          const AT x = r0[v][e];
+          const AT* u = &u2s[(nh2 + CHI2 * (v * VE + e)) * k2];
+#pragma unroll
+          for (int n2 = 0; n2 < 16; ++n2)
+            if (n2 < k2) w[n2] += x * u[n2];
+        }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        r0[v] = r1[v];
+        if constexpr (PD == 2) r1[v] = r2[v];
+      }
+    }
+#pragma unroll
+    for (int n2 = 0; n2 < 16; ++n2)
+      if (n2 < k2) W[tid * k2 + n2] = w[n2];
+  }
+  __syncthreads();
+  if (tid < k1 * k2) {
+    const int n1 = tid / k2, n2 = tid % k2;
+    AT acc = 0;
+    for (int nh1 = 0; nh1 < chi1; ++nh1)
+      for (int nc1 = 0; nc1 < chi1; ++nc1)
+        acc += u1s[(nh1 + chi1 * nc1) * k1 + n1] * W[(nh1 * chi1 + nc1) * k2 + n2];
+    Tn[(long)((n1 * k2 + n2) * dm.chic + c) * Hn + (g0 + gl)] = (MT)acc;
+  }
+}
+
 // Non-prime chain (3D) with U1, U2 staged in LDS; one workgroup per (c, group of up to 8 g).
 template <class AT, class MT, class UT, bool ACC = false>
 __global__ __launch_bounds__(256) void k_nstage3b(const AT* __restrict__ C, long ldc, const UT* __restrict__ U1,

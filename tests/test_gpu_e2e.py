@@ -164,6 +164,18 @@ def test_chunking_does_not_change_results():
     np.testing.assert_allclose(b, a, rtol=1e-13)
 
 
+@pytest.mark.parametrize("precision", ["split_fp16", "fp32"])
+@pytest.mark.parametrize("chi", [8, 12])
+def test_chunking_reduced_forms(precision, chi):
+    """Pair chunks of 5 cut the n1' blocks (k2 = 8 or 12) of the MFMA prime chain: every entry
+    of B and of the product is computed by the same arithmetic as without chunking."""
+    beta = 1 / 4.5115
+    _, a = run_gpu("ising", 3, beta, chi, 7, precision=precision, chunk=0)
+    _, b = run_gpu("ising", 3, beta, chi, 7, precision=precision, chunk=5)
+    print(f"{precision} chi={chi}: max rel diff {np.max(np.abs(np.array(b) - np.array(a)) / np.abs(np.array(a))):.2e}")
+    np.testing.assert_allclose(b, a, rtol=1e-13)
+
+
 def test_state_errors():
     r = P.HOTRG("ising", 2, 0.4, 4, max_steps=2)
     r.step()
