@@ -757,6 +757,18 @@ struct EigDesc {
 // LU with partial pivoting of the tridiagonal T - lam I (diagonal d, subdiagonal e), one
 // thread: U has three diagonals (reciprocal pivot ri, superdiagonals u1, u2), L the
 // multipliers l, pv[r] = 1 when rows r and r + 1 were swapped.  Pivots are floored at pivlu.
+// 1 / q from the hardware reciprocal estimate and two Newton-Raphson steps r <- r + r (1 - q r)
+// (each squares the relative error, so any estimate good to 2^-14 ends within an ulp or two).
+// Used where a quotient sits on a serial dependence chain (the Sturm recurrence) and the
+// IEEE division sequence would cost twice the instructions.  q must be a normal number.
+__device__ inline double recip_nr(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  double t = fma(-q, r, 1.0);
+  r = fma(r, t, r);
+  t = fma(-q, r, 1.0);
+  return fma(r, t, r);
+}
+
 __device__ inline void lu_shifted(const double* d, const double* e, int n, double lam, double pivlu, double* ri,
                                   double* u1, double* u2, double* lq, int* pv) {
   double a0 = d[0] - lam, b0 = n > 1 ? e[0] : 0.0, c0 = 0.0;   // current row: diag, super, super2
@@ -935,7 +947,7 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
         for (int r = 1; r < n; ++r) {
-          q = d[r] - x - e2[r - 1] / q;
+          q = fma(-e2[r - 1], recip_nr(q), d[r] - x);      // |q| >= pivmin: a normal number
           if (fabs(q) < pivmin) q = -pivmin;
           cnt += q < 0.0;
         }
@@ -1061,6 +1073,41 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
 
   // ---- 4. back-transformation: V[:, iv] = H_0 H_1 ... H_{n-3} z_iv -------------
   constexpr int PER = EIG_MAXN / 64;
+  if (kvec <= nw) {
+    // one vector per wave: the reflectors pass through LDS in chunks shared by all waves
+    // (the inverse-iteration arrays are free now), instead of each wave reading them from
+    // global memory one dependent step at a time
+    const int ch = min(32, (int)(sizeof(lu_raw) / sizeof(double)) / n);
+    const bool mine = wv < kvec;
+    double y[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int i = lane + 64 * t;
+      y[t] = (mine && i < n) ? Z[(long)wv * n + i] : 0.0;
+    }
+    for (int k0 = n - 3; k0 >= 0; k0 -= ch) {
+      const int k1 = max(k0 - ch + 1, 0);
+      __syncthreads();                                   // the previous chunk is consumed
+      for (int i = tid; i < (k0 - k1 + 1) * n; i += nt) lu_raw[i] = R[(long)k1 * n + i];
+      __syncthreads();
+      if (mine) {
+        for (int k = k0; k >= k1; --k) {
+          const double* v = lu_raw + (long)(k - k1) * n;
+          double dp = 0.0;
+#pragma unroll
+          for (int t = 0; t < PER; ++t) { const int i = lane + 64 * t; if (i < n) dp += v[i] * y[t]; }
+          for (int o = 32; o > 0; o >>= 1) dp += __shfl_xor(dp, o);
+#pragma unroll
+          for (int t = 0; t < PER; ++t) { const int i = lane + 64 * t; if (i < n) y[t] -= 2.0 * dp * v[i]; }
+        }
+      }
+    }
+    if (mine) {
+#pragma unroll
+      for (int t = 0; t < PER; ++t) { const int i = lane + 64 * t; if (i < n) V[(long)i * n + wv] = y[t]; }
+    }
+    return;
+  }
   for (int iv = wv; iv < kvec; iv += nw) {
     double y[PER];
 #pragma unroll
@@ -1658,8 +1705,8 @@ __global__ __launch_bounds__(256) void k_nstage3p(const AT* __restrict__ C, long
   typedef AT vec __attribute__((ext_vector_type(VE)));
   static_assert(CHI2 % VE == 0, "rows of whole 16-byte vectors");
   __shared__ AT u1s[256 * 16];   // [nh1 + chi1 nc1][n1]
-  __shared__ AT u2s[256 * 16];   // [nh2 + chi2 nc2][n2]
-  __shared__ AT W[256 * 16];     // [nh1 chi1 + nc1][n2]
+  __shared__ AT u2s[256 * 16];   // [nh2 + chi2 nc2][n2]; then W[nh1 chi1 + nc1][n2]
+  AT* W = u2s;                   // (two arrays instead of three: more workgroups per CU)
   const int tid = threadIdx.x;
   const int c = blockIdx.x / gcount, gl = blockIdx.x % gcount;
   const int b = dm.b, chi1 = dm.chi1, k1 = dm.k1, k2 = dm.k2;
@@ -1667,11 +1714,11 @@ __global__ __launch_bounds__(256) void k_nstage3p(const AT* __restrict__ C, long
   for (int i = tid; i < chi1 * chi1 * k1; i += 256) u1s[i] = (AT)U1[i];
   for (int i = tid; i < CHI2 * CHI2 * k2; i += 256) u2s[i] = (AT)U2[i];
   __syncthreads();
+  AT w[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) w[n2] = 0;
   if (tid < chi1 * chi1) {
     const int nh1 = tid / chi1, nc1 = tid % chi1;
-    AT w[16];
-#pragma unroll
-    for (int n2 = 0; n2 < 16; ++n2) w[n2] = 0;
     const AT* Cb = C + (long)(c * b + nh1 * CHI2) * ldc + (long)gl * b + nc1 * CHI2;
     // rows nh2 (r0), nh2 + 1 (r1) and, for 4-byte types, nh2 + 2 (r2) are in registers
     vec r0[NV], r1[NV], r2[NV];
@@ -1702,6 +1749,9 @@ __global__ __launch_bounds__(256) void k_nstage3p(const AT* __restrict__ C, long
         if constexpr (PD == 2) r1[v] = r2[v];
       }
     }
+  }
+  __syncthreads();                 // every thread is done with u2s before W overwrites it
+  if (tid < chi1 * chi1) {
 #pragma unroll
     for (int n2 = 0; n2 < 16; ++n2)
       if (n2 < k2) W[tid * k2 + n2] = w[n2];
