@@ -423,17 +423,19 @@ void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, 
                  hipStream_t s, const FuseArgs* fuse = nullptr, bool small_tiles = false) {
   typedef typename OpOf<F>::type Op;
   constexpr int PL = FormInfo<F>::planes;
-  if constexpr (F != F_FP64 && F != F_FP32) {
-    if (!small_tiles && Z == 1 && smult == 1.0 && Mp % GB_BM == 0 && Np % GB_BN == 0 && Kp % GB_BK == 0) {
+  if constexpr (F != F_FP64) {
+    // FP32 goes through the same kernel with four-k fragments (OpF32v)
+    typedef typename std::conditional<F == F_FP32, OpF32v, Op>::type OpB;
+    if (!small_tiles && Z == 1 && smult == 1.0 && Mp % GB_BM == 0 && Np % GB_BN == 0 && Kp % 64 == 0) {
       const int mt = (int)(Mp / GB_BM), nt = (int)(Np / GB_BN);
       constexpr int WAVES = 8;   // 2 waves per SIMD: one wave's LDS/barrier phase hides under the other's MFMAs
       if (fuse)
-        hipLaunchKernelGGL((k_gemm_big<Op, PL, WAVES, true>), dim3((unsigned)(mt * nt)), dim3(64 * WAVES), 0, s,
-                           (const typename Op::T*)A, lda, aplane, (const typename Op::T*)B, ldb, bplane,
+        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, true>), dim3((unsigned)(mt * nt)), dim3(64 * WAVES), 0, s,
+                           (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B, ldb, bplane,
                            (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, *fuse);
       else
-        hipLaunchKernelGGL((k_gemm_big<Op, PL, WAVES, false>), dim3((unsigned)(mt * nt)), dim3(64 * WAVES), 0, s,
-                           (const typename Op::T*)A, lda, aplane, (const typename Op::T*)B, ldb, bplane,
+        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, false>), dim3((unsigned)(mt * nt)), dim3(64 * WAVES), 0, s,
+                           (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B, ldb, bplane,
                            (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, FuseArgs{});
       return;
     }

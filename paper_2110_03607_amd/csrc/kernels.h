@@ -178,7 +178,7 @@ template <> struct Store<F_SPLIT_FP16> {
 template <int F> struct FormInfo {
   static constexpr bool fp16 = (F == F_FP16 || F == F_SPLIT_FP16);
   static constexpr int planes = (F == F_SPLIT_BF16 || F == F_SPLIT_FP16) ? 2 : 1;
-  static constexpr bool fused_ok = (F != F_FP64 && F != F_FP32);   // 16-bit forms: large-tile GEMM
+  static constexpr bool fused_ok = (F != F_FP64);   // large-tile GEMM with the non-prime epilogue
 };
 
 // ---------------------------------------------------------------------------
@@ -223,6 +223,19 @@ struct OpBF16 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
   __device__ static Frag ld(const T* p) { return *(const Frag*)p; }
+  __device__ static int out_row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
+// FP32 in the large-tile kernel: a 16-byte fragment holds four k values and feeds four
+// v_mfma_f32_16x16x4f32.  At step s lane l stands for k = 4 (l / 16) + s in both operands (a
+// permutation of the 16 k values of the slice, the same for A and B, so the sum is unchanged).
+struct OpF32v {
+  typedef float T; typedef float Acc; typedef f4 AccV; typedef f4v Frag;
+  __device__ static AccV mma(Frag a, Frag b, AccV c) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], c, 0, 0, 0);
+    return c;
+  }
   __device__ static int out_row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
@@ -383,6 +396,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
   typedef typename Op::Frag Frag;
   typedef typename Op::AccV AccV;
   constexpr int THREADS = 64 * WAVES, WNC = WAVES / 2, NB = GB_BN / 16 / WNC, WTN = GB_BN / WNC;
+  constexpr int ES = sizeof(typename Op::T), CE = 16 / ES, BKE = 64 / ES;   // bytes, per chunk, per row
   constexpr int CH = 1024 / THREADS;                        // 16-byte chunks per thread, plane, operand
   constexpr int STAGE = PLANES * (GB_BM + GB_BN) * 64;     // bytes per stage
   __shared__ __attribute__((aligned(16))) char lds[2 * STAGE];
@@ -400,8 +414,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
 #define GB_LD1(k, k0)                                                                                  \
   if constexpr ((k) < PLANES * CH) {                                                                   \
     const int p_ = (k) / CH, q_ = tid + ((k) % CH) * THREADS, r_ = q_ >> 2, c_ = q_ & 3;               \
-    sa##k = *(const uint4*)(Ab + 2 * (p_ * a_plane + (m0 + r_) * lda + (k0) + c_ * 8));               \
-    sb##k = *(const uint4*)(Bb + 2 * (p_ * b_plane + (n0 + r_) * ldb + (k0) + c_ * 8));               \
+    sa##k = *(const uint4*)(Ab + ES * (p_ * a_plane + (m0 + r_) * lda + (k0) + c_ * CE));             \
+    sb##k = *(const uint4*)(Bb + ES * (p_ * b_plane + (n0 + r_) * ldb + (k0) + c_ * CE));             \
   }
 #define GB_ST1(k, stage)                                                                               \
   if constexpr ((k) < PLANES * CH) {                                                                   \
@@ -422,13 +436,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = AccV{0, 0, 0, 0};
 
-  const int nk = Kp / GB_BK;
+  const int nk = Kp / BKE;
   GB_GLOAD(0);
   GB_LSTORE(0);
   __syncthreads();
   const int fr = lane & 15, fc = lane >> 4;
   for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) { GB_GLOAD((long)(kt + 1) * GB_BK); }
+    if (kt + 1 < nk) { GB_GLOAD((long)(kt + 1) * BKE); }
     const char* base = lds + (kt & 1) * STAGE;
     Frag b[PLANES][NB];
 #pragma unroll
