@@ -565,6 +565,34 @@ inline bool prime_mfma_ok(const Dims& dm) {
          dm.chi2 >= 4 && dm.H <= 4096 && dm.b <= 256 && dm.H % 4 == 0;
 }
 
+// Prime chain on MFMA (3D, reduced forms) for the pair range [pr0, pr1); false, with nothing
+// launched, when the form or the shape needs the VALU kernels.
+template <int F>
+bool launch_prime_mfma(hipStream_t s, const Dims& dm, const void* T, const void* U1, const void* U2, long pr0,
+                       long pr1, typename Store<F>::T* Bop, long Kp, long bplane, const DevState* st) {
+  if constexpr (F == F_FP64) {
+    return false;
+  } else {
+    if (!prime_mfma_ok(dm)) return false;
+    const dim3 g((unsigned)dm.H), t(256);
+    const float *Tf = (const float*)T, *U1f = (const float*)U1, *U2f = (const float*)U2;
+    const bool all16 = dm.chic == 16 && dm.chi1 == 16 && dm.chi2 == 16 && dm.k1 == 16 && dm.k2 == 16;
+    switch (all16 ? 0 : dm.chi2 / 4) {
+      case 0: hipLaunchKernelGGL((k_pstage3m<F, 4, true>), g, t, 0, s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
+                                 Kp, bplane, st); break;
+      case 1: hipLaunchKernelGGL((k_pstage3m<F, 1, false>), g, t, 0, s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
+                                 Kp, bplane, st); break;
+      case 2: hipLaunchKernelGGL((k_pstage3m<F, 2, false>), g, t, 0, s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
+                                 Kp, bplane, st); break;
+      case 3: hipLaunchKernelGGL((k_pstage3m<F, 3, false>), g, t, 0, s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
+                                 Kp, bplane, st); break;
+      default: hipLaunchKernelGGL((k_pstage3m<F, 4, false>), g, t, 0, s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1, Bop,
+                                  Kp, bplane, st); break;
+    }
+    return true;
+  }
+}
+
 inline bool nstage3c_ok(const Dims& dm) {
   return dm.chi1 <= 16 && dm.chi2 <= 16 && dm.k1 <= 16 && dm.k2 <= 16;
 }
@@ -604,27 +632,11 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     hipEvent_t t0 = tmark(h);
     hipLaunchKernelGGL((k_zero_pad<ST>), dim3(grid_for((Np - ncols) * Kp + ncols * (Kp - H) + 1)), dim3(256), 0,
                        h->s, Bop, ncols, Np, H, Kp, bplane, FormInfo<F>::planes, 1);
-    if constexpr (F != F_FP64) {
-      if (ld.d == 3 && prime_mfma_ok(dm) && !h->scalar_prime) {
-        const dim3 g((unsigned)H), t(256);
-        const float *Tf = (const float*)T, *U1f = (const float*)U1, *U2f = (const float*)U2;
-        const bool all16 = dm.chic == 16 && dm.chi1 == 16 && dm.chi2 == 16 && dm.k1 == 16 && dm.k2 == 16;
-        switch (all16 ? 0 : dm.chi2 / 4) {
-          case 0: hipLaunchKernelGGL((k_pstage3m<F, 4, true>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1,
-                                     Bop, Kp, bplane, (const DevState*)st); break;
-          case 1: hipLaunchKernelGGL((k_pstage3m<F, 1, false>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1,
-                                     Bop, Kp, bplane, (const DevState*)st); break;
-          case 2: hipLaunchKernelGGL((k_pstage3m<F, 2, false>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1,
-                                     Bop, Kp, bplane, (const DevState*)st); break;
-          case 3: hipLaunchKernelGGL((k_pstage3m<F, 3, false>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0, (int)pr1,
-                                     Bop, Kp, bplane, (const DevState*)st); break;
-          default: hipLaunchKernelGGL((k_pstage3m<F, 4, false>), g, t, 0, h->s, Tf, U1f, U2f, dm, (int)pr0,
-                                      (int)pr1, Bop, Kp, bplane, (const DevState*)st); break;
-        }
-        goto prime_done;
-      }
-    }
-    if (ld.d == 3 && dm.chi2 % 8 == 0 && !h->scalar_prime)
+    const bool mfma_prime = ld.d == 3 && !h->scalar_prime &&
+                            launch_prime_mfma<F>(h->s, dm, T, U1, U2, pr0, pr1, Bop, Kp, bplane, st);
+    if (mfma_prime)
+      ;                                    // launched above
+    else if (ld.d == 3 && dm.chi2 % 8 == 0 && !h->scalar_prime)
       hipLaunchKernelGGL((k_pstage3v<MT, UT, F, 8>), dim3((unsigned)H), dim3(256), 0, h->s, T, (const UT*)U1,
                          (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane, (const DevState*)st);
     else if (ld.d == 3 && dm.chi2 % 4 == 0 && !h->scalar_prime)
@@ -637,7 +649,6 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
       hipLaunchKernelGGL((k_pstage<MT, UT, F>), dim3((unsigned)(H * dm.chic)), dim3(256), 0, h->s, T,
                          (const UT*)U1, (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane,
                          (const DevState*)st);
-  prime_done:
     tclose(h, HOTRG_T_PRIME, t0);
     const double* sp = nullptr;
     if (FormInfo<F>::fp16) {
