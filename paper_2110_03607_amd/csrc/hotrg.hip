@@ -491,10 +491,17 @@ int enqueue_gram(hotrg_handle* h, const void* T, bool t_is_f64, const LocalDims&
       ps.od[k] = dims2[l]; ps.sstride[k++] = str[l];
     }
     ps.rows = R; ps.cols = g.C; ps.rows_p = g.Rp; ps.ldd = g.Cp;
+    const bool by4 = ps.cols % 4 == 0 && ps.ldd % 4 == 0 && ps.od[ps.nd - 1] % 4 == 0 && ps.nd > ps.nrow;
     auto permute = [&](const void* src, double* dst) {
-      if (t_is_f64)
+      if (t_is_f64 && by4)
+        hipLaunchKernelGGL((k_permute4<double, double>), dim3(grid_for(g.Rp * g.Cp / 4)), dim3(256), 0, h->s,
+                           (const double*)src, dst, ps, 1.0);
+      else if (t_is_f64)
         hipLaunchKernelGGL((k_permute<double, double>), dim3(grid_for(g.Rp * g.Cp)), dim3(256), 0, h->s,
                            (const double*)src, dst, ps, 1.0);
+      else if (by4)
+        hipLaunchKernelGGL((k_permute4<float, double>), dim3(grid_for(g.Rp * g.Cp / 4)), dim3(256), 0, h->s,
+                           (const float*)src, dst, ps, 1.0);
       else
         hipLaunchKernelGGL((k_permute<float, double>), dim3(grid_for(g.Rp * g.Cp)), dim3(256), 0, h->s,
                            (const float*)src, dst, ps, 1.0);

@@ -662,6 +662,30 @@ __global__ void k_permute(const S* __restrict__ src, D* __restrict__ dst, PermSp
   }
 }
 
+// k_permute four destination columns at a time (one index decomposition for four elements):
+// needs cols, ldd and the innermost destination dimension to be multiples of 4, so the four
+// columns share every index but the innermost and sit at source offsets off + e * its stride.
+template <class S, class D>
+__global__ void k_permute4(const S* __restrict__ src, D* __restrict__ dst, PermSpec ps, double scale) {
+  const long total = ps.rows_p * ps.ldd / 4;
+  const long inner = ps.sstride[ps.nd - 1];
+  for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < total; q += (long)gridDim.x * blockDim.x) {
+    const long i = 4 * q, row = i / ps.ldd, col = i % ps.ldd;
+    D v[4];
+    if (row >= ps.rows || col >= ps.cols) {
+      v[0] = v[1] = v[2] = v[3] = (D)0;
+    } else {
+      long off = 0, rr = row, cc = col;
+      for (int k = ps.nd - 1; k >= ps.nrow; --k) { off += (cc % ps.od[k]) * ps.sstride[k]; cc /= ps.od[k]; }
+      for (int k = ps.nrow - 1; k >= 0; --k) { off += (rr % ps.od[k]) * ps.sstride[k]; rr /= ps.od[k]; }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = (D)((double)src[off + e * inner] * scale);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dst[i + e] = v[e];
+  }
+}
+
 // A operand of the bottleneck in form F: A[m][k] = s_A * T[m][k] for m, k < H, zero padded
 // to Mp x Kp.  s_A = 1 except for the FP16 forms (power of two from max|T|).
 // The operand rows may be longer than Kp (ld >= Kp, derivative mode stores [dT | T] per row):
@@ -1027,16 +1051,19 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
     while (j0 > 0 && fabs(w[j0 - 1] - w[iv]) <= ortol) --j0;
     return j0;
   };
-  // independent vectors, a wave each
-  const bool side_by_side = n <= PW_MAXN;
-  if (side_by_side && wv < PW_WAVES) {
-    double* base = lu_raw + wv * (PW_MAXN * 5 + PW_MAXN / 2);
-    double *ri = base, *u1 = ri + PW_MAXN, *u2 = u1 + PW_MAXN, *lq = u2 + PW_MAXN, *z = lq + PW_MAXN;
-    int* pv = (int*)(z + PW_MAXN);
+  // independent vectors, a wave each: as many waves as sets of factor arrays (5 n doubles and
+  // n ints) fit in lu_raw, at most PW_WAVES (8 up to n = 256, 3 at n = 576, 2 at n = 1024)
+  const int pw_stride = 5 * n + (n + 1) / 2;
+  const int pw_waves = min(PW_WAVES, (int)(sizeof(lu_raw) / sizeof(double)) / pw_stride);
+  const bool side_by_side = pw_waves >= 2;
+  if (side_by_side && wv < pw_waves) {
+    double* base = lu_raw + wv * pw_stride;
+    double *ri = base, *u1 = ri + n, *u2 = u1 + n, *lq = u2 + n, *z = lq + n;
+    int* pv = (int*)(z + n);
     int rank = 0;                                        // position among the independent vectors
     for (int iv = 0; iv < kvec; ++iv) {
       if (first_in_cluster(iv) != iv) continue;
-      if (rank++ % PW_WAVES != wv) continue;
+      if (rank++ % pw_waves != wv) continue;
       if (lane == 0) lu_shifted(d, e, n, w[iv], pivlu, ri, u1, u2, lq, pv);
       start_vector(z, iv, lane, 64);
       __threadfence_block();
@@ -1087,38 +1114,47 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
 
   // ---- 4. back-transformation: V[:, iv] = H_0 H_1 ... H_{n-3} z_iv -------------
   constexpr int PER = EIG_MAXN / 64;
-  if (kvec <= nw) {
-    // one vector per wave: the reflectors pass through LDS in chunks shared by all waves
-    // (the inverse-iteration arrays are free now), instead of each wave reading them from
-    // global memory one dependent step at a time
+  if (kvec <= 2 * nw) {
+    // up to two vectors per wave (wv and wv + nw): the reflectors pass through LDS in chunks
+    // shared by all waves (the inverse-iteration arrays are free now), instead of each wave
+    // reading them from global memory one dependent step at a time
     const int ch = min(32, (int)(sizeof(lu_raw) / sizeof(double)) / n);
-    const bool mine = wv < kvec;
-    double y[PER];
+    const bool has0 = wv < kvec, has1 = wv + nw < kvec;
+    double y0[PER], y1[PER];
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
       const int i = lane + 64 * t;
-      y[t] = (mine && i < n) ? Z[(long)wv * n + i] : 0.0;
+      y0[t] = (has0 && i < n) ? Z[(long)wv * n + i] : 0.0;
+      y1[t] = (has1 && i < n) ? Z[(long)(wv + nw) * n + i] : 0.0;
     }
     for (int k0 = n - 3; k0 >= 0; k0 -= ch) {
       const int k1 = max(k0 - ch + 1, 0);
       __syncthreads();                                   // the previous chunk is consumed
       for (int i = tid; i < (k0 - k1 + 1) * n; i += nt) lu_raw[i] = R[(long)k1 * n + i];
       __syncthreads();
-      if (mine) {
+      if (has0) {
         for (int k = k0; k >= k1; --k) {
           const double* v = lu_raw + (long)(k - k1) * n;
-          double dp = 0.0;
+          double dp0 = 0.0, dp1 = 0.0;
 #pragma unroll
-          for (int t = 0; t < PER; ++t) { const int i = lane + 64 * t; if (i < n) dp += v[i] * y[t]; }
-          for (int o = 32; o > 0; o >>= 1) dp += __shfl_xor(dp, o);
+          for (int t = 0; t < PER; ++t) {
+            const int i = lane + 64 * t;
+            if (i < n) { dp0 += v[i] * y0[t]; dp1 += v[i] * y1[t]; }
+          }
+          for (int o = 32; o > 0; o >>= 1) { dp0 += __shfl_xor(dp0, o); dp1 += __shfl_xor(dp1, o); }
 #pragma unroll
-          for (int t = 0; t < PER; ++t) { const int i = lane + 64 * t; if (i < n) y[t] -= 2.0 * dp * v[i]; }
+          for (int t = 0; t < PER; ++t) {
+            const int i = lane + 64 * t;
+            if (i < n) { y0[t] -= 2.0 * dp0 * v[i]; y1[t] -= 2.0 * dp1 * v[i]; }
+          }
         }
       }
     }
-    if (mine) {
 #pragma unroll
-      for (int t = 0; t < PER; ++t) { const int i = lane + 64 * t; if (i < n) V[(long)i * n + wv] = y[t]; }
+    for (int t = 0; t < PER; ++t) {
+      const int i = lane + 64 * t;
+      if (has0 && i < n) V[(long)i * n + wv] = y0[t];
+      if (has1 && i < n) V[(long)i * n + wv + nw] = y1[t];
     }
     return;
   }
