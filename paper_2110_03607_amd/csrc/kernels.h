@@ -450,6 +450,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
 #pragma unroll
       for (int j = 0; j < NB; ++j)
         b[p][j] = *(const Frag*)(base + p * (GB_BM + GB_BN) * 64 + GB_BM * 64 + swz(wn * WTN + j * 16 + fr, fc));
+    // the compiler's MFMA / LDS-read interleaving strategy 0 for this block (bottleneck 77.6 ->
+    // 75.4 ms per chi = 16 step against its default schedule)
+    __builtin_amdgcn_iglp_opt(0);
     // MFMA phase at raised wave priority: the other wave of the SIMD issues its loads and LDS
     // stores in the gaps instead of competing for issue with these MFMAs
     __builtin_amdgcn_s_setprio(1);
