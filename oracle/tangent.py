@@ -101,8 +101,9 @@ def isometry_tangent(A, dA, Ap, dAp, chi):
     return tr, Ut, dUt
 
 
-def run_with_tangent(model: H.Model, beta: float, chi: int, steps: int):
-    """Returns (lnz0, dlnz0, [(lnz_p, dlnz_p) for p = 1..steps])."""
+def run_with_tangent(model: H.Model, beta: float, chi: int, steps: int, on_step=None):
+    """Returns (lnz0, dlnz0, [(lnz_p, dlnz_p) for p = 1..steps]).  on_step(p, lnz_p, dlnz_p),
+    when given, is called after every step (progress reports; no effect on the values)."""
     W, V, dW, dV = weight_derivatives(model, beta)
     X, dX = bond_factor_tangent(W, dW)
     T0, dT0 = initial_tensor_tangent(X, dX, V, dV, model.d)
@@ -127,6 +128,8 @@ def run_with_tangent(model: H.Model, beta: float, chi: int, steps: int):
         lnz += math.log(t) / 2.0 ** p
         dlnz += (dt / t) / 2.0 ** p
         recs.append((lnz, dlnz))
+        if on_step is not None:
+            on_step(p, lnz, dlnz)
         T = H.rename(Tnew / t)
         dT = H.rename(dTnew / t - Tnew * dt / t ** 2)
     return out0[0], out0[1], recs

@@ -1,6 +1,10 @@
 """Write oracle fixtures for the physics configurations (calls only oracle/).
 
 Usage:  python tests/golden/make_golden.py config1 config2 [config3 ...]
+        python tests/golden/make_golden.py grad_config5 BETA [STEPS]
+
+The script refuses to run while oracle/, this script or tests/seeded_inputs.py differ from
+the committed tree, so that the commit stamped into every fixture is the code that wrote it.
 
 Each fixture is JSON: the configuration, per-run lnZ/V after every step, the
 trace t_p, the Gu-Wen ratio, the judgement values and the leading normalised
@@ -62,11 +66,25 @@ def run_config(name, cfg, betas):
     return runs
 
 
+# Files whose committed state a fixture depends on.
+SOURCES = ("oracle", "tests/golden/make_golden.py", "tests/seeded_inputs.py")
+
+
+def committed_revision():
+    """HEAD, after checking that the oracle and the input generators have no uncommitted
+    changes (else the stamp would name code other than the code that ran)."""
+    dirty = subprocess.check_output(["git", "-C", ROOT, "status", "--porcelain", "--", *SOURCES], text=True)
+    if dirty.strip():
+        raise SystemExit("make_golden.py: uncommitted changes in " + ", ".join(SOURCES) + ":\n" + dirty
+                         + "commit them first; the fixture records the commit that wrote it")
+    return subprocess.check_output(["git", "-C", ROOT, "rev-parse", "HEAD"], text=True).strip()
+
+
+REVISION = None
+
+
 def provenance():
-    try:
-        rev = subprocess.check_output(["git", "-C", ROOT, "rev-parse", "HEAD"], text=True).strip()
-    except Exception:
-        rev = "unknown"
+    rev = REVISION
     cpu = platform.processor()
     try:
         with open("/proc/cpuinfo") as f:
@@ -104,36 +122,86 @@ def run_grad():
     return runs
 
 
-# Batched sweep: the instances of the sweep checked against the oracle (both ends of the
-# 3D temperature range; the first and last three 2D instances, one per chi).
-CONFIG4_SAMPLE_3D = (0, 63)
-CONFIG4_SAMPLE_2D = (0, 1, 2, 45, 46, 47)
+# Batched sweep: the instances of the sweep checked against the oracle -- every 4th 3D
+# temperature and the last one (17 of 64), and all 48 2D instances.
+CONFIG4_SAMPLE_3D = tuple(range(0, 64, 4)) + (63,)
+CONFIG4_SAMPLE_2D = tuple(range(48))
 
 
-def run_config4():
+def run_config4(write):
+    """Runs the sampled instances one by one; write(runs) is called after each (partial file)."""
     c3, c2 = SI.CONFIG4_3D, SI.CONFIG4_2D
     runs = []
-    for i in CONFIG4_SAMPLE_3D:
-        cfg = dict(kind=c3["kind"], d=3, q=2, chi=c3["chi"], steps=c3["steps"])
-        r = run_config(f"config4 3D[{i}]", cfg, [1.0 / c3["temps"][i]])[0]
-        r.update(index=i, d=3, chi=c3["chi"])
-        runs.append(r)
     for i in CONFIG4_SAMPLE_2D:
         chi = c2["chis"][i % len(c2["chis"])]
         cfg = dict(kind=c2["kind"], d=2, q=2, chi=chi, steps=c2["steps"])
         r = run_config(f"config4 2D[{i}]", cfg, [float(c2["betas"][i])])[0]
         r.update(index=i, d=2, chi=chi)
         runs.append(r)
+        write(runs)
+    for i in CONFIG4_SAMPLE_3D:
+        cfg = dict(kind=c3["kind"], d=3, q=2, chi=c3["chi"], steps=c3["steps"])
+        r = run_config(f"config4 3D[{i}]", cfg, [1.0 / c3["temps"][i]])[0]
+        r.update(index=i, d=3, chi=c3["chi"])
+        runs.append(r)
+        write(runs)
     return runs
 
 
-def main(names):
-    if "config4" in names:
-        doc = dict(config="config4", runs=run_config4(), steps=SI.CONFIG4_3D["steps"], provenance=provenance(),
-                   source="oracle/hotrg.py (FP64 NumPy), written by tests/golden/make_golden.py")
-        path = os.path.join(HERE, "config4.json")
-        with open(path, "w") as f:
+def grad_config5_path(beta):
+    return os.path.join(HERE, f"grad_config5_beta{beta:.2f}.json")
+
+
+def run_grad_config5(beta, steps):
+    """The oracle's forward-mode derivative for 3D 3-state Potts, chi = 16 (the derivative
+    configuration) at one beta; the file is rewritten after every step, so that a partial
+    run leaves the steps it finished (`steps_done`)."""
+    cfg = SI.CONFIG5
+    t0 = time.time()
+    doc = dict(config="grad_config5", kind=cfg["kind"], d=cfg["d"], q=cfg["q"], chi=cfg["chi"], beta=beta,
+               steps_planned=steps, steps_done=0, lnz=[], dlnz=[], step_seconds=[], provenance=provenance(),
+               source="oracle/tangent.py (FP64 NumPy), written by tests/golden/make_golden.py")
+    last = [time.time()]
+
+    def on_step(p, lnz, dlnz):
+        now = time.time()
+        doc["lnz"].append(lnz)
+        doc["dlnz"].append(dlnz)
+        doc["step_seconds"].append(now - last[0])
+        doc["steps_done"] = p
+        doc["wall_seconds"] = now - t0
+        last[0] = now
+        with open(grad_config5_path(beta), "w") as f:
             json.dump(doc, f, indent=1)
+        print(f"  grad_config5 beta={beta:.2f} step {p} lnz/V={lnz:.15f} dlnz/dbeta={dlnz:.15f} "
+              f"({doc['step_seconds'][-1]:.0f}s)", flush=True)
+
+    lnz0, dlnz0, _ = TG.run_with_tangent(H.Model(cfg["kind"], cfg["d"], cfg["q"]), beta, cfg["chi"], steps,
+                                          on_step=on_step)
+    doc.update(lnz0=lnz0, dlnz0=dlnz0)
+    with open(grad_config5_path(beta), "w") as f:
+        json.dump(doc, f, indent=1)
+    print("wrote", grad_config5_path(beta), flush=True)
+
+
+def main(names):
+    global REVISION
+    REVISION = committed_revision()
+    if names and names[0] == "grad_config5":
+        beta = float(names[1])
+        steps = int(names[2]) if len(names) > 2 else 6
+        run_grad_config5(beta, steps)
+        return
+    if "config4" in names:
+        path = os.path.join(HERE, "config4.json")
+
+        def write(runs):
+            doc = dict(config="config4", runs=runs, steps=SI.CONFIG4_3D["steps"], provenance=provenance(),
+                       source="oracle/hotrg.py (FP64 NumPy), written by tests/golden/make_golden.py")
+            with open(path, "w") as f:
+                json.dump(doc, f, indent=1)
+
+        run_config4(write)
         print("wrote", path, flush=True)
         names = [n for n in names if n != "config4"]
     if "grad" in names:
