@@ -6,7 +6,7 @@
  * that decide the truncation (Sections 3.2 and 4.2.4), their eigendecomposition
  * (Section 4.2.5), the choice and truncation of the isometries (Sections 2,
  * 4.2.6-4.2.7), the new-tensor contraction in the prime chain / bottleneck /
- * non-prime chain order (Section 4.2.8, eqs. TU1-TUNCD, BottleneckPart,
+ * non-prime chain order (Section 4.2.9, eqs. TU1-TUNCD, BottleneckPart,
  * AfterBNNCD-AfterBN1), the renaming of Section 3.1.3, and the lnZ/V
  * bookkeeping of Section 4.1.1 (eqs. eq_lnZ, K_recurrence).
  *
@@ -73,7 +73,7 @@ typedef struct hotrg_opts {
     int max_steps;    /* capacity of the per-step record (diagnostics), >= 1      */
     int chunk;        /* new-tensor columns per chunk in units of (n'_1..,c') groups;
                          0 = automatic.  Bounds the memory of the prime-chain output
-                         (the paper's loop over n'_1, Section 4.2.8).            */
+                         (the paper's loop over n'_1, Section 4.2.9).            */
     int record_grad;  /* 1: carry d/dbeta through every step (FP64 / FP32 forms,
                          beta > 0); hotrg_grad then returns d(lnZ/V)/dbeta        */
 } hotrg_opts;
@@ -112,6 +112,21 @@ int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts*
                void* workspace_dev, size_t workspace_bytes, void* hip_stream,
                hotrg_handle** out);
 
+/* Bytes of device workspace for a run started from a supplied tensor (hotrg_init_tensor);
+ * 0 for an invalid argument. */
+size_t hotrg_tensor_workspace_bytes(int d, const int* dims, int chi, const hotrg_opts* opts);
+
+/* Start a run from a caller-supplied local tensor instead of a lattice model: the method of
+ * Sections 3-4 coarse-grains any translation-invariant network of one local tensor.  T0_dev is
+ * FP64 device memory in the storage order above with dims[0] = chi_c (lattice axis 0, the first
+ * Current direction), dims[j] = chi_{n_j}; 1 <= dims[i], chi <= 16 (d = 3) or 32 (d = 2).  T0
+ * is read (the caller keeps ownership; it may be freed once the stream has passed this call),
+ * normalised by f^(0) = 1/Tr T0 (Section 3.1.3), and lnZ/V at p = 0 is ln Tr T0.  opts.record_grad
+ * must be 0.  A non-positive or non-finite Tr T0 is reported as HOTRG_E_NUMERIC by the first
+ * synchronising call (sticky).  Errors: HOTRG_E_ARG, HOTRG_E_OOM, HOTRG_E_DEVICE. */
+int hotrg_init_tensor(int d, const int* dims, const double* T0_dev, int chi, const hotrg_opts* opts,
+                      void* workspace_dev, size_t workspace_bytes, void* hip_stream, hotrg_handle** out);
+
 /* Enqueue one coarse-graining step along lattice axis `axis` (0 <= axis < d).
  * Any order is allowed; following the cycle 0, 1, .., d-1, 0, .. of the
  * renaming in Section 3.1.3 needs no re-layout.  The lattice volume doubles.
@@ -138,7 +153,7 @@ int hotrg_spectrum(hotrg_handle* h, int step, int dir, int side, double* out, in
 #define HOTRG_T_PRIME       1  /* prime chain into the B operand (eqs. TU1..TUNCD)          */
 #define HOTRG_T_BOTTLENECK  2  /* bottleneck GEMM (eq. BottleneckPart), one entry per chunk */
 #define HOTRG_T_NONPRIME    3  /* non-prime chain + renaming (eqs. AfterBNNCD..AfterBN1)    */
-#define HOTRG_T_TRACE       4  /* trace, lnZ/V, normalisation (4.2.11-4.2.14)                */
+#define HOTRG_T_TRACE       4  /* trace, lnZ/V, normalisation (4.2.11, 4.2.15-4.2.17)        */
 #define HOTRG_T_CONTRACT    5  /* whole new-tensor contraction incl. the A operand          */
 #define HOTRG_T_STEP        6  /* whole hotrg_step                                          */
 #define HOTRG_T_COUNT       7
@@ -202,7 +217,10 @@ size_t hotrg_debug_eigh_workspace_bytes(int n, int batch);
  * inverse iteration -- the solver used for A and A' in Section 4.2.5) of `batch`
  * (1..4) row-major n x n matrices (1 <= n <= 1024): eigenvalues descending into
  * w_dev[batch][n], eigenvectors as columns of V_dev[batch][n][n] (row-major).
- * A_dev is overwritten.  Errors: HOTRG_E_ARG, HOTRG_E_OOM, HOTRG_E_DEVICE. */
+ * A_dev is overwritten.  Errors: HOTRG_E_ARG, HOTRG_E_OOM, HOTRG_E_DEVICE, and
+ * HOTRG_E_NUMERIC when the tridiagonal form has a non-finite entry, an eigenvalue is not
+ * resolved within the bisection's iteration cap, or an eigenpair's residual
+ * ||T z - lambda z|| exceeds 1e-9 |T| (the same failure makes hotrg_step's run fail). */
 int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_dev,
                      void* workspace_dev, size_t workspace_bytes, void* hip_stream);
 

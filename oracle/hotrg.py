@@ -277,7 +277,7 @@ def choose_isometry(A: np.ndarray, Ap: np.ndarray, chi: int, multiplets: bool = 
 
 
 # ----------------------------------------------------------------------------
-# Section 4.2.8: the new local tensor in three stages (eq. Contraction_NewTensor)
+# Section 4.2.9: the new local tensor in three stages (eq. Contraction_NewTensor)
 # ----------------------------------------------------------------------------
 
 
@@ -291,7 +291,7 @@ def _contract_leg(X: np.ndarray, axis: int, W: np.ndarray) -> np.ndarray:
 def new_tensor(T: np.ndarray, Ut: dict[int, np.ndarray], only=None, T_check: np.ndarray | None = None,
                U_prime: dict[int, np.ndarray] | None = None) -> np.ndarray:
     """T^new[n_{d-1}..n_1, n'_{d-1}..n'_1, c, c'] from two copies of T (hat and check)
-    and the isometries Ut[j] (chi_{n_j}^2 x chi_new_j), in the order of Section 4.2.8:
+    and the isometries Ut[j] (chi_{n_j}^2 x chi_new_j), in the order of Section 4.2.9:
 
       prime chain   eqs. (TU1)..(TUNCD): contract each n'^check_j with U^(j)
       bottleneck    eq. (BottleneckPart): sum over n'^hat_{d-1}..n'^hat_1 and rho

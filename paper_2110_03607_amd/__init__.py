@@ -72,6 +72,11 @@ _SIGS = {
     "hotrg_init": (ctypes.c_int, [ctypes.POINTER(hotrg_model), ctypes.c_double, ctypes.c_int,
                                   ctypes.POINTER(hotrg_opts), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                   ctypes.POINTER(ctypes.c_void_p)]),
+    "hotrg_tensor_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                                       ctypes.POINTER(hotrg_opts)]),
+    "hotrg_init_tensor": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.POINTER(hotrg_opts), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
     "hotrg_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hotrg_log_z": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     "hotrg_step_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(hotrg_step_record)]),
@@ -154,6 +159,20 @@ def hotrg_init(model: hotrg_model, beta: float, chi: int, opts: hotrg_opts, work
     h = ctypes.c_void_p()
     rc = lib().hotrg_init(ctypes.byref(model), beta, chi, ctypes.byref(opts), ctypes.c_void_p(workspace_ptr),
                           workspace_bytes, ctypes.c_void_p(stream_ptr), ctypes.byref(h))
+    _check(rc, None)
+    return h
+
+
+def hotrg_tensor_workspace_bytes(d: int, dims, chi: int, opts: hotrg_opts) -> int:
+    return lib().hotrg_tensor_workspace_bytes(d, _ints(dims), chi, ctypes.byref(opts))
+
+
+def hotrg_init_tensor(d: int, dims, T0_ptr: int, chi: int, opts: hotrg_opts, workspace_ptr: int,
+                      workspace_bytes: int, stream_ptr: int):
+    h = ctypes.c_void_p()
+    rc = lib().hotrg_init_tensor(d, _ints(dims), ctypes.c_void_p(T0_ptr), chi, ctypes.byref(opts),
+                                 ctypes.c_void_p(workspace_ptr), workspace_bytes, ctypes.c_void_p(stream_ptr),
+                                 ctypes.byref(h))
     _check(rc, None)
     return h
 
@@ -331,6 +350,32 @@ class HOTRG:
         self.stream = torch.cuda.current_stream()
         self.handle = hotrg_init(self.model, beta, chi, self.opts, aligned, nbytes, self.stream.cuda_stream)
         self.steps = 0
+
+    @classmethod
+    def from_tensor(cls, T0, chi: int, precision: str = "fp64", max_steps: int = 64, chunk: int = 0):
+        """A run started from a local tensor T0 (a float64 torch tensor on the GPU, storage order
+        T[c][n_1]..[c'][n'_1].., shape dims + dims) instead of a lattice model."""
+        import torch
+
+        self = cls.__new__(cls)
+        d = T0.dim() // 2
+        dims = list(T0.shape[:d])
+        self.model = None
+        self.opts = hotrg_opts(FORMS[precision], max_steps, chunk, 0)
+        self.d = d
+        nbytes = hotrg_tensor_workspace_bytes(d, dims, chi, self.opts)
+        if nbytes == 0:
+            raise HotrgError(HOTRG_E_ARG, "invalid tensor dims, chi or options")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream()
+        T0c = T0.contiguous().to(dtype=torch.float64)
+        self.handle = None
+        self.handle = hotrg_init_tensor(d, dims, T0c.data_ptr(), chi, self.opts, aligned, nbytes,
+                                        self.stream.cuda_stream)
+        self._t0 = T0c          # kept alive until the stream has read it
+        self.steps = 0
+        return self
 
     def step(self, axis: int | None = None) -> None:
         if axis is None:

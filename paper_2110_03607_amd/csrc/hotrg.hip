@@ -5,12 +5,13 @@
 //   1. Gram matrices A^(j), A'^(j) in three steps (Section 3.2): permute T so that the
 //      (side leg, c') or (side leg, c) pair is the row index, FP64 MFMA GEMM X X^T with
 //      split-K and a fixed-order reduction, then the (rho, eta) contraction.
-//   2. FP64 Jacobi eigendecomposition of A and A' (Section 4.2.5).
+//   2. FP64 eigendecomposition of A and A' (Householder tridiagonalisation, Sturm bisection,
+//      inverse iteration; Section 4.2.5).
 //   3. Judgement values, choice, truncation (Sections 2, 4.2.6-4.2.7).
-//   4. For each chunk of new-tensor columns (the paper's loop over n'_1, Section 4.2.8):
+//   4. For each chunk of new-tensor columns (the paper's loop over n'_1, Section 4.2.9):
 //      prime chain -> B operand, bottleneck GEMM on MFMA in the precision form,
 //      non-prime chain + renaming into T^next.
-//   5. Trace, Gu-Wen ratio, lnZ/V, normalisation (Section 4.1.1, 4.2.12-4.2.14).
+//   5. Trace, Gu-Wen ratio, lnZ/V, normalisation (Sections 4.1.1, 4.2.11, 4.2.15-4.2.17).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -165,14 +166,17 @@ void need_max(Need& a, const Need& b) {
   a.comb = std::max(a.comb, b.comb);
 }
 
-// All bond dimensions a run can reach: q, then min(x^2, chi) repeatedly.
-std::vector<int> reachable_dims(int q, int chi) {
-  std::vector<int> v{q};
-  int x = q;
-  while (x < chi) {
-    x = std::min(x * x, chi);
-    v.push_back(x);
-    if (x == 1) break;
+// All bond dimensions a run can reach from the starting dimensions: each of them, then
+// min(x^2, chi) repeatedly.
+std::vector<int> reachable_dims(const std::vector<int>& starts, int chi) {
+  std::vector<int> v;
+  for (int x : starts) {
+    for (;;) {
+      if (std::find(v.begin(), v.end(), x) == v.end()) v.push_back(x);
+      const int nx = std::min(x * x, chi);
+      if (nx == x || x >= chi) break;
+      x = nx;
+    }
   }
   return v;
 }
@@ -188,9 +192,9 @@ struct Plan {
 };
 
 // Maximum needs over every bond-dimension combination a run can reach.
-Need plan_need(int d, int q, int chi, int form, int user_chunk, bool grad) {
+Need plan_need(int d, const std::vector<int>& starts, int chi, int form, int user_chunk, bool grad) {
   Need nd{};
-  const std::vector<int> vals = reachable_dims(q, chi);
+  const std::vector<int> vals = reachable_dims(starts, chi);
   LocalDims ld;
   ld.d = d;
   const int nv = (int)vals.size();
@@ -253,9 +257,10 @@ void place_scratch(Plan& P, size_t& o, const Need& nd, bool grad) {
   }
 }
 
-Plan make_plan(int d, int q, int chi, int form, int user_chunk, int max_steps, bool grad = false) {
+Plan make_plan(int d, const std::vector<int>& starts, int chi, int form, int user_chunk, int max_steps,
+               bool grad = false) {
   Plan P{};
-  const Need nd = plan_need(d, q, chi, form, user_chunk, grad);
+  const Need nd = plan_need(d, starts, chi, form, user_chunk, grad);
   P.need = nd;
   P.max_steps = max_steps;
   P.grad = grad;
@@ -266,8 +271,9 @@ Plan make_plan(int d, int q, int chi, int form, int user_chunk, int max_steps, b
   return P;
 }
 
-// Noise floor of the Gram spectrum relative to its largest eigenvalue in each form:
-// 16 unit roundoffs of the form (0 for FP64: the exact multiplet rule of the oracle).
+// Relative difference below which two Gram eigenvalues count as one multiplet in each form,
+// and floor (relative to the largest) below which eigenvalues are not examined: 16 unit
+// roundoffs of the form (0 for FP64: the exact multiplet rule of the oracle).
 double multiplet_tau(int form) {
   switch (form) {
     case HOTRG_FP64: return 0.0;
@@ -287,6 +293,11 @@ unsigned grid_for(long n, int block = 256) {
 // Grid of the kernels that end in one atomic per workgroup on a single device scalar
 // (max|T|): a grid-stride loop over at most 1024 workgroups keeps those atomics few.
 unsigned grid_reduce(long n) { return std::min(grid_for(n), 1024u); }
+
+// Clears n ints (one workgroup; used instead of a memset so that recorded streams hold kernels only).
+__global__ void k_zero_int(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
 
 // Multi-workgroup tridiagonalisation of the large matrices of an eigensolver batch (one
 // launch per reflector); k_eigh_tri then finishes every matrix.
@@ -862,6 +873,7 @@ int collect_eig(hotrg_handle* h, const LocalDims& ld, EigDesc* out) {
       e.V = h->at<double>(h->plan.off_Vo) + slot * am;
       e.scratch = h->at<double>(h->plan.off_Vw) + slot * 2 * am;
       e.tail = e.w + n;   // the w slot holds chi^2 + 8 values
+      e.fail = &h->st()->eig_fail;
       out[count++] = e;
     }
   }
@@ -1115,7 +1127,7 @@ size_t hotrg_workspace_bytes(const hotrg_model* model, int chi, const hotrg_opts
   if (!opts || check_model(model, chi) != HOTRG_OK || !form_valid(opts->precision) || opts->max_steps < 1)
     return 0;
   if (opts->record_grad && opts->precision != HOTRG_FP64 && opts->precision != HOTRG_FP32) return 0;
-  return make_plan(model->d, model->q, chi, opts->precision, opts->chunk, opts->max_steps, opts->record_grad != 0)
+  return make_plan(model->d, {model->q}, chi, opts->precision, opts->chunk, opts->max_steps, opts->record_grad != 0)
       .total;
 }
 
@@ -1179,11 +1191,69 @@ int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts*
   int rc = check_init_args(model, beta, chi, opts);
   if (rc) return rc;
   if (!workspace) return fail(nullptr, HOTRG_E_ARG, "workspace is NULL");
-  Plan P = make_plan(model->d, model->q, chi, opts->precision, opts->chunk, opts->max_steps, opts->record_grad != 0);
+  Plan P = make_plan(model->d, {model->q}, chi, opts->precision, opts->chunk, opts->max_steps,
+                     opts->record_grad != 0);
   if (ws_bytes < P.total) return fail(nullptr, HOTRG_E_OOM, "workspace too small");
   if (((uintptr_t)workspace) % ALIGN) return fail(nullptr, HOTRG_E_ARG, "workspace must be 256-byte aligned");
   hotrg_handle* h = new_handle(model, beta, chi, opts, workspace, ws_bytes, stream, P);
   if (!h) return HOTRG_E_DEVICE;
+  *out = h;
+  return HOTRG_OK;
+}
+
+static int check_tensor_args(int d, const int* dims, int chi, const hotrg_opts* opts) {
+  if ((d != 2 && d != 3) || !dims || !opts) return fail(nullptr, HOTRG_E_ARG, "invalid d, dims or opts");
+  const int maxchi = d == 3 ? MAX_CHI_3D : MAX_CHI_2D;
+  if (chi < 1 || chi > maxchi) return fail(nullptr, HOTRG_E_ARG, "chi out of range");
+  for (int i = 0; i < d; ++i)
+    if (dims[i] < 1 || dims[i] > maxchi) return fail(nullptr, HOTRG_E_ARG, "tensor dimension out of range");
+  if (!form_valid(opts->precision) || opts->max_steps < 1 || opts->chunk < 0 || opts->record_grad != 0)
+    return fail(nullptr, HOTRG_E_ARG, "invalid options (record_grad must be 0 for a supplied tensor)");
+  return HOTRG_OK;
+}
+
+size_t hotrg_tensor_workspace_bytes(int d, const int* dims, int chi, const hotrg_opts* opts) {
+  if (check_tensor_args(d, dims, chi, opts) != HOTRG_OK) return 0;
+  return make_plan(d, std::vector<int>(dims, dims + d), chi, opts->precision, opts->chunk, opts->max_steps).total;
+}
+
+int hotrg_init_tensor(int d, const int* dims, const double* T0_dev, int chi, const hotrg_opts* opts,
+                      void* workspace, size_t ws_bytes, void* stream, hotrg_handle** out) {
+  if (!out) return fail(nullptr, HOTRG_E_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = check_tensor_args(d, dims, chi, opts);
+  if (rc) return rc;
+  if (!T0_dev || !workspace) return fail(nullptr, HOTRG_E_ARG, "T0 or workspace is NULL");
+  const Plan P = make_plan(d, std::vector<int>(dims, dims + d), chi, opts->precision, opts->chunk, opts->max_steps);
+  if (ws_bytes < P.total) return fail(nullptr, HOTRG_E_OOM, "workspace too small");
+  if (((uintptr_t)workspace) % ALIGN) return fail(nullptr, HOTRG_E_ARG, "workspace must be 256-byte aligned");
+  hotrg_handle* h = new hotrg_handle();
+  h->model = hotrg_model{-1, d, 0, 0.0, 0.0};
+  h->opts = *opts;
+  h->chi = chi;
+  h->form = opts->precision;
+  h->ws = (char*)workspace;
+  h->ws_bytes = ws_bytes;
+  h->s = (hipStream_t)stream;
+  h->plan = P;
+  h->ld.d = d;
+  long H = 1;
+  for (int i = 0; i < d; ++i) { h->ld.chi[i] = dims[i]; h->axes[i] = i; H *= dims[i]; }
+  // state and step records cleared by a kernel (no memset node if a caller records the stream)
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(256), 0, h->s, (int*)(h->ws + P.off_state),
+                     (int)((P.off_T - P.off_state) / sizeof(int)));
+  hipLaunchKernelGGL(k_init_user_trace, dim3(1), dim3(256), 0, h->s, T0_dev, (int)H, h->st());
+  if (h->form == HOTRG_FP64)
+    hipLaunchKernelGGL((k_init_user_scale<double>), dim3(grid_reduce(H * H)), dim3(256), 0, h->s, T0_dev,
+                       h->at<double>(P.off_T), H * H, h->st());
+  else
+    hipLaunchKernelGGL((k_init_user_scale<float>), dim3(grid_reduce(H * H)), dim3(256), 0, h->s, T0_dev,
+                       h->at<float>(P.off_T), H * H, h->st());
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    delete h;
+    return fail(nullptr, HOTRG_E_DEVICE, std::string("device error in hotrg_init_tensor: ") + hipGetErrorString(e));
+  }
   *out = h;
   return HOTRG_OK;
 }
@@ -1207,7 +1277,7 @@ int hotrg_step(hotrg_handle* h, int axis) {
     eb.count = ne;
     for (int i = 0; i < ne; ++i) {
       eb.n[i] = eig[i].n; eb.kvec[i] = eig[i].kvec; eb.A[i] = eig[i].A; eb.w[i] = eig[i].w;
-      eb.V[i] = eig[i].V; eb.scratch[i] = eig[i].scratch; eb.tail[i] = eig[i].tail;
+      eb.V[i] = eig[i].V; eb.scratch[i] = eig[i].scratch; eb.tail[i] = eig[i].tail; eb.fail[i] = eig[i].fail;
     }
     enqueue_tri_steps(eb, h->s);
     hipLaunchKernelGGL(k_eigh_tri, dim3(ne), dim3(EIG_THREADS), 0, h->s, eb);
@@ -1483,8 +1553,9 @@ int hotrg_debug_gram(int d, const int* dims, int dir, int side, const double* T_
 
 size_t hotrg_debug_eigh_workspace_bytes(int n, int batch) {
   if (n < 1 || n > EIG_MAXN || batch < 1 || batch > 4) return 0;
-  return (size_t)batch * 2 * n * n * 8;
+  return (size_t)batch * 2 * n * n * 8 + ALIGN;   // reflectors and vectors, then the failure flag
 }
+
 
 int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_dev, void* workspace,
                      size_t ws_bytes, void* stream) {
@@ -1492,6 +1563,8 @@ int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_d
     return fail(nullptr, HOTRG_E_ARG, "invalid argument");
   if (ws_bytes < hotrg_debug_eigh_workspace_bytes(n, batch)) return fail(nullptr, HOTRG_E_OOM, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
+  int* flag = (int*)((char*)workspace + (size_t)batch * 2 * n * n * 8);
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, flag, 1);
   EigBatch eb{};
   eb.count = batch;
   for (int b = 0; b < batch; ++b) {
@@ -1501,13 +1574,18 @@ int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_d
     eb.w[b] = w_dev + (size_t)b * n;
     eb.V[b] = V_dev + (size_t)b * n * n;
     eb.scratch[b] = (double*)workspace + (size_t)b * 2 * n * n;
+    eb.fail[b] = flag;
   }
   enqueue_tri_steps(eb, s);
   hipLaunchKernelGGL(k_eigh_tri, dim3(batch), dim3(EIG_THREADS), 0, s, eb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
-  e = hipStreamSynchronize(s);
+  int failed = 0;
+  e = hipMemcpyAsync(&failed, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
+  if (failed) return fail(nullptr, HOTRG_E_NUMERIC, "eigensolver failure (non-finite input, no convergence or a residual "
+                                                    "above the bound)");
   return HOTRG_OK;
 }
 
@@ -1543,7 +1621,7 @@ static int batch_layout(const hotrg_instance* inst, int n, const hotrg_opts* o, 
   for (int i = 0; i < n; ++i) {
     const int rc = check_init_args(&inst[i].model, inst[i].beta, inst[i].chi, o);
     if (rc) return rc;
-    needs[i] = plan_need(inst[i].model.d, inst[i].model.q, inst[i].chi, o->precision, o->chunk, false);
+    needs[i] = plan_need(inst[i].model.d, {inst[i].model.q}, inst[i].chi, o->precision, o->chunk, false);
     need_max(shared, needs[i]);
   }
   size_t off = 0;
@@ -1612,7 +1690,7 @@ static bool desc_equal(const std::vector<EigDesc>& a, const std::vector<EigDesc>
   if (a.size() != c.size()) return false;
   for (size_t i = 0; i < a.size(); ++i)
     if (a[i].n != c[i].n || a[i].kvec != c[i].kvec || a[i].A != c[i].A || a[i].w != c[i].w || a[i].V != c[i].V ||
-        a[i].scratch != c[i].scratch || a[i].tail != c[i].tail)
+        a[i].scratch != c[i].scratch || a[i].tail != c[i].tail || a[i].fail != c[i].fail)
       return false;
   return true;
 }

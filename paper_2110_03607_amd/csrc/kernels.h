@@ -760,6 +760,7 @@ struct EigBatch {
   double* V[4];
   double* scratch[4];
   double* tail[4];   // may be null: where the sum of the eigenvalues not resolved one by one goes
+  int* fail[4];      // set to 1 when the decomposition failed (see eigh_tri_body); never cleared here
 };
 
 // zs -= sum_{j0 <= j < j1} (Z_j . zs) Z_j: all coefficients first (a wave per vector,
@@ -793,6 +794,7 @@ struct EigDesc {
   double* V;
   double* scratch;
   double* tail;   // may be null
+  int* fail;      // set to 1 on failure
 };
 
 // LU with partial pivoting of the tridiagonal T - lam I (diagonal d, subdiagonal e), one
@@ -861,9 +863,13 @@ __device__ inline void lu_solve(double* z, int n, const double* ri, const double
 
 // tridiag_done: the tridiagonal form was built by k_tri_step (multi-workgroup, large n):
 // reflectors in R, diagonal and subdiagonal at Z[0, n) and Z[n, 2n).
+// *fail is set to 1 (and never cleared) when the tridiagonal matrix has a non-finite entry, when
+// an eigenvalue interval is still open after the bisection's iteration cap, or when a computed
+// eigenpair has a residual ||T z - lambda z||_2 above EIG_RES_TOL |T| (|z| = 1).
+constexpr double EIG_RES_TOL = 1e-9;
 __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ A, double* __restrict__ w,
                               double* __restrict__ V, double* __restrict__ R, const bool tridiag_done,
-                              double* __restrict__ tail_out) {
+                              double* __restrict__ tail_out, int* __restrict__ fail) {
   __shared__ double d[EIG_MAXN], e[EIG_MAXN], vv[EIG_MAXN], qv[EIG_MAXN];
   __shared__ double red[EIG_THREADS / 64];
   double* Z = R + (long)n * n;                          // reflector k at R[k n ..]; tridiagonal eigenvector i at Z[i n ..)
@@ -936,6 +942,12 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
     __syncthreads();
   }
 
+  {
+    int bad = 0;
+    for (int i = tid; i < n; i += nt) bad |= !isfinite(d[i]) || !isfinite(e[i]);
+    if (__syncthreads_or(bad) && tid == 0) *fail = 1;
+  }
+
   // ---- 2. eigenvalues by bisection (descending) -------------------------------
   double tnorm = 0.0, lo = 0.0, hi = 0.0;
   {
@@ -1005,6 +1017,7 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
         b = nb;
       }
     }
+    if (act && jl == 0 && !done) *fail = 1;   // interval still open at the iteration cap
     if (act && jl == 0) w[idx] = 0.5 * (a + b);
   }
   __syncthreads();
@@ -1114,6 +1127,21 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
     __syncthreads();
   }
   __syncthreads();
+  // residual of every computed eigenpair of the tridiagonal matrix (a wave per vector); the
+  // negated comparison also flags NaN
+  for (int iv = wv; iv < kvec; iv += nw) {
+    const double* z = Z + (long)iv * n;
+    const double lam = w[iv];
+    double rr = 0.0;
+    for (int i = lane; i < n; i += 64) {
+      double r = (d[i] - lam) * z[i];
+      if (i > 0) r += e[i - 1] * z[i - 1];
+      if (i + 1 < n) r += e[i] * z[i + 1];
+      rr += r * r;
+    }
+    for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
+    if (lane == 0 && !(sqrt(rr) <= EIG_RES_TOL * tnorm)) *fail = 1;
+  }
 
   // ---- 4. back-transformation: V[:, iv] = H_0 H_1 ... H_{n-3} z_iv -------------
   constexpr int PER = EIG_MAXN / 64;
@@ -1187,14 +1215,15 @@ constexpr int TRI_MULTI_N = 128;
 // Up to four matrices passed by value (one coarse-graining step of one instance).
 __global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
   const int b = blockIdx.x;
-  eigh_tri_body(eb.n[b], eb.kvec[b], eb.A[b], eb.w[b], eb.V[b], eb.scratch[b], eb.n[b] >= TRI_MULTI_N, eb.tail[b]);
+  eigh_tri_body(eb.n[b], eb.kvec[b], eb.A[b], eb.w[b], eb.V[b], eb.scratch[b], eb.n[b] >= TRI_MULTI_N, eb.tail[b],
+                eb.fail[b]);
 }
 
 // Any number of matrices from a descriptor table in device memory (a step of a batch of
 // instances: one launch for all their decompositions).
 __global__ __launch_bounds__(EIG_THREADS) void k_eigh_list(const EigDesc* __restrict__ list) {
   const EigDesc ds = list[blockIdx.x];
-  eigh_tri_body(ds.n, ds.kvec, ds.A, ds.w, ds.V, ds.scratch, ds.n >= TRI_MULTI_N, ds.tail);
+  eigh_tri_body(ds.n, ds.kvec, ds.A, ds.w, ds.V, ds.scratch, ds.n >= TRI_MULTI_N, ds.tail, ds.fail);
 }
 
 // ---------------------------------------------------------------------------
@@ -1309,11 +1338,13 @@ __global__ __launch_bounds__(256) void k_tri_step_list(const EigDesc* __restrict
 // Judgement values, choice and truncation (Sections 2, 4.2.6-4.2.7):
 //   epsilon = sum_{l >= chi_new} max(lambda_l, 0),  U if epsilon < epsilon' else U'.
 // When the cut splits a multiplet of equal eigenvalues (difference at most
-// max(MULT_RTOL lambda_{k-1}, tau lambda_0), eigenvalue at least max(MULT_ATOL, tau) of the
-// largest) the whole multiplet is dropped by zeroing its columns: "the first chi columns"
-// are not unique there.  tau = 0 in the FP64 form (the oracle's rule); in the reduced-
-// precision forms tau is the form's noise floor relative to lambda_0, so that a multiplet
-// that is exact in the method is still recognised after rounding.
+// max(MULT_RTOL, tau) lambda_{k-1}, eigenvalue at least max(MULT_ATOL, tau) of the largest)
+// the whole multiplet is dropped by zeroing its columns: "the first chi columns" are not
+// unique there.  tau = 0 in the FP64 form (the oracle's rule); in the reduced-precision forms
+// tau is a multiple of the form's unit roundoff, so that a multiplet that is exact in the
+// method is still recognised after rounding.  The pair's difference is measured against the
+// pair itself, as in the FP64 rule: against lambda_0 a small pair a few per cent apart (a cut
+// deep in the spectrum) would be taken for a multiplet and dropped.
 // w: [2][n] (side 0 = A, side 1 = A'), V: [2][n][n].  identity != 0: untruncated, the
 // isometry is the identity (any orthonormal basis is exact when chi_new = n).
 // ---------------------------------------------------------------------------
@@ -1357,7 +1388,7 @@ __global__ void k_choose(const double* __restrict__ w0, const double* __restrict
     const double floor_ = fmax(MULT_ATOL, tau) * lam[0];
     if (k < n)
       while (k > 1 && lam[k - 1] >= floor_ &&
-             lam[k - 1] - lam[k] <= fmax(MULT_RTOL * lam[k - 1], tau * lam[0])) --k;
+             lam[k - 1] - lam[k] <= fmax(MULT_RTOL, tau) * lam[k - 1]) --k;
     prime_s = side;
     kept_s = k;
   }
@@ -1384,7 +1415,7 @@ __global__ void k_choose(const double* __restrict__ w0, const double* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Prime chain (Section 4.2.8, eqs. TU1..TUNCD) written straight into the B operand
+// Prime chain (Section 4.2.9, eqs. TU1..TUNCD) written straight into the B operand
 // of the bottleneck GEMM (B^T rows n, K-contiguous):
 //   3D:  B[(g - g0) b + nc][rho b + (nh1' chi2 + nh2')] =
 //          sum_{nc1', nc2'} U1[nh1' + chi1 nc1', n1'] U2[nh2' + chi2 nc2', n2'] T[rho, nc][c', nc1', nc2']
@@ -2196,6 +2227,56 @@ __global__ void k_rec_init(StepRec* rec_base, const DevState* st, int axis, int 
     rec->dims_before[1] = c1;
     rec->dims_before[2] = d == 3 ? c2 : 0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Initial tensor supplied by the caller (FP64, storage order, H x H): t0 = Tr T0, lnZ/V at
+// p = 0 = ln t0 and f^(0) = 1/t0 (Section 3.1.3, eq. Trace_LocalTensor).  A non-positive or
+// non-finite t0 is a numeric failure (sticky; f = 1 then).  One workgroup; k_init_user_scale
+// then writes T = f T0 into the master tensor.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_init_user_trace(const double* __restrict__ T0, int H, DevState* st) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int h = tid; h < H; h += 256) s += T0[(long)h * H + h];
+  red[tid] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double t = red[0];
+    const bool ok = t > 0.0 && isfinite(t);
+    st->lnz0 = ok ? log(t) : 0.0;
+    st->lnz = st->lnz0;
+    st->dlnz = 0.0;
+    st->f = ok ? 1.0 / t : 1.0;
+    st->maxabs = 0.0;
+    st->p = 0;
+    st->err = ok ? 0 : 3;   // HOTRG_E_NUMERIC
+    st->eig_fail = 0;
+  }
+}
+
+template <class MT>
+__global__ void k_init_user_scale(const double* __restrict__ T0, MT* __restrict__ T, long n, DevState* st) {
+  __shared__ double red[256];
+  const double f = st->f;
+  double mx = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const MT v = (MT)(T0[i] * f);
+    T[i] = v;
+    mx = fmax(mx, fabs((double)v));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax((unsigned long long*)&st->maxabs, __double_as_longlong(red[0]));
 }
 
 // ---------------------------------------------------------------------------

@@ -31,3 +31,9 @@ CONFIG4_3D = dict(kind="ising", d=3, q=2, temps=tuple(np.linspace(4.0, 5.0, 64))
 CONFIG4_2D = dict(kind="ising", d=2, q=2, betas=tuple(np.linspace(0.3, 0.6, 48)),
                   chis=(16, 24, 32), steps=20)
 CONFIG5 = dict(kind="potts", d=3, q=3, betas=(0.50, 0.55, 0.60), chi=16, steps=20)
+
+
+def random_positive_tensor(shape, seed=0, spread=0.5):
+    """Dense FP64 tensor with i.i.d. entries exp(spread * N(0, 1)) (all positive, so every
+    trace of a network of copies is positive)."""
+    return np.exp(random_tensor(shape, seed=seed, scale=spread))

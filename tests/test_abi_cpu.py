@@ -125,3 +125,24 @@ def test_batch_workspace_and_argument_errors():
     assert P.lib().hotrg_batch_step(None) == P.HOTRG_E_ARG
     assert not P.lib().hotrg_batch_instance(None, 0)
     P.lib().hotrg_batch_destroy(None)
+
+
+def test_supplied_tensor_argument_validation():
+    o = P.hotrg_opts(P.HOTRG_FP64, 8, 0, 0)
+    assert P.hotrg_tensor_workspace_bytes(3, [3, 4, 2], 6, o) > 0
+    assert P.hotrg_tensor_workspace_bytes(2, [32, 32], 32, o) > 0
+    assert P.hotrg_tensor_workspace_bytes(3, [17, 4, 2], 6, o) == 0       # above the 3D maximum
+    assert P.hotrg_tensor_workspace_bytes(3, [0, 4, 2], 6, o) == 0
+    assert P.hotrg_tensor_workspace_bytes(4, [2, 2, 2, 2], 6, o) == 0
+    assert P.hotrg_tensor_workspace_bytes(3, [3, 4, 2], 6, P.hotrg_opts(P.HOTRG_FP64, 8, 0, 1)) == 0   # no beta
+    # the plan covers the dims the run reaches from (3, 4, 2): it is at least that of a model run
+    # whose dims pass through the same values
+    assert P.hotrg_tensor_workspace_bytes(3, [16, 16, 16], 16, o) >= \
+        P.hotrg_workspace_bytes(P.hotrg_model(P.HOTRG_ISING, 3, 2, 1.0, 0.0), 16, o)
+    with pytest.raises(P.HotrgError) as e:
+        P.hotrg_init_tensor(3, [3, 4, 2], 0, 6, o, 0, 0, 0)
+    assert e.value.code == P.HOTRG_E_ARG
+
+
+def test_eigh_workspace_holds_the_failure_flag():
+    assert P.hotrg_debug_eigh_workspace_bytes(256, 4) >= 4 * 2 * 256 * 256 * 8 + 4

@@ -12,6 +12,7 @@ pytestmark = pytest.mark.gpu
 
 gu = pytest.importorskip("tests.gpu_util")
 P = gu.P
+from tests import parity as PT  # noqa: E402
 from tests import seeded_inputs as SI  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -78,19 +79,60 @@ def config4_instances():
     return inst
 
 
-@pytest.mark.parametrize("precision,bound", [("split_fp16", 1e-5), ("fp64", 1e-10)])
-def test_config4_sweep_against_oracle(precision, bound):
-    """64 x 3D Ising chi = 12 (T = linspace(4, 5, 64)) and 48 x 2D Ising (beta = linspace(0.3,
-    0.6, 48), chi round-robin 16, 24, 32), 20 steps, as one batch; sampled instances against
-    the oracle after every step.  Split FP16: 1e-5 over the sweep.  In the ordered phase
-    (T = 4.0 in 3D, beta near 0.6 in 2D) even/odd pairs of Gram eigenvalues come within the
-    form's noise floor of each other at some cuts; the split form then drops the pair where
-    FP64 keeps it (or the reverse), which moves lnZ/V by a few 1e-6 at that step (printed:
-    the steps where the kept counts differ)."""
+# lnZ/V bounds for the sweep: FP64 1e-10 at every step.  Split FP16: 1e-6 (the MFMA bar) up to
+# the first step where the instance keeps a different number of columns than the oracle, 1e-5
+# from there on.  In the ordered phase (3D T near 4.0, 2D beta near 0.6) even/odd pairs of
+# Gram eigenvalues come within the form's noise floor of each other at some cuts; the split
+# form then drops a pair that FP64 keeps (or the reverse), which moves lnZ/V by a few 1e-6.
+# The instances and steps concerned are printed (and listed in the design doc).
+SWEEP_BOUND = {"fp64": (1e-10, 1e-10), "split_fp16": (1e-6, 1e-5)}
+
+
+def load_config4():
     path = os.path.join(GOLDEN, "config4.json")
     if not os.path.exists(path):
         pytest.skip("config4 fixture not generated")
-    fx = json.load(open(path))
+    return json.load(open(path))
+
+
+def check_sweep(fx, lnz_of, kept_of, precision, label):
+    """lnz_of(idx, p), kept_of(idx, p) -> the batch's values for instance idx after step p."""
+    steps = SI.CONFIG4_3D["steps"]
+    tight, loose = SWEEP_BOUND[precision]
+    worst, diverged = 0.0, []
+    for run in fx["runs"]:
+        idx = run["index"] if run["d"] == 3 else 64 + run["index"]
+        ref = [st["lnz_per_site"] for st in run["steps"]]
+        per = [abs(lnz_of(idx, p) - ref[p - 1]) / abs(ref[p - 1]) for p in range(1, steps + 1)]
+        kdiff, krounding = [], []
+        for p in range(1, steps + 1):
+            for j in range(1, run["d"]):
+                dd = run["steps"][p - 1]["dirs"][str(j)]
+                kg = kept_of(idx, p)[j - 1]
+                if kg != dd["kept"]:
+                    (krounding if PT.rounding_decided_cut(dd, kg) else kdiff).append(p)
+        first = min(kdiff + krounding) if kdiff + krounding else steps + 1
+        if kdiff or krounding:
+            diverged.append((run["d"], run["chi"], round(run["beta"], 6), first))
+        print(f"{label} d={run['d']} chi={run['chi']} beta={run['beta']:.6f}: max rel err {max(per):.2e}"
+              + (f"; kept differs from step {first} ({kdiff}; at rounding-decided cuts {krounding})"
+                 if kdiff or krounding else ""))
+        if precision == "fp64":
+            assert not kdiff, (idx, kdiff)
+        for p in range(1, steps + 1):
+            assert per[p - 1] < (tight if p < first else loose), (idx, p, per[p - 1])
+        worst = max(worst, max(per))
+    print(f"{label}: {len(fx['runs'])} instances compared, worst {worst:.2e}; kept counts diverge "
+          f"(d, chi, beta, first step): {diverged}")
+
+
+@pytest.mark.parametrize("precision", ["split_fp16", "fp64"])
+def test_config4_sweep_against_oracle(precision):
+    """64 x 3D Ising chi = 12 (T = linspace(4, 5, 64)) and 48 x 2D Ising (beta = linspace(0.3,
+    0.6, 48), chi round-robin 16, 24, 32), 20 steps, as one batch, synchronised after every
+    step; every instance of the oracle fixture (all 2D ones, every 4th 3D temperature and the
+    last) against the oracle after every step."""
+    fx = load_config4()
     inst = config4_instances()
     steps = SI.CONFIG4_3D["steps"]
     bt = P.HOTRGBatch(inst, precision=precision, max_steps=steps)
@@ -101,21 +143,40 @@ def test_config4_sweep_against_oracle(precision, bound):
         if (p + 1) % 5 == 0:
             print(f"  [config4 {precision}: {p + 1} steps]", flush=True)
     graphs, eager = bt.graph_stats()
-    worst = 0.0
-    for run in fx["runs"]:
-        idx = run["index"] if run["d"] == 3 else 64 + run["index"]
-        ref = [s["lnz_per_site"] for s in run["steps"]]
-        per = [abs(lnz[p][idx] - ref[p]) / abs(ref[p]) for p in range(steps)]
-        kept = [[bt.info(idx, p + 1).kept[j] for j in range(run["d"] - 1)] for p in range(steps)]
-        kref = [[s["dirs"][str(j)]["kept"] for j in range(1, run["d"])] for s in run["steps"]]
-        print(f"config4 {precision} d={run['d']} chi={run['chi']} beta={run['beta']:.6f}: max rel err {max(per):.2e}"
-              f"\n  per step: " + " ".join(f"{e:.1e}" for e in per)
-              + f"\n  kept differs at steps: {[p + 1 for p in range(steps) if kept[p] != kref[p]]}")
-        worst = max(worst, max(per))
+    check_sweep(fx, lambda i, p: lnz[p - 1][i], lambda i, p: list(bt.info(i, p).kept), precision,
+                f"config4 {precision}")
     bt.close()
-    print(f"config4 {precision}: {graphs} graph launches, {eager} eager steps; worst {worst:.2e}")
-    assert all(np.isfinite(v) for row in lnz for v in row)
-    assert worst < bound
+    print(f"config4 {precision}: {graphs} graph launches, {eager} eager steps")
+    assert graphs >= 10
+
+
+@pytest.mark.parametrize("precision", ["split_fp16", "fp64"])
+def test_config4_back_to_back_graph_replays(precision):
+    """The sweep as bench.py times it: run(20) with no synchronisation between the steps (the
+    saturated steps replayed from the recorded graphs back to back); afterwards every
+    instance's lnZ/V after every step is read from its step records and compared with the
+    oracle fixture as above."""
+    fx = load_config4()
+    inst = config4_instances()
+    steps = SI.CONFIG4_3D["steps"]
+    bt = P.HOTRGBatch(inst, precision=precision, max_steps=steps, tune=True)
+    bt.run(steps)
+    bt.synchronize()
+    graphs, eager = bt.graph_stats()
+    recs = {}
+
+    def rec(i, p):
+        if (i, p) not in recs:
+            recs[(i, p)] = bt.info(i, p)
+        return recs[(i, p)]
+
+    check_sweep(fx, lambda i, p: rec(i, p).lnz_per_site, lambda i, p: list(rec(i, p).kept), precision,
+                f"config4 back to back {precision}")
+    final = bt.log_z()
+    assert all(final[i] == rec(i, steps).lnz_per_site for i in range(len(inst)))
+    bt.close()
+    print(f"config4 back to back {precision}: {graphs} graph launches, {eager} eager steps")
+    assert graphs >= 10
 
 
 @pytest.mark.parametrize("precision", ["fp64", "split_fp16"])

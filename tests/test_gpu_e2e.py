@@ -12,6 +12,7 @@ import pytest
 
 from oracle import exact as E
 from oracle import hotrg as H
+from tests import parity as PT
 
 pytestmark = pytest.mark.gpu
 
@@ -68,19 +69,59 @@ def test_initial_lnz_closed_form():
 # Physics configurations against the oracle fixtures
 # ---------------------------------------------------------------------------
 
-def _compare_run(run_fix, lnz_gpu, rtol):
-    errs = []
-    for rec, g in zip(run_fix["steps"], lnz_gpu):
-        errs.append(abs(g - rec["lnz_per_site"]) / abs(rec["lnz_per_site"]))
-    return max(errs), errs[-1]
+def _rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+# The trace t_p and the Gu-Wen ratio X after every step against the oracle fixture.
+# FP64: 1e-10 (the bound of lnZ/V) at every step up to the first cut whose effective gap
+# (lambda_{kept-1} - lambda_kept) / lambda_0 is below 1e-5; after it the kept subspace, and with
+# it t_p and X, moves by (rounding of A) / gap in any two FP64 implementations (in config 2 at
+# T = 4.0 the gaps fall to 1e-7 and t_p parts by up to 5e-4 while lnZ/V, where t_p enters with
+# weight 1/2^p, stays within 1e-11).  Reduced forms: t_p and X carry the form's rounding
+# amplified by the flow (near T_c a perturbation of T grows by about 2^(y_t / 3) = 1.44 per step,
+# y_t the thermal exponent of the 3D Ising class), up to 1e-4 (FP32, split FP16) and 0.1 (split
+# BF16) at late steps; there only a gross-error bound is asserted and the values are printed.
+TRACE_TIGHT = {"fp64": 1e-10}
+TRACE_GROSS = {"fp64": 1e-2, "fp32": 0.5, "split_fp16": 0.5, "split_bf16": 0.5}
+FP64_GAP_THRESHOLD = 1e-5
+
+
+def compare_run(r, run_fix, lnz_gpu, precision, dirs):
+    """Per-step errors of lnZ/V, t_p and X against one oracle run, and the steps where the
+    kept column counts differ.  FP64 must keep the oracle's column counts, except at a cut
+    decided by rounding (tests/parity.py).  Returns (max lnZ/V error, final lnZ/V error)."""
+    steps = len(run_fix["steps"])
+    e_lnz, e_tr, e_x, kdiff, krounding = [], [], [], [], []
+    for p in range(1, steps + 1):
+        rec, info = run_fix["steps"][p - 1], r.info(p)
+        e_lnz.append(_rel(lnz_gpu[p - 1], rec["lnz_per_site"]))
+        e_tr.append(_rel(info.trace, rec["trace"]))
+        e_x.append(_rel(info.gu_wen, rec["gu_wen"]))
+        assert info.lnz_per_site == lnz_gpu[p - 1]
+        for j in dirs:
+            dd = rec["dirs"][str(j)]
+            if info.kept[j - 1] != dd["kept"]:
+                (krounding if PT.rounding_decided_cut(dd, info.kept[j - 1]) else kdiff).append(p)
+    fmt = lambda v: " ".join(f"{e:.1e}" for e in v)   # noqa: E731
+    ncond = PT.conditioned_steps(run_fix, FP64_GAP_THRESHOLD)
+    print(f"  lnZ/V per step: {fmt(e_lnz)}\n  trace per step: {fmt(e_tr)}\n  Gu-Wen X per step: {fmt(e_x)}"
+          f"\n  kept differs at steps: {kdiff} (at rounding-decided cuts: {krounding}); "
+          f"steps before an effective gap < {FP64_GAP_THRESHOLD:.0e}: {ncond}")
+    if precision == "fp64":
+        assert kdiff == [], f"FP64 kept counts differ from the oracle at steps {kdiff}"
+        assert max(e_tr[:ncond]) < TRACE_TIGHT["fp64"] and max(e_x[:ncond]) < TRACE_TIGHT["fp64"]
+    assert max(e_tr) < TRACE_GROSS[precision] and max(e_x) < TRACE_GROSS[precision]
+    return max(e_lnz), e_lnz[-1]
 
 
 def test_config1_fp64_2d_ising_chi8():
     fx = load("config1.json")
     for run in fx["runs"]:
-        _, lnz = run_gpu("ising", 2, run["beta"], fx["chi"], fx["steps"])
-        emax, elast = _compare_run(run, lnz, 1e-10)
-        print(f"config1 beta={run['beta']:.6f} max|df|/|f|={emax:.2e} final={elast:.2e}")
+        r, lnz = run_gpu("ising", 2, run["beta"], fx["chi"], fx["steps"])
+        print(f"config1 beta={run['beta']:.6f}")
+        emax, elast = compare_run(r, run, lnz, "fp64", dirs=(1,))
+        print(f"  max|df|/|f|={emax:.2e} final={elast:.2e}")
         assert emax < 1e-10
 
 
@@ -91,13 +132,9 @@ def test_config2_3d_ising_chi8(precision, bound):
     worst = 0.0
     for run in fx["runs"]:
         r, lnz = run_gpu("ising", 3, run["beta"], fx["chi"], fx["steps"], precision=precision)
-        emax, elast = _compare_run(run, lnz, bound)
-        per_step = [abs(g - rec["lnz_per_site"]) / abs(rec["lnz_per_site"]) for rec, g in zip(run["steps"], lnz)]
-        print(f"config2 {precision} beta={run['beta']:.6f} max rel err={emax:.2e} final={elast:.2e}")
-        print("  per step:", " ".join(f"{e:.1e}" for e in per_step))
-        kept = [[r.info(p).kept[j] for j in range(2)] for p in range(1, fx["steps"] + 1)]
-        kept_ref = [[rec["dirs"][str(j)]["kept"] for j in (1, 2)] for rec in run["steps"]]
-        print("  kept differs at steps:", [p + 1 for p in range(fx["steps"]) if kept[p] != kept_ref[p]])
+        print(f"config2 {precision} beta={run['beta']:.6f}")
+        emax, elast = compare_run(r, run, lnz, precision, dirs=(1, 2))
+        print(f"  max rel err={emax:.2e} final={elast:.2e}")
         worst = max(worst, emax)
     assert worst < bound
 
@@ -106,20 +143,14 @@ def test_config2_3d_ising_chi8(precision, bound):
                                              ("split_bf16", 1e-4)])
 def test_config3_3d_ising_chi16(precision, bound):
     """3D Ising, chi = 16, T = 4.5115, 25 steps (the benchmark workload) against the oracle
-    fixture after every step; steps 1-3 are untruncated, step 3 is the 2x2x2 torus."""
-    path = os.path.join(GOLDEN, "config3.json")
-    if not os.path.exists(path):
-        pytest.skip("config3 fixture not generated")
+    fixture after every step: lnZ/V, trace and Gu-Wen ratio, and in FP64 the kept column
+    counts; steps 1-3 are untruncated, step 3 is the 2x2x2 torus."""
     fx = load("config3.json")
     run = fx["runs"][0]
     r, lnz = run_gpu("ising", 3, run["beta"], fx["chi"], fx["steps"], precision=precision)
-    emax, elast = _compare_run(run, lnz, bound)
-    per_step = [abs(g - rec["lnz_per_site"]) / abs(rec["lnz_per_site"]) for rec, g in zip(run["steps"], lnz)]
-    print(f"config3 {precision} beta={run['beta']:.7f} max rel err={emax:.2e} final={elast:.2e}")
-    print("  per step:", " ".join(f"{e:.1e}" for e in per_step))
-    kept = [[r.info(p).kept[j] for j in range(2)] for p in range(1, fx["steps"] + 1)]
-    kept_ref = [[rec["dirs"][str(j)]["kept"] for j in (1, 2)] for rec in run["steps"]]
-    print("  kept differs at steps:", [p + 1 for p in range(fx["steps"]) if kept[p] != kept_ref[p]])
+    print(f"config3 {precision} beta={run['beta']:.7f}")
+    emax, elast = compare_run(r, run, lnz, precision, dirs=(1, 2))
+    print(f"  max rel err={emax:.2e} final={elast:.2e}")
     assert emax < bound
 
 

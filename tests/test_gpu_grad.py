@@ -127,34 +127,84 @@ def potts16(beta, precision, steps=20):
         if (p + 1) % 5 == 0:
             print(f"  [potts chi=16 {precision} beta={beta}: {p + 1} steps]", flush=True)
     kept = [tuple(r.info(p).kept[:2]) for p in range(1, steps + 1)]
+    _LNZ[(beta, precision, steps)] = [r.info(p).lnz_per_site for p in range(1, steps + 1)]
     r.close()
     return np.array(g), kept
+
+
+_LNZ = {}
+
+
+def potts16_lnz(beta, precision, steps=20):
+    potts16(beta, precision, steps)
+    return _LNZ[(beta, precision, steps)]
 
 
 def _fmt(v):
     return " ".join(f"{e:.1e}" for e in v)
 
 
-@pytest.mark.parametrize("beta", [0.50, 0.60])
+# Steps of the 20 at which the central differences must be consistent (see the test below),
+# per beta.  beta = 0.55 sits next to the first-order transition of the 3D 3-state Potts model:
+# there lnZ/V(beta) of the truncated flow bends on the scale 1e-4 from about step 11, so only
+# the first ten steps can be checked with h = 1e-4.
+FD_MIN_CHECKABLE = {0.50: 15, 0.55: 10, 0.60: 15}
+
+
+@pytest.mark.parametrize("beta", [0.50, 0.55, 0.60])
 def test_potts_chi16_fp64_gradient_vs_central_differences(beta):
     """3D 3-state Potts, chi = 16, 20 steps: the FP64 derivative against central differences
-    of the FP64 forward, at every step where the differences at h = 1e-4, 1e-5 and 1e-6 are
-    consistent with a smooth lnZ/V(beta): |fd(1e-5) - fd(1e-6)| <= 2e-9 |g| (no jump inside
-    +-1e-5) and |fd(1e-4) - fd(1e-6)| <= 1e-5 |g|.  There the derivative must match
-    fd(1e-6) to 1e-8 and fd(1e-4) to 1e-5.  Late steps where the truncated approximant jumps
-    inside +-h (a kept column traded between near-degenerate eigenvalues) are printed."""
+    of the FP64 forward, at every step where the differences at h = 1e-4, 1e-5 and 1e-6 behave
+    as those of a smooth lnZ/V(beta): the central difference of a smooth function departs from
+    the derivative as h^2, so |fd(1e-5) - fd(1e-6)| may be at most 3/100 of |fd(1e-4) - fd(1e-6)|
+    (1/100 expected; a jump of the truncated approximant inside +-1e-5 breaks this), or 2e-9 |g|
+    (rounding of the FP64 forward); and |fd(1e-4) - fd(1e-6)| <= 1e-5 |g| (no bend on the scale
+    1e-4).  There the derivative must match fd(1e-6) to 1e-8 and fd(1e-4) to 1e-5.  The steps
+    left out are printed; at least FD_MIN_CHECKABLE[beta] steps must be checkable."""
     g64 = potts16(beta, "fp64")[0]
     fd4, fd5, fd6 = fd_fp64(beta, 1e-4), fd_fp64(beta, 1e-5), fd_fp64(beta, 1e-6)
     rel = lambda x: np.abs(g64 - x) / np.abs(g64)   # noqa: E731
-    ok = (np.abs(fd5 - fd6) <= 2e-9 * np.abs(g64)) & (np.abs(fd4 - fd6) <= 1e-5 * np.abs(g64))
+    smooth = np.abs(fd5 - fd6) <= np.maximum(2e-9 * np.abs(g64), 0.03 * np.abs(fd4 - fd6))
+    ok = smooth & (np.abs(fd4 - fd6) <= 1e-5 * np.abs(g64))
     print(f"Potts chi=16 beta={beta}: d(lnZ/V)/dbeta fp64 {g64[-1]:.12f} fd(1e-6) {fd6[-1]:.12f} "
-          f"fd(1e-4) {fd4[-1]:.12f}; checkable steps {[p + 1 for p in range(len(g64)) if ok[p]]}; "
+          f"fd(1e-4) {fd4[-1]:.12f}; checkable steps {[p + 1 for p in range(len(g64)) if ok[p]]}, "
+          f"left out {[p + 1 for p in range(len(g64)) if not ok[p]]}; "
           f"max rel err there vs h=1e-6 {rel(fd6)[ok].max():.2e}, vs h=1e-4 {rel(fd4)[ok].max():.2e}"
           f"\n  per step vs h=1e-6: {_fmt(rel(fd6))}\n  per step vs h=1e-5: {_fmt(rel(fd5))}"
           f"\n  per step vs h=1e-4: {_fmt(rel(fd4))}")
-    assert ok.sum() >= 15
+    assert ok.sum() >= FD_MIN_CHECKABLE[beta]
     assert rel(fd6)[ok].max() < 1e-8
     assert rel(fd4)[ok].max() < 1e-5
+
+
+def grad_config5_fixture(beta):
+    path = os.path.join(os.path.dirname(__file__), "golden", f"grad_config5_beta{beta:.2f}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"oracle derivative fixture for beta={beta} not generated")
+    fx = json.load(open(path))
+    if fx["steps_done"] < 1:
+        pytest.skip("fixture has no steps")
+    return fx
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-5)])
+@pytest.mark.parametrize("beta", [0.50, 0.55, 0.60])
+def test_potts_chi16_gradient_matches_oracle(beta, precision, tol):
+    """3D 3-state Potts, chi = 16 (the derivative configuration): d(lnZ/V)/dbeta after every
+    step for which the oracle's forward-mode derivative is stored (the first steps; a
+    saturated step of the oracle's derivative costs about half an hour of CPU), FP64 to 1e-9
+    and FP32 to 1e-5 relative, and lnZ/V to 1e-10 (FP64) and 1e-6 (FP32)."""
+    fx = grad_config5_fixture(beta)
+    n = fx["steps_done"]
+    g, _ = potts16(beta, precision)
+    lz = potts16_lnz(beta, precision)
+    eg = [abs(g[p] - fx["dlnz"][p]) / abs(fx["dlnz"][p]) for p in range(n)]
+    el = [abs(lz[p] - fx["lnz"][p]) / abs(fx["lnz"][p]) for p in range(n)]
+    print(f"Potts chi=16 beta={beta} {precision}: {n} steps against the oracle derivative "
+          f"(commit {fx['provenance']['oracle_commit'][:8]}); d(lnZ/V)/dbeta per step {_fmt(eg)}; "
+          f"lnZ/V per step {_fmt(el)}")
+    assert max(eg) < tol
+    assert max(el) < (1e-10 if precision == "fp64" else 1e-6)
 
 
 @pytest.mark.parametrize("beta", [0.50, 0.55, 0.60])

@@ -2,14 +2,20 @@
 the FP64 oracle on the same seeded inputs (random dense T, isometries from QR).
 
 Because the isometries are inputs here, no eigenvector gauge is involved and the new
-tensors are compared element by element (normwise relative error).
+tensors are compared element by element: for every compared (n'_1, .., n'_{d-1}) column
+slice, max |got - ref| / max |ref| over the slice (tests/parity.py) must stay below the
+form's bound.  Small shapes compare every slice; the full chi = 16 shape compares 16 slices
+spread over the 256.
 """
+
+import functools
 
 import numpy as np
 import pytest
 
 from oracle import hotrg as H
 from tests import layout as LY
+from tests import parity as PT
 from tests import seeded_inputs as SI
 
 pytestmark = pytest.mark.gpu
@@ -17,19 +23,23 @@ pytestmark = pytest.mark.gpu
 gu = pytest.importorskip("tests.gpu_util")
 P = gu.P
 
-# Normwise relative tolerance of the new tensor per form ("Parity tolerances"):
-# tol = C * u_form * sqrt(K) with K = H the bottleneck contraction length, C = 16.
-U_FORM = {P.HOTRG_FP64: 2.0 ** -53, P.HOTRG_FP32: 2.0 ** -24, P.HOTRG_SPLIT_FP16: 2.0 ** -21,
-          P.HOTRG_SPLIT_BF16: 2.0 ** -16, P.HOTRG_FP16: 2.0 ** -11, P.HOTRG_BF16: 2.0 ** -8}
+# Per-slice bound of max|got - ref| / max|ref| per precision form, for the seeded N(0, 1)
+# tensors and QR isometries below.  Each bound is at most ten times the largest error
+# measured on an MI355X over all the shapes of this file (the measured maxima are listed in
+# the design doc, section 6): a change that loses a term, a plane or a scale factor fails.
+# Measured maxima (MI355X, all shapes): FP64 3.3e-15, FP32 1.6e-6, split FP16 9.4e-7, split
+# BF16 6.7e-6, FP16 4.4e-4, BF16 3.6e-3.
+SLICE_BOUND = {P.HOTRG_FP64: 3e-14, P.HOTRG_FP32: 1.5e-5, P.HOTRG_SPLIT_FP16: 9e-6,
+               P.HOTRG_SPLIT_BF16: 6e-5, P.HOTRG_FP16: 4e-3, P.HOTRG_BF16: 3e-2}
+# Gram matrices (FP64 in every form): measured max 3.3e-15.
+GRAM_BOUND = 3e-14
+FORM_NAME = {P.HOTRG_FP64: "fp64", P.HOTRG_FP32: "fp32", P.HOTRG_SPLIT_FP16: "split_fp16",
+             P.HOTRG_SPLIT_BF16: "split_bf16", P.HOTRG_FP16: "fp16", P.HOTRG_BF16: "bf16"}
 
 
-def tol(form, Hdim):
-    return 16.0 * U_FORM[form] * np.sqrt(Hdim)
-
-
-def oracle_next_storage(T_paper, Us):
+def oracle_next_storage(T_paper, Us, only=None):
     d = T_paper.ndim // 2
-    Tnew = H.new_tensor(T_paper, {j + 1: Us[j] for j in range(d - 1)})
+    Tnew = H.new_tensor(T_paper, {j + 1: Us[j] for j in range(d - 1)}, only=only)
     return LY.to_storage(H.rename(Tnew))
 
 
@@ -52,6 +62,22 @@ def _random_case(dims, kdims, seed):
     return Ts, Us
 
 
+@functools.lru_cache(maxsize=None)
+def _small_reference(dims, kdims, seed):
+    Ts, Us = _random_case(dims, kdims, seed)
+    return Ts, Us, oracle_next_storage(LY.to_paper(Ts), Us)
+
+
+def _check_all_slices(form, dims, kdims, seed):
+    Ts, Us, ref = _small_reference(dims, kdims, seed)
+    got = gu.contract(Ts, Us, list(kdims), form)
+    picks = PT.spread_picks(kdims, 10 ** 9)              # every slice
+    worst, errs = PT.worst_slice_error(got, ref, picks)
+    print(f"{FORM_NAME[form]} dims={dims} k={kdims}: {len(picks)} slices, max slice error {worst:.2e} "
+          f"(bound {SLICE_BOUND[form]:.0e})")
+    assert worst < SLICE_BOUND[form]
+
+
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
     gu.require_gpu()
@@ -59,13 +85,7 @@ def _gpu():
 
 @pytest.mark.parametrize("dims,kdims", CASES_3D + CASES_2D)
 def test_contract_fp64_matches_oracle(dims, kdims):
-    Ts, Us = _random_case(dims, kdims, seed=0)
-    ref = oracle_next_storage(LY.to_paper(Ts), Us)
-    got = gu.contract(Ts, Us, list(kdims), P.HOTRG_FP64)
-    Hd = int(np.prod(dims))
-    err = gu.relerr(got, ref)
-    print(f"fp64 dims={dims} k={kdims} relerr={err:.3e}")
-    assert err < tol(P.HOTRG_FP64, Hd)
+    _check_all_slices(P.HOTRG_FP64, dims, kdims, seed=0)
 
 
 @pytest.mark.parametrize("form", [P.HOTRG_FP32, P.HOTRG_SPLIT_FP16, P.HOTRG_SPLIT_BF16, P.HOTRG_FP16,
@@ -73,48 +93,33 @@ def test_contract_fp64_matches_oracle(dims, kdims):
 @pytest.mark.parametrize("dims,kdims", [((8, 8, 8), (8, 8)), ((3, 5, 4), (7, 6)), ((8, 8), (16,)),
                                        ((3, 12, 12), (12, 12))])
 def test_contract_forms_match_oracle(form, dims, kdims):
-    Ts, Us = _random_case(dims, kdims, seed=3)
-    ref = oracle_next_storage(LY.to_paper(Ts), Us)
-    got = gu.contract(Ts, Us, list(kdims), form)
-    Hd = int(np.prod(dims))
-    err = gu.relerr(got, ref)
-    print(f"form={form} dims={dims} k={kdims} relerr={err:.3e} tol={tol(form, Hd):.1e}")
-    assert err < tol(form, Hd)
+    _check_all_slices(form, dims, kdims, seed=3)
 
 
-def test_contract_full_size_sampled():
-    """chi = 16 in 3D (the bottleneck at full size, M = K = 4096): the oracle computes
-    only a few (n'_1, n'_2) slices of the new tensor; compare those element by element."""
-    dims, kdims = (16, 16, 16), (16, 16)
-    Ts, Us = _random_case(dims, kdims, seed=7)
-    Tp = LY.to_paper(Ts)
-    got = gu.contract(Ts, Us, list(kdims), P.HOTRG_FP64)
-    picks = [(0, 0), (15, 15), (3, 11)]
-    Tnew = H.new_tensor(Tp, {1: Us[0], 2: Us[1]}, only=picks)
-    ref = LY.to_storage(H.rename(Tnew))
-    # T^next storage [n1][n2][c][n1'][n2'][c']: compare the picked (n1', n2') columns
-    for (n1p, n2p) in picks:
-        g = got[:, :, :, n1p, n2p, :]
-        r = ref[:, :, :, n1p, n2p, :]
-        err = gu.relerr(g, r)
-        print(f"full-size slice ({n1p},{n2p}) relerr={err:.3e}")
-        assert err < tol(P.HOTRG_FP64, 4096)
+FULL_DIMS, FULL_K, FULL_SEED = (16, 16, 16), (16, 16), 8
+FULL_PICKS = PT.spread_picks(FULL_K, 16)
 
 
-@pytest.mark.parametrize("form", [P.HOTRG_SPLIT_FP16, P.HOTRG_SPLIT_BF16, P.HOTRG_FP16, P.HOTRG_FP32])
-def test_contract_forms_full_size_sampled(form):
-    """chi = 16 in 3D through the production kernels of each form (for the 16-bit forms the
-    non-prime chain runs in the GEMM epilogue at this size); sampled slices vs the oracle."""
-    dims, kdims = (16, 16, 16), (16, 16)
-    Ts, Us = _random_case(dims, kdims, seed=8)
-    Tp = LY.to_paper(Ts)
-    got = gu.contract(Ts, Us, list(kdims), form)
-    picks = [(0, 0), (15, 15), (7, 2)]
-    ref = LY.to_storage(H.rename(H.new_tensor(Tp, {1: Us[0], 2: Us[1]}, only=picks)))
-    for (n1p, n2p) in picks:
-        err = gu.relerr(got[:, :, :, n1p, n2p, :], ref[:, :, :, n1p, n2p, :])
-        print(f"form={form} full-size slice ({n1p},{n2p}) relerr={err:.3e} tol={tol(form, 4096):.1e}")
-        assert err < tol(form, 4096)
+@functools.lru_cache(maxsize=None)
+def _full_reference():
+    """chi = 16 in 3D (the bottleneck at full size, M = K = 4096): the oracle computes only the
+    16 picked (n'_1, n'_2) slices of the new tensor."""
+    Ts, Us = _random_case(FULL_DIMS, FULL_K, FULL_SEED)
+    return Ts, Us, oracle_next_storage(LY.to_paper(Ts), Us, only=FULL_PICKS)
+
+
+@pytest.mark.parametrize("form", [P.HOTRG_FP64, P.HOTRG_SPLIT_FP16, P.HOTRG_SPLIT_BF16, P.HOTRG_FP16,
+                                  P.HOTRG_FP32, P.HOTRG_BF16])
+def test_contract_full_size_sampled(form):
+    """chi = 16 in 3D through the production kernels of each form (for the reduced forms the
+    non-prime chain runs in the GEMM epilogue at this size): 16 spread (n'_1, n'_2) slices of
+    the new tensor against the oracle, element by element."""
+    Ts, Us, ref = _full_reference()
+    got = gu.contract(Ts, Us, list(FULL_K), form)
+    worst, errs = PT.worst_slice_error(got, ref, FULL_PICKS)
+    print(f"{FORM_NAME[form]} full size, 16 slices: max slice error {worst:.2e} (bound {SLICE_BOUND[form]:.0e}); "
+          "per slice " + " ".join(f"{e:.1e}" for e in errs))
+    assert worst < SLICE_BOUND[form]
 
 
 @pytest.mark.parametrize("dims", [(4, 4, 4), (3, 5, 2), (8, 8, 8), (12, 12, 12), (8, 8), (16, 24), (32, 32)])
@@ -129,9 +134,9 @@ def test_gram_matches_oracle(dims):
             ax = H.axis_n(d, j) if side == 0 else H.axis_np(d, j)
             ref = H.gram_matrix(Tp, ax)
             got = gu.gram(Ts, j, side)
-            err = gu.relerr(got, ref)
-            print(f"gram dims={dims} j={j} side={side} relerr={err:.3e}")
-            assert err < 1e-13
+            err = PT.slice_error(got, ref)
+            print(f"gram dims={dims} j={j} side={side} max|dA|/max|A|={err:.3e}")
+            assert err < GRAM_BOUND
 
 
 @pytest.mark.parametrize("n", [1, 2, 7, 64, 144, 256])
