@@ -11,6 +11,13 @@ the stored FP64 oracle fixture, the same figures for the FP64 form, and the orac
 timed on a bounded sample on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form split_fp16] [--no-cpu]
+
+Measurement helpers (each prints its own lines and exits):
+  --mfma-ceiling          issue rate of the MFMA instruction of each form (register-only loop)
+  --counter-steps N       N steps of the headline workload, lnZ/V printed after each step (a short
+                          run for rocprofv3 counter passes)
+  --copy-calibration MiB  a plain device copy of MiB, three times (the reference that turns the
+                          FETCH_SIZE / WRITE_SIZE counters into bytes)
 """
 
 from __future__ import annotations
@@ -33,14 +40,42 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6, "fp16": 2516.6,
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16 (f32 acc)", "fp16": "f16 (f32 acc)",
          "split_bf16": "bf16x3 hi/lo split (f32 acc)", "split_fp16": "f16x3 hi/lo split (f32 acc)"}
 PRODUCTS = {"split_bf16": 3, "split_fp16": 3}
+CEILING_KEY = {"fp64": "fp64", "fp32": "fp32", "bf16": "bf16", "fp16": "fp16", "split_bf16": "bf16",
+               "split_fp16": "fp16"}
 # HBM bytes per launch of the bottleneck kernel of the split FP16 form at chi = 16 (16 pair
-# groups per launch), from two rocprofv3 counter runs of paper_2110_03607_amd.step_probe
+# groups per launch), from two rocprofv3 counter runs of `bench.py --counter-steps 6`
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors read off a 1 GiB copy);
 # profiles/hotrg3d_chi16_split_fp16_trace_and_traffic.md. Valid only while that kernel is unchanged.
 GEMM_TRAFFIC_BYTES = {"split_fp16": 6.459e9}
 # Algorithmic bytes of the same launch: A operand (2 planes x 4096^2 x 2 B), B chunk
 # (2 planes x 65536 x 4096 x 2 B) and the new-tensor chunk written (4096 x 256 x 4 B).
 GEMM_ALGO_BYTES = {"split_fp16": 2 * 4096 * 4096 * 2 + 2 * 65536 * 4096 * 2 + 4096 * 256 * 4}
+
+
+def mfma_ceiling(P, torch):
+    """TFLOP/s of the MFMA instruction each form contracts with, from a loop of independent
+    register-only MFMAs over the whole GPU (hotrg_probe_mfma_rate)."""
+    s = torch.cuda.current_stream().cuda_stream
+    return {f: round(P.hotrg_probe_mfma_rate(P.FORMS[f], s), 1) for f in ("fp64", "fp32", "fp16", "bf16")}
+
+
+def counter_steps(P, torch, form, steps):
+    r = P.HOTRG("ising", 3, 1.0 / TEMP, CHI, precision=form, max_steps=steps)
+    for p in range(steps):
+        r.step()
+        print(f"step {p + 1} lnZ/V {r.log_z():.15f}", flush=True)
+    r.close()
+
+
+def copy_calibration(torch, mib):
+    n = mib * 1024 * 1024 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copied {mib} MiB three times ({3 * mib * 1024} KiB read and written)", flush=True)
 
 
 def fixture_lnz():
@@ -110,6 +145,16 @@ def run_batch(P, torch, form, steps=20, graphs=True):
     lnz = b.log_z()
     graphs, eager = b.graph_stats()
     b_tuned = b.tuned
+    # phase identification (Section 4.1.2, eq. ratio_X): the Gu-Wen ratio after the last step of
+    # each 3D instance -> 2 in the ordered phase (two degenerate fixed-point sectors), 1 in the
+    # disordered one; the crossing of X = 1.5 between neighbouring temperatures estimates T_c
+    temps = [1.0 / i.beta for i in inst[:64]]
+    xs = [b.info(i, steps).gu_wen for i in range(64)]
+    cross = None
+    for i in range(63):
+        if (xs[i] - 1.5) * (xs[i + 1] - 1.5) <= 0 and xs[i] != xs[i + 1]:
+            cross = temps[i] + (1.5 - xs[i]) * (temps[i + 1] - temps[i]) / (xs[i + 1] - xs[i])
+            break
     b.close()
     timed = steps - first_timed + 1
     ms = (t1 - t0) * 1e3 / timed
@@ -120,7 +165,9 @@ def run_batch(P, torch, form, steps=20, graphs=True):
             "contract_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
             "graph_launches": graphs, "eager_steps": eager, "wall_s_all_steps": round(t1 - t_start, 3),
             "autotuner": {"seconds": round(tune_s, 3), "classes": b_tuned},
-            "lnz_per_site_first_last": [lnz[0], lnz[63], lnz[64], lnz[-1]]}
+            "lnz_per_site_first_last": [lnz[0], lnz[63], lnz[64], lnz[-1]],
+            "gu_wen_scan_3d": {"T": [round(t, 5) for t in temps], "X_after_step_20": [round(x, 5) for x in xs],
+                               "T_where_X_crosses_1.5": None if cross is None else round(cross, 4)}}
 
 
 def eigh_2d_chi32(P, torch, beta=0.44, steps=8, timed=3):
@@ -213,6 +260,9 @@ def main():
                     help="skip the FP64 reference run (profiling runs of the headline form only)")
     ap.add_argument("--other-forms", default="fp32,split_bf16,fp16,bf16",
                     help="comma-separated forms also reported (2 timed steps each); empty for none")
+    ap.add_argument("--mfma-ceiling", action="store_true", help="only the MFMA issue-rate probe")
+    ap.add_argument("--counter-steps", type=int, default=0, help="only N steps with per-step output")
+    ap.add_argument("--copy-calibration", type=int, default=0, help="only a device copy of MiB, three times")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of the "
@@ -226,11 +276,21 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     P.lib()
+    if args.mfma_ceiling:
+        print(json.dumps({"mfma_ceiling_tflops": mfma_ceiling(P, torch)}), flush=True)
+        return
+    if args.counter_steps:
+        counter_steps(P, torch, args.form, args.counter_steps)
+        return
+    if args.copy_calibration:
+        copy_calibration(torch, args.copy_calibration)
+        return
     if args.batch_only:
         print(json.dumps({"batch_sweep": run_batch(P, torch, args.form, graphs=not args.batch_no_graphs)}), flush=True)
         return
     ref_lnz = fixture_lnz()
 
+    ceiling = mfma_ceiling(P, torch)
     head = run_form(P, torch, args.form, args.steps, args.warmup)
     tm = head["timings"]
     ms_per_step = head["wall"] * 1e3 / args.steps
@@ -313,6 +373,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(bott_tflops / peak, 4),
             "issued_frac": round(bott_tflops * PRODUCTS.get(args.form, 1) / peak, 4),
+            "mfma_ceiling": ceiling[CEILING_KEY[args.form]],
+            "issued_frac_of_ceiling": round(bott_tflops * PRODUCTS.get(args.form, 1) / ceiling[CEILING_KEY[args.form]], 4),
             "avg_launch_ms": round(bott_ms_avg, 4),
             "launches": tm["bottleneck"]["count"],
             "traffic": GEMM_TRAFFIC_BYTES.get(args.form),

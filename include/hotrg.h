@@ -68,6 +68,16 @@ typedef struct hotrg_model {
     double h;     /* field (Ising only)                              */
 } hotrg_model;
 
+/* ---- normalisation factor f^(p) (Section 3.1.3: any f is admissible; lnZ/V does not
+ * depend on it, eqs. eq_lnZ, K_recurrence) ------------------------------------------ */
+#define HOTRG_NORM_TRACE   0  /* f^(p) = 1 / Tr T^(p)    (the paper's example)            */
+#define HOTRG_NORM_MAXABS  1  /* f^(p) = 1 / max |T^(p)| (the largest element becomes 1)  */
+
+/* ---- choice between U and U' (Section 4.2.6: any rational criterion may be used) ---- */
+#define HOTRG_CHOOSE_EPSILON 0  /* Section 2: U if epsilon < epsilon', otherwise U'      */
+#define HOTRG_CHOOSE_U       1  /* always U (the non-prime side); epsilons still recorded */
+#define HOTRG_CHOOSE_UPRIME  2  /* always U' (the prime side)                            */
+
 typedef struct hotrg_opts {
     int precision;    /* HOTRG_FP64 .. HOTRG_SPLIT_FP16                          */
     int max_steps;    /* capacity of the per-step record (diagnostics), >= 1      */
@@ -75,7 +85,10 @@ typedef struct hotrg_opts {
                          0 = automatic.  Bounds the memory of the prime-chain output
                          (the paper's loop over n'_1, Section 4.2.9).            */
     int record_grad;  /* 1: carry d/dbeta through every step (FP64 / FP32 forms,
-                         beta > 0); hotrg_grad then returns d(lnZ/V)/dbeta        */
+                         beta > 0, norm = HOTRG_NORM_TRACE); hotrg_grad then
+                         returns d(lnZ/V)/dbeta                                    */
+    int norm;         /* HOTRG_NORM_TRACE (0) or HOTRG_NORM_MAXABS                 */
+    int choice;       /* HOTRG_CHOOSE_EPSILON (0), HOTRG_CHOOSE_U, HOTRG_CHOOSE_UPRIME */
 } hotrg_opts;
 
 typedef struct hotrg_handle hotrg_handle;
@@ -223,6 +236,30 @@ size_t hotrg_debug_eigh_workspace_bytes(int n, int batch);
  * ||T z - lambda z|| exceeds 1e-9 |T| (the same failure makes hotrg_step's run fail). */
 int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_dev,
                      void* workspace_dev, size_t workspace_bytes, void* hip_stream);
+
+/* ---- measurement -------------------------------------------------------------------------
+ * Issue rate of the MFMA instruction a precision form contracts with (FP64: v_mfma_f64_16x16x4,
+ * FP32: v_mfma_f32_16x16x4_f32, 16-bit forms: v_mfma_f32_16x16x32_{f16,bf16}), in TFLOP/s, from
+ * a kernel whose waves run only independent MFMAs on register operands: the ceiling a
+ * contraction kernel of that form can reach on this GPU at its clock under load.  Synchronises
+ * `hip_stream`.  Errors: HOTRG_E_ARG, HOTRG_E_DEVICE. */
+int hotrg_probe_mfma_rate(int precision, double* tflops, void* hip_stream);
+
+/* ---- allocation-free variant of hotrg_debug_eigh ------------------------------------------
+ * For callers that cannot allocate device memory or pass a workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same eigensolver and results
+ * as hotrg_debug_eigh; its scratch (2 n^2 doubles per matrix) lives in a static device array of
+ * hotrg_eigh_noalloc_max_bytes() = 16 MiB that each device holds until the process ends, so
+ * batch * 2 * n^2 * 8 <= 16 MiB (n = 1024: batch 1; n <= 724: batch 2; n <= 512: batch 4).
+ * Larger requests return HOTRG_E_ARG with nothing enqueued.  The call only enqueues work on
+ * `hip_stream` (no allocation, no synchronisation): *status_dev (a device int) is set to 0 and
+ * then to 1 if the decomposition failed (as hotrg_debug_eigh's HOTRG_E_NUMERIC).  All calls on
+ * one device share the static array: calls that overlap on one device (different streams or
+ * host threads without ordering between them) race and give undefined results.
+ * Errors: HOTRG_E_ARG, HOTRG_E_DEVICE. */
+size_t hotrg_eigh_noalloc_max_bytes(void);
+int hotrg_eigh_noalloc(int n, int batch, double* A_dev, double* w_dev, double* V_dev, int* status_dev,
+                       void* hip_stream);
 
 /* ---- batched runs: a sweep of independent instances (models, beta, chi) --------------
  * The same coarse-graining step (Sections 3-4) applied to many independent runs, e.g. a

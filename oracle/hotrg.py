@@ -254,20 +254,28 @@ class Truncation:
     kept: int                     # columns not zeroed by the multiplet rule (R8)
 
 
-def choose_isometry(A: np.ndarray, Ap: np.ndarray, chi: int, multiplets: bool = True) -> Truncation:
+CHOICES = ("epsilon", "U", "Uprime")
+
+
+def choose_isometry(A: np.ndarray, Ap: np.ndarray, chi: int, multiplets: bool = True,
+                    choice: str = "epsilon") -> Truncation:
     """Decompose A and A', compare epsilon and epsilon', keep the first chi_new columns.
 
-    chi_new = min(chi_j^2, chi) (Section 2).  If epsilon < epsilon' then U is
-    adopted, otherwise U' (R3).  With `multiplets`, columns of a multiplet split by
-    the cut are zeroed (R8).
+    chi_new = min(chi_j^2, chi) (Section 2).  choice "epsilon" (the paper's criterion): if
+    epsilon < epsilon' then U is adopted, otherwise U' (R3).  Section 4.2.6 allows any rational
+    criterion; "U" and "Uprime" always adopt that side (epsilon and epsilon' are still
+    recorded).  With `multiplets`, columns of a multiplet split by the cut are zeroed (R8).
     """
+    if choice not in CHOICES:
+        raise ValueError(choice)
     n = A.shape[0]
     chi_new = min(n, chi)
     lam, U = eig_descending(A)
     lam_p, U_p = eig_descending(Ap)
     eps = judgement_value(lam, chi_new)
     eps_p = judgement_value(lam_p, chi_new)
-    if eps < eps_p:
+    prime = (not eps < eps_p) if choice == "epsilon" else (choice == "Uprime")
+    if not prime:
         Ut, prime, lam_c = U[:, :chi_new].copy(), False, lam
     else:
         Ut, prime, lam_c = U_p[:, :chi_new].copy(), True, lam_p
@@ -396,7 +404,7 @@ class StepRecord:
     truncations: dict = field(default_factory=dict)
 
 
-def coarse_grain(T: np.ndarray, chi: int, multiplets: bool = True):
+def coarse_grain(T: np.ndarray, chi: int, multiplets: bool = True, choice: str = "epsilon"):
     """One coarse-graining step along the Current direction of T (Sections 3-4).
 
     Returns (T^new before normalisation and before renaming, truncations).
@@ -407,7 +415,7 @@ def coarse_grain(T: np.ndarray, chi: int, multiplets: bool = True):
     for j in range(1, d):
         A = gram_matrix(T, axis_n(d, j))              # non-prime side
         Ap = gram_matrix(T, axis_np(d, j))            # prime side
-        tr[j] = choose_isometry(A, Ap, chi, multiplets)
+        tr[j] = choose_isometry(A, Ap, chi, multiplets, choice)
         Ut[j] = tr[j].U
     return new_tensor(T, Ut), tr
 
@@ -433,7 +441,7 @@ def normalisation_factor(T: np.ndarray, norm: str) -> float:
 
 
 def run(model: Model, beta: float, chi: int, steps: int, T0: np.ndarray | None = None,
-        on_step=None, norm: str = "trace", multiplets: bool = True):
+        on_step=None, norm: str = "trace", multiplets: bool = True, choice: str = "epsilon"):
     """Full oracle run: initial tensor, normalisation, `steps` coarse-graining steps.
 
     lnZ bookkeeping follows eqs. (eq_lnZ) and (K_recurrence):
@@ -453,7 +461,7 @@ def run(model: Model, beta: float, chi: int, steps: int, T0: np.ndarray | None =
     records = []
     for p in range(1, steps + 1):
         dims = T.shape
-        Tnew, tr = coarse_grain(T, chi, multiplets)
+        Tnew, tr = coarse_grain(T, chi, multiplets, choice)
         t = trace(Tnew)
         if not (t > 0.0 and math.isfinite(t)):
             raise FloatingPointError(f"non-positive trace at step {p}: {t}")

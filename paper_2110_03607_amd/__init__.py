@@ -21,6 +21,11 @@ HOTRG_OK, HOTRG_E_ARG, HOTRG_E_STATE, HOTRG_E_NUMERIC, HOTRG_E_OOM, HOTRG_E_DEVI
 HOTRG_ISING, HOTRG_POTTS = 0, 1
 # precision forms
 HOTRG_FP64, HOTRG_FP32, HOTRG_BF16, HOTRG_FP16, HOTRG_SPLIT_BF16, HOTRG_SPLIT_FP16 = range(6)
+# normalisation factor and choice between U and U'
+HOTRG_NORM_TRACE, HOTRG_NORM_MAXABS = 0, 1
+NORMS = {"trace": HOTRG_NORM_TRACE, "maxabs": HOTRG_NORM_MAXABS}
+HOTRG_CHOOSE_EPSILON, HOTRG_CHOOSE_U, HOTRG_CHOOSE_UPRIME = 0, 1, 2
+CHOICES = {"epsilon": HOTRG_CHOOSE_EPSILON, "U": HOTRG_CHOOSE_U, "Uprime": HOTRG_CHOOSE_UPRIME}
 FORMS = {"fp64": HOTRG_FP64, "fp32": HOTRG_FP32, "bf16": HOTRG_BF16, "fp16": HOTRG_FP16,
          "split_bf16": HOTRG_SPLIT_BF16, "split_fp16": HOTRG_SPLIT_FP16}
 HOTRG_MAX_DIRS = 3
@@ -33,7 +38,7 @@ class hotrg_model(ctypes.Structure):
 
 class hotrg_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("max_steps", ctypes.c_int), ("chunk", ctypes.c_int),
-                ("record_grad", ctypes.c_int)]
+                ("record_grad", ctypes.c_int), ("norm", ctypes.c_int), ("choice", ctypes.c_int)]
 
 
 class hotrg_step_record(ctypes.Structure):
@@ -114,6 +119,10 @@ _SIGS = {
     "hotrg_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "hotrg_debug_eigh": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "hotrg_probe_mfma_rate": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "hotrg_eigh_noalloc_max_bytes": (ctypes.c_size_t, []),
+    "hotrg_eigh_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -254,6 +263,22 @@ def hotrg_debug_eigh(n, batch, A_ptr, w_ptr, V_ptr, ws_ptr, ws_bytes, stream_ptr
     _check(rc, None)
 
 
+def hotrg_probe_mfma_rate(precision: int, stream_ptr: int) -> float:
+    v = ctypes.c_double()
+    _check(lib().hotrg_probe_mfma_rate(precision, ctypes.byref(v), ctypes.c_void_p(stream_ptr)), None)
+    return v.value
+
+
+def hotrg_eigh_noalloc_max_bytes() -> int:
+    return lib().hotrg_eigh_noalloc_max_bytes()
+
+
+def hotrg_eigh_noalloc(n, batch, A_ptr, w_ptr, V_ptr, status_ptr, stream_ptr):
+    rc = lib().hotrg_eigh_noalloc(n, batch, ctypes.c_void_p(A_ptr), ctypes.c_void_p(w_ptr), ctypes.c_void_p(V_ptr),
+                                  ctypes.c_void_p(status_ptr), ctypes.c_void_p(stream_ptr))
+    _check(rc, None)
+
+
 def _check_batch(rc: int, b=None):
     if rc != HOTRG_OK:
         msg = lib().hotrg_batch_last_error(b)
@@ -333,13 +358,14 @@ class HOTRG:
 
     def __init__(self, kind: str, d: int, beta: float, chi: int, q: int | None = None, J: float = 1.0,
                  h: float = 0.0, precision: str = "fp64", max_steps: int = 64, chunk: int = 0,
-                 record_grad: bool = False):
+                 record_grad: bool = False, norm: str = "trace", choice: str = "epsilon"):
         import torch
 
         kind_id = {"ising": HOTRG_ISING, "potts": HOTRG_POTTS}[kind]
         q = 2 if kind == "ising" else (3 if q is None else q)
         self.model = hotrg_model(kind_id, d, q, J, h)
-        self.opts = hotrg_opts(FORMS[precision], max_steps, chunk, 1 if record_grad else 0)
+        self.opts = hotrg_opts(FORMS[precision], max_steps, chunk, 1 if record_grad else 0, NORMS[norm],
+                               CHOICES[choice])
         self.d = d
         nbytes = hotrg_workspace_bytes(self.model, chi, self.opts)
         if nbytes == 0:
@@ -352,7 +378,8 @@ class HOTRG:
         self.steps = 0
 
     @classmethod
-    def from_tensor(cls, T0, chi: int, precision: str = "fp64", max_steps: int = 64, chunk: int = 0):
+    def from_tensor(cls, T0, chi: int, precision: str = "fp64", max_steps: int = 64, chunk: int = 0,
+                    norm: str = "trace", choice: str = "epsilon"):
         """A run started from a local tensor T0 (a float64 torch tensor on the GPU, storage order
         T[c][n_1]..[c'][n'_1].., shape dims + dims) instead of a lattice model."""
         import torch
@@ -361,7 +388,7 @@ class HOTRG:
         d = T0.dim() // 2
         dims = list(T0.shape[:d])
         self.model = None
-        self.opts = hotrg_opts(FORMS[precision], max_steps, chunk, 0)
+        self.opts = hotrg_opts(FORMS[precision], max_steps, chunk, 0, NORMS[norm], CHOICES[choice])
         self.d = d
         nbytes = hotrg_tensor_workspace_bytes(d, dims, chi, self.opts)
         if nbytes == 0:
@@ -466,12 +493,12 @@ class HOTRGBatch:
     """
 
     def __init__(self, instances, precision: str = "fp64", max_steps: int = 64, chunk: int = 0,
-                 graphs: bool = True, tune: bool = False):
+                 graphs: bool = True, tune: bool = False, norm: str = "trace", choice: str = "epsilon"):
         import torch
 
         self.instances = list(instances)
         self.n = len(self.instances)
-        self.opts = hotrg_opts(FORMS[precision], max_steps, chunk, 0)
+        self.opts = hotrg_opts(FORMS[precision], max_steps, chunk, 0, NORMS[norm], CHOICES[choice])
         nbytes = hotrg_batch_workspace_bytes(self.instances, self.opts)
         if nbytes == 0:
             raise HotrgError(HOTRG_E_ARG, "invalid instance or options")

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -271,14 +272,15 @@ Plan make_plan(int d, const std::vector<int>& starts, int chi, int form, int use
   return P;
 }
 
-// Relative difference below which two Gram eigenvalues count as one multiplet in each form,
-// and floor (relative to the largest) below which eigenvalues are not examined: 16 unit
-// roundoffs of the form (0 for FP64: the exact multiplet rule of the oracle).
+// Relative rounding of the Gram spectrum in each form (the multiplet floor of k_choose): 16 unit
+// roundoffs of the arithmetic that bounds the form's accuracy (0 for FP64: the exact multiplet
+// rule of the oracle).  Split FP16 operands carry 22 bits, more than the FP32 master tensor and
+// accumulation they feed, so its value is FP32's.
 double multiplet_tau(int form) {
   switch (form) {
     case HOTRG_FP64: return 0.0;
     case HOTRG_FP32: return 16.0 * 0x1p-24;
-    case HOTRG_SPLIT_FP16: return 16.0 * 0x1p-21;
+    case HOTRG_SPLIT_FP16: return 16.0 * 0x1p-24;
     case HOTRG_SPLIT_BF16: return 16.0 * 0x1p-16;
     case HOTRG_FP16: return 16.0 * 0x1p-11;
     default: return 16.0 * 0x1p-8;
@@ -428,6 +430,12 @@ template <> struct GemmCfg<F_FP16> { static constexpr int BK = 64; };
 template <> struct GemmCfg<F_SPLIT_BF16> { static constexpr int BK = 64; };
 template <> struct GemmCfg<F_SPLIT_FP16> { static constexpr int BK = 64; };
 
+// Operand tiles of the large-tile GEMM loaded straight into LDS (k_gemm_big, DL).
+#ifndef HOTRG_GEMM_DIRECT_LOADS
+#define HOTRG_GEMM_DIRECT_LOADS 0
+#endif
+constexpr bool GEMM_DIRECT_LOADS = HOTRG_GEMM_DIRECT_LOADS != 0;
+
 template <int F>
 void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, long bplane, void* C, long ldc,
                  long czs, long Mp, long Np, long Kp, int Z, long kchunk, const double* scale_ptr, double smult,
@@ -441,13 +449,13 @@ void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, 
       const int mt = (int)(Mp / GB_BM), nt = (int)(Np / GB_BN);
       constexpr int WAVES = 8;   // 2 waves per SIMD: one wave's LDS/barrier phase hides under the other's MFMAs
       if (fuse)
-        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, true>), dim3((unsigned)(mt * nt)), dim3(64 * WAVES), 0, s,
-                           (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B, ldb, bplane,
-                           (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, *fuse);
+        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, true, GEMM_DIRECT_LOADS>), dim3((unsigned)(mt * nt)),
+                           dim3(64 * WAVES), 0, s, (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B,
+                           ldb, bplane, (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, *fuse);
       else
-        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, false>), dim3((unsigned)(mt * nt)), dim3(64 * WAVES), 0, s,
-                           (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B, ldb, bplane,
-                           (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, FuseArgs{});
+        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, false, GEMM_DIRECT_LOADS>), dim3((unsigned)(mt * nt)),
+                           dim3(64 * WAVES), 0, s, (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B,
+                           ldb, bplane, (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, FuseArgs{});
       return;
     }
   }
@@ -915,7 +923,7 @@ int enqueue_choose(hotrg_handle* h, const LocalDims& ld, const int* k, const voi
     hipLaunchKernelGGL(k_choose, dim3(1), dim3(256), 0, h->s, (const double*)(w + s0 * wn),
                        (const double*)(w + s1 * wn), (const double*)(Vo + s0 * am), (const double*)(Vo + s1 * am),
                        n, k[j - 1], n <= h->chi ? 1 : 0, multiplet_tau(h->form), Ut, Ut32, rec_base,
-                       (const DevState*)st, j - 1);
+                       (const DevState*)st, j - 1, h->opts.choice);
     if (dT) {
       double* dUt = h->at<double>(h->plan.off_dUt) + (size_t)(j - 1) * ut_stride;
       float* dUt32 = h->at<float>(h->plan.off_dUt32) + (size_t)(j - 1) * ut_stride;
@@ -1020,7 +1028,7 @@ bool same_dims(const LocalDims& a, const LocalDims& b) {
 // natural cycle (computed on the device from the step counter).
 int enqueue_step_front(hotrg_handle* h, int axis_rec) {
   const LocalDims& ld = h->ld;
-  hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(256), 0, h->s, h->rec(0), (const DevState*)h->st(), axis_rec, ld.d,
+  hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(256), 0, h->s, h->rec(0), h->st(), axis_rec, ld.d,
                      ld.chi[0], ld.chi[1], ld.d == 3 ? ld.chi[2] : 0);
   void* dT = h->grad ? h->at<void>(h->plan.off_dT) : nullptr;
   return enqueue_grams(h, h->at<void>(h->plan.off_T), ld, dT);
@@ -1047,9 +1055,18 @@ int enqueue_step_back(hotrg_handle* h, const StepPlan& sp, hipEvent_t t_dec) {
   const long Hn = sp.Hn;
   const int chic = sp.ld.chi[0];
   hipEvent_t t_tr = tmark(h);
+  const int norm = h->opts.norm;
+  if (norm == HOTRG_NORM_MAXABS) {
+    if (h->form == HOTRG_FP64)
+      hipLaunchKernelGGL((k_maxabs_raw<double>), dim3(grid_reduce(Hn * Hn)), dim3(256), 0, h->s, (const double*)Tn,
+                         Hn * Hn, st);
+    else
+      hipLaunchKernelGGL((k_maxabs_raw<float>), dim3(grid_reduce(Hn * Hn)), dim3(256), 0, h->s, (const float*)Tn,
+                         Hn * Hn, st);
+  }
   if (h->form == HOTRG_FP64) {
     hipLaunchKernelGGL((k_trace_lnz<double>), dim3(1), dim3(256), 0, h->s, (const double*)Tn, (int)Hn, chic, st,
-                       h->rec(0));
+                       h->rec(0), norm);
     if (h->grad)
       hipLaunchKernelGGL((k_trace_t<double>), dim3(1), dim3(256), 0, h->s, (const double*)dTn, (int)Hn, st);
     hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, h->s, st);
@@ -1060,7 +1077,7 @@ int enqueue_step_back(hotrg_handle* h, const StepPlan& sp, hipEvent_t t_dec) {
       hipLaunchKernelGGL((k_scale<double>), dim3(grid_reduce(Hn * Hn)), dim3(256), 0, h->s, (double*)Tn, Hn * Hn, st);
   } else {
     hipLaunchKernelGGL((k_trace_lnz<float>), dim3(1), dim3(256), 0, h->s, (const float*)Tn, (int)Hn, chic, st,
-                       h->rec(0));
+                       h->rec(0), norm);
     if (h->grad)
       hipLaunchKernelGGL((k_trace_t<float>), dim3(1), dim3(256), 0, h->s, (const float*)dTn, (int)Hn, st);
     hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, h->s, st);
@@ -1123,9 +1140,16 @@ static int check_model(const hotrg_model* m, int chi) {
   return HOTRG_OK;
 }
 
+// The option fields every entry point checks: form, record size, chunk, normalisation, choice.
+static bool opts_valid(const hotrg_opts* o) {
+  return o && form_valid(o->precision) && o->max_steps >= 1 && o->chunk >= 0 && o->record_grad >= 0 &&
+         o->record_grad <= 1 && (o->norm == HOTRG_NORM_TRACE || o->norm == HOTRG_NORM_MAXABS) &&
+         o->choice >= HOTRG_CHOOSE_EPSILON && o->choice <= HOTRG_CHOOSE_UPRIME &&
+         !(o->record_grad && o->norm != HOTRG_NORM_TRACE);
+}
+
 size_t hotrg_workspace_bytes(const hotrg_model* model, int chi, const hotrg_opts* opts) {
-  if (!opts || check_model(model, chi) != HOTRG_OK || !form_valid(opts->precision) || opts->max_steps < 1)
-    return 0;
+  if (!opts_valid(opts) || check_model(model, chi) != HOTRG_OK) return 0;
   if (opts->record_grad && opts->precision != HOTRG_FP64 && opts->precision != HOTRG_FP32) return 0;
   return make_plan(model->d, {model->q}, chi, opts->precision, opts->chunk, opts->max_steps, opts->record_grad != 0)
       .total;
@@ -1134,9 +1158,9 @@ size_t hotrg_workspace_bytes(const hotrg_model* model, int chi, const hotrg_opts
 static int check_init_args(const hotrg_model* model, double beta, int chi, const hotrg_opts* opts) {
   if (!opts || !model) return fail(nullptr, HOTRG_E_ARG, "model or opts is NULL");
   if (check_model(model, chi) != HOTRG_OK) return fail(nullptr, HOTRG_E_ARG, "invalid model or chi");
-  if (!form_valid(opts->precision) || opts->max_steps < 1 || opts->chunk < 0 || opts->record_grad < 0 ||
-      opts->record_grad > 1)
-    return fail(nullptr, HOTRG_E_ARG, "invalid options");
+  if (!opts_valid(opts))
+    return fail(nullptr, HOTRG_E_ARG, "invalid options (form, max_steps, chunk, norm, choice; the derivative needs "
+                                      "the trace normalisation)");
   if (opts->record_grad && opts->precision != HOTRG_FP64 && opts->precision != HOTRG_FP32)
     return fail(nullptr, HOTRG_E_ARG, "the derivative is available in the FP64 and FP32 forms");
   if (opts->record_grad && !(beta > 0.0))
@@ -1169,11 +1193,11 @@ static hotrg_handle* new_handle(const hotrg_model* model, double beta, int chi, 
     if (h->form == HOTRG_FP64)
       hipLaunchKernelGGL((k_init_tensor<double>), dim3(1), dim3(256), 0, h->s, h->at<double>(P.off_T),
                          h->grad ? h->at<double>(P.off_dT) : (double*)nullptr, model->kind, model->d, model->q, beta,
-                         model->J, model->h, h->st());
+                         model->J, model->h, h->st(), opts->norm);
     else
       hipLaunchKernelGGL((k_init_tensor<float>), dim3(1), dim3(256), 0, h->s, h->at<float>(P.off_T),
                          h->grad ? h->at<float>(P.off_dT) : (float*)nullptr, model->kind, model->d, model->q, beta,
-                         model->J, model->h, h->st());
+                         model->J, model->h, h->st(), opts->norm);
     e = hipGetLastError();
   }
   if (e != hipSuccess) {
@@ -1207,7 +1231,7 @@ static int check_tensor_args(int d, const int* dims, int chi, const hotrg_opts* 
   if (chi < 1 || chi > maxchi) return fail(nullptr, HOTRG_E_ARG, "chi out of range");
   for (int i = 0; i < d; ++i)
     if (dims[i] < 1 || dims[i] > maxchi) return fail(nullptr, HOTRG_E_ARG, "tensor dimension out of range");
-  if (!form_valid(opts->precision) || opts->max_steps < 1 || opts->chunk < 0 || opts->record_grad != 0)
+  if (!opts_valid(opts) || opts->record_grad != 0)
     return fail(nullptr, HOTRG_E_ARG, "invalid options (record_grad must be 0 for a supplied tensor)");
   return HOTRG_OK;
 }
@@ -1242,7 +1266,9 @@ int hotrg_init_tensor(int d, const int* dims, const double* T0_dev, int chi, con
   // state and step records cleared by a kernel (no memset node if a caller records the stream)
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(256), 0, h->s, (int*)(h->ws + P.off_state),
                      (int)((P.off_T - P.off_state) / sizeof(int)));
-  hipLaunchKernelGGL(k_init_user_trace, dim3(1), dim3(256), 0, h->s, T0_dev, (int)H, h->st());
+  if (opts->norm == HOTRG_NORM_MAXABS)
+    hipLaunchKernelGGL((k_maxabs_raw<double>), dim3(grid_reduce(H * H)), dim3(256), 0, h->s, T0_dev, H * H, h->st());
+  hipLaunchKernelGGL(k_init_user_trace, dim3(1), dim3(256), 0, h->s, T0_dev, (int)H, h->st(), opts->norm);
   if (h->form == HOTRG_FP64)
     hipLaunchKernelGGL((k_init_user_scale<double>), dim3(grid_reduce(H * H)), dim3(256), 0, h->s, T0_dev,
                        h->at<double>(P.off_T), H * H, h->st());
@@ -1589,6 +1615,111 @@ int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_d
   return HOTRG_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Measurement: issue rate of the MFMA instruction each precision form uses.
+// ---------------------------------------------------------------------------
+int hotrg_probe_mfma_rate(int precision, double* tflops, void* stream) {
+  if (!tflops || !form_valid(precision)) return fail(nullptr, HOTRG_E_ARG, "invalid argument");
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned blocks = 4096, threads = 512;
+  double flops_per_mma = 0.0;
+  int iters = 0;
+  auto launch = [&](int it) {
+    switch (precision) {
+      case HOTRG_FP64: hipLaunchKernelGGL(k_mfma_loop<OpF64>, dim3(blocks), dim3(threads), 0, s, it, (float*)nullptr);
+        break;
+      case HOTRG_FP32: hipLaunchKernelGGL(k_mfma_loop<OpF32>, dim3(blocks), dim3(threads), 0, s, it, (float*)nullptr);
+        break;
+      case HOTRG_BF16: case HOTRG_SPLIT_BF16:
+        hipLaunchKernelGGL(k_mfma_loop<OpBF16>, dim3(blocks), dim3(threads), 0, s, it, (float*)nullptr); break;
+      default: hipLaunchKernelGGL(k_mfma_loop<OpF16>, dim3(blocks), dim3(threads), 0, s, it, (float*)nullptr);
+    }
+  };
+  switch (precision) {
+    case HOTRG_FP64: flops_per_mma = 2.0 * 16 * 16 * 4; iters = 256; break;
+    case HOTRG_FP32: flops_per_mma = 2.0 * 16 * 16 * 4; iters = 512; break;
+    default: flops_per_mma = 2.0 * 16 * 16 * 32; iters = 1024; break;
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(nullptr, HOTRG_E_DEVICE, "event creation failed");
+  launch(iters / 8);   // warm-up
+  (void)hipEventRecord(e0, s);
+  launch(iters);
+  (void)hipEventRecord(e1, s);
+  float ms = 0.f;
+  hipError_t e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
+  const double waves = (double)blocks * threads / 64.0;
+  *tflops = waves * iters * 8.0 * flops_per_mma / (ms * 1e-3) / 1e12;
+  return HOTRG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free eigensolver entry point: the same kernels as hotrg_debug_eigh, with their
+// scratch (reflectors and tridiagonal eigenvectors, 2 n^2 doubles per matrix) in a static device
+// array instead of a caller workspace.  Every device the library runs on holds its own copy until
+// the process ends; all calls on one device share it.
+// ---------------------------------------------------------------------------
+static constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;   // 16 MiB
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};   // device address of `scratch`, per device
+}  // namespace
+
+size_t hotrg_eigh_noalloc_max_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
+int hotrg_eigh_noalloc(int n, int batch, double* A_dev, double* w_dev, double* V_dev, int* status_dev,
+                       void* stream) {
+  if (n < 1 || n > EIG_MAXN || batch < 1 || batch > 4 || !A_dev || !w_dev || !V_dev || !status_dev)
+    return fail(nullptr, HOTRG_E_ARG, "invalid argument");
+  const size_t need = (size_t)batch * 2 * n * n * sizeof(double);
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(nullptr, HOTRG_E_ARG, "batch * 2 n^2 doubles exceed the 16 MiB static scratch of hotrg_eigh_noalloc "
+                                      "(use hotrg_debug_eigh with a workspace)");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(nullptr, HOTRG_E_DEVICE, "device index out of range");
+  double* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+      // the host-side name `scratch` is not a device address: look the array up on this device
+      void* p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return fail(nullptr, HOTRG_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      g_noalloc_ptr[dev] = p;
+    }
+    base = (double*)g_noalloc_ptr[dev];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, status_dev, 1);
+  EigBatch eb{};
+  eb.count = batch;
+  for (int b = 0; b < batch; ++b) {
+    eb.n[b] = n;
+    eb.kvec[b] = n;
+    eb.A[b] = A_dev + (size_t)b * n * n;
+    eb.w[b] = w_dev + (size_t)b * n;
+    eb.V[b] = V_dev + (size_t)b * n * n;
+    eb.scratch[b] = base + (size_t)b * 2 * n * n;
+    eb.fail[b] = status_dev;
+  }
+  enqueue_tri_steps(eb, s);
+  hipLaunchKernelGGL(k_eigh_tri, dim3(batch), dim3(EIG_THREADS), 0, s, eb);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
+  return HOTRG_OK;
+}
 
 // ===========================================================================
 // Batched runs

@@ -30,6 +30,8 @@ struct DevState {
   double inv_scale;    // 1 / (s_A s_B) applied to the FP16-form products
   double dlnz;         // d(lnZ/V)/d(beta) (derivative mode)
   double dt;           // d(Tr T^new)/d(beta) of the last step
+  double kappa;        // K^(p+1) / 2^(p+1) of eq. K_recurrence: sum_q ln(1/f^(q)) / 2^q over the steps done
+  double mraw;         // max |T^new| before normalisation (normalisation by the largest element)
   int err;             // sticky error code (HOTRG_E_*)
   int p;               // steps done
   int eig_fail;        // eigensolver did not converge
@@ -387,7 +389,11 @@ struct FuseArgs {
   int chic, g0;
 };
 
-template <class Op, int PLANES, int WAVES, bool FUSE>
+// DL: the operand tiles go from global memory straight into LDS (global_load_lds_dwordx4: each
+// lane's 16 bytes land at the wave's LDS base + 16 lane), with no staging registers and no LDS
+// store instructions.  Lane l of a load fetches the global chunk that belongs at its LDS slot
+// (the XOR swizzle is applied to the global address instead of the LDS address).
+template <class Op, int PLANES, int WAVES, bool FUSE, bool DL = false>
 __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
     const typename Op::T* __restrict__ A, long lda, long a_plane,
     const typename Op::T* __restrict__ B, long ldb, long b_plane,
@@ -437,10 +443,69 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
     for (int j = 0; j < NB; ++j) acc[i][j] = AccV{0, 0, 0, 0};
 
   const int nk = Kp / BKE;
+  const int fr = lane & 15, fc = lane >> 4;
+  if constexpr (DL) {
+    // global offsets (elements) of this lane's chunk in each of its CH slots, k excluded
+    long offa[CH], offb[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int q = i * THREADS + wave * 64 + lane, r = q >> 2, c = (q & 3) ^ ((r >> 1) & 3);
+      offa[i] = (m0 + r) * lda + c * CE;
+      offb[i] = (n0 + r) * ldb + c * CE;
+    }
+    auto issue = [&](int stage, long k0) {
+#pragma unroll
+      for (int p = 0; p < PLANES; ++p)
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          char* la = lds + stage * STAGE + p * (GB_BM + GB_BN) * 64 + (i * THREADS + wave * 64) * 16;
+          __builtin_amdgcn_global_load_lds((const void*)(Ab + ES * (p * a_plane + offa[i] + k0)),
+                                           (__attribute__((address_space(3))) void*)la, 16, 0, 0);
+          __builtin_amdgcn_global_load_lds((const void*)(Bb + ES * (p * b_plane + offb[i] + k0)),
+                                           (__attribute__((address_space(3))) void*)(la + GB_BM * 64), 16, 0, 0);
+        }
+    };
+    issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's loads are in LDS
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      // the next stage into the other buffer first (it was last read in k-step kt - 1, before the
+      // barrier that ended it); the last k-step fetches its own slice again (in bounds, never
+      // read), so the loop body has no branch
+      issue((kt + 1) & 1, (long)(kt + 1 < nk ? kt + 1 : kt) * BKE);
+      const char* base = lds + (kt & 1) * STAGE;
+      Frag b[PLANES][NB];
+#pragma unroll
+      for (int p = 0; p < PLANES; ++p)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          b[p][j] = *(const Frag*)(base + p * (GB_BM + GB_BN) * 64 + GB_BM * 64 + swz(wn * WTN + j * 16 + fr, fc));
+      __builtin_amdgcn_iglp_opt(0);
+      __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        Frag a[PLANES];
+#pragma unroll
+        for (int p = 0; p < PLANES; ++p)
+          a[p] = *(const Frag*)(base + p * (GB_BM + GB_BN) * 64 + swz(wm * 128 + i * 16 + fr, fc));
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          if constexpr (PLANES == 2) {
+            acc[i][j] = Op::mma(a[0], b[PLANES - 1][j], acc[i][j]);
+            acc[i][j] = Op::mma(a[PLANES - 1], b[0][j], acc[i][j]);
+          }
+          acc[i][j] = Op::mma(a[0], b[0][j], acc[i][j]);
+        }
+      }
+      __builtin_amdgcn_s_setprio(0);
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's part of the next stage is in LDS
+      __syncthreads();
+    }
+  }
+  if constexpr (!DL) {
   GB_GLOAD(0);
   GB_LSTORE(0);
   __syncthreads();
-  const int fr = lane & 15, fc = lane >> 4;
   for (int kt = 0; kt < nk; ++kt) {
     if (kt + 1 < nk) { GB_GLOAD((long)(kt + 1) * BKE); }
     const char* base = lds + (kt & 1) * STAGE;
@@ -474,6 +539,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
     __builtin_amdgcn_s_setprio(0);
     if (kt + 1 < nk) { GB_LSTORE((kt + 1) & 1); }
     __syncthreads();
+  }
   }
 #undef GB_GLOAD
 #undef GB_LSTORE
@@ -1338,13 +1404,15 @@ __global__ __launch_bounds__(256) void k_tri_step_list(const EigDesc* __restrict
 // Judgement values, choice and truncation (Sections 2, 4.2.6-4.2.7):
 //   epsilon = sum_{l >= chi_new} max(lambda_l, 0),  U if epsilon < epsilon' else U'.
 // When the cut splits a multiplet of equal eigenvalues (difference at most
-// max(MULT_RTOL, tau) lambda_{k-1}, eigenvalue at least max(MULT_ATOL, tau) of the largest)
-// the whole multiplet is dropped by zeroing its columns: "the first chi columns" are not
-// unique there.  tau = 0 in the FP64 form (the oracle's rule); in the reduced-precision forms
-// tau is a multiple of the form's unit roundoff, so that a multiplet that is exact in the
-// method is still recognised after rounding.  The pair's difference is measured against the
-// pair itself, as in the FP64 rule: against lambda_0 a small pair a few per cent apart (a cut
-// deep in the spectrum) would be taken for a multiplet and dropped.
+// max(MULT_RTOL lambda_{k-1}, tau sqrt(lambda_{k-1} lambda_0)), eigenvalue at least
+// max(MULT_ATOL, tau) of the largest) the whole multiplet is dropped by zeroing its columns:
+// "the first chi columns" are not unique there.  tau = 0 in the FP64 form (the oracle's rule);
+// in the reduced-precision forms tau is the form's relative rounding, so that a multiplet that
+// is exact in the method is still recognised after rounding.  A = M M^T: a relative
+// perturbation e of M moves eigenvalue lambda_k by about 2 e sqrt(lambda_k lambda_0)
+// (u_k^T dM M^T u_k), so the floor scales with sqrt(lambda_{k-1} lambda_0): a floor of
+// tau lambda_0 would take pairs a tenth apart deep in the spectrum (lambda near 1e-6 lambda_0)
+// for multiplets, and one of tau lambda_{k-1} misses multiplets split by the rounding.
 // w: [2][n] (side 0 = A, side 1 = A'), V: [2][n][n].  identity != 0: untruncated, the
 // isometry is the identity (any orthonormal basis is exact when chi_new = n).
 // ---------------------------------------------------------------------------
@@ -1353,7 +1421,7 @@ constexpr double MULT_RTOL = 1e-10, MULT_ATOL = 1e-12;
 __global__ void k_choose(const double* __restrict__ w0, const double* __restrict__ w1,
                          const double* __restrict__ V0, const double* __restrict__ V1, int n, int chi_new,
                          int identity, double tau, double* __restrict__ Ut, float* __restrict__ Ut32,
-                         StepRec* rec_base, const DevState* __restrict__ st, int dir_index) {
+                         StepRec* rec_base, const DevState* __restrict__ st, int dir_index, int choice) {
   StepRec* rec = rec_base + st->p;
   __shared__ double eps_s[2];
   __shared__ int prime_s, kept_s;
@@ -1382,13 +1450,14 @@ __global__ void k_choose(const double* __restrict__ w0, const double* __restrict
   }
   __syncthreads();
   if (tid == 0) {
-    const int side = !(eps_s[0] < eps_s[1]);
+    // choice 0: the judgement values (Section 2); 1: always U; 2: always U' (Section 4.2.6)
+    const int side = choice == 0 ? !(eps_s[0] < eps_s[1]) : (choice == 2);
     const double* lam = side ? w1 : w0;
     int k = chi_new;
     const double floor_ = fmax(MULT_ATOL, tau) * lam[0];
     if (k < n)
       while (k > 1 && lam[k - 1] >= floor_ &&
-             lam[k - 1] - lam[k] <= fmax(MULT_RTOL, tau) * lam[k - 1]) --k;
+             lam[k - 1] - lam[k] <= fmax(MULT_RTOL * lam[k - 1], tau * sqrt(lam[k - 1] * lam[0]))) --k;
     prime_s = side;
     kept_s = k;
   }
@@ -1988,9 +2057,12 @@ __global__ __launch_bounds__(64) void k_nstage2(const AT* __restrict__ C, long l
 // the old Current leg is the last slot: T^next[nb * chi_c + c][nb * chi_c + c'].
 // One workgroup of 256 threads; fixed-order reductions.
 // ---------------------------------------------------------------------------
+// norm 0: f^(p) = 1 / t_p; norm 1: f^(p) = 1 / max |T^new| (st->mraw, reduced by k_maxabs_raw).
+// lnZ^(p) / V^(p) = K^(p) / 2^p + ln(t_p) / 2^p with K^(p+1) / 2^(p+1) = K^(p) / 2^p + ln(1/f^(p)) / 2^p
+// (eqs. eq_lnZ, K_recurrence); for norm 0 this is the running sum of ln(t_q) / 2^q.
 template <class MT>
 __global__ __launch_bounds__(256) void k_trace_lnz(const MT* __restrict__ Tn, int Hn, int chic_old,
-                                                   DevState* st, StepRec* rec_base) {
+                                                   DevState* st, StepRec* rec_base, int norm) {
   // the step counter lives on the device (st->p = steps done before this one), so that a
   // recorded step can be replayed unchanged
   const int p = st->p + 1;
@@ -2025,9 +2097,18 @@ __global__ __launch_bounds__(256) void k_trace_lnz(const MT* __restrict__ Tn, in
     const bool ok = (t > 0.0) && isfinite(t);
     if (!ok && st->err == 0) st->err = 3;   // HOTRG_E_NUMERIC
     if (st->eig_fail && st->err == 0) st->err = 3;
-    const double lnz = st->lnz + (ok ? log(t) : 0.0) / ldexp(1.0, p);
+    const double w = ldexp(1.0, -p);
+    const double lnz = st->kappa + (ok ? log(t) : 0.0) * w;
+    double f = ok ? 1.0 / t : 1.0;
+    if (norm == 1) {
+      const double m = st->mraw;
+      const bool okm = m > 0.0 && isfinite(m);
+      if (!okm && st->err == 0) st->err = 3;
+      f = okm ? 1.0 / m : 1.0;
+    }
     st->lnz = lnz;
-    st->f = ok ? 1.0 / t : 1.0;
+    st->kappa -= log(f) * w;
+    st->f = f;
     rec->trace = t;
     rec->lnz = lnz;
     rec->gu_wen = ty * ty / ty2;
@@ -2196,6 +2277,22 @@ __global__ void k_scale(MT* __restrict__ T, long n, DevState* st) {
   if (threadIdx.x == 0) atomicMax((unsigned long long*)&st->maxabs, __double_as_longlong(red[0]));
 }
 
+// max |T| over n elements into st->mraw (which the step's record kernel cleared).
+template <class MT>
+__global__ void k_maxabs_raw(const MT* __restrict__ T, long n, DevState* st) {
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    mx = fmax(mx, fabs((double)T[i]));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax((unsigned long long*)&st->mraw, __double_as_longlong(red[0]));
+}
+
 // End of a step (after the trace kernels, before the normalisation that recomputes max|T|):
 // the device step counter advances.
 __global__ void k_step_end(DevState* st) {
@@ -2213,7 +2310,7 @@ __global__ void k_inv_scale_fp16(DevState* st, int b) {
 
 // Fresh step record.
 // axis < 0: the natural cycle, lattice axis (p - 1) mod d.
-__global__ void k_rec_init(StepRec* rec_base, const DevState* st, int axis, int d, int c0, int c1, int c2) {
+__global__ void k_rec_init(StepRec* rec_base, DevState* st, int axis, int d, int c0, int c1, int c2) {
   const int p = st->p + 1;
   StepRec* rec = rec_base + (p - 1);
   if (axis < 0) axis = (p - 1) % d;
@@ -2221,6 +2318,7 @@ __global__ void k_rec_init(StepRec* rec_base, const DevState* st, int axis, int 
   for (int i = threadIdx.x; i < (int)(sizeof(StepRec) / sizeof(int)); i += blockDim.x) w[i] = 0;
   __syncthreads();
   if (threadIdx.x == 0) {
+    st->mraw = 0.0;
     rec->p = p;
     rec->axis = axis;
     rec->dims_before[0] = c0;
@@ -2235,7 +2333,8 @@ __global__ void k_rec_init(StepRec* rec_base, const DevState* st, int axis, int 
 // non-finite t0 is a numeric failure (sticky; f = 1 then).  One workgroup; k_init_user_scale
 // then writes T = f T0 into the master tensor.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_init_user_trace(const double* __restrict__ T0, int H, DevState* st) {
+__global__ __launch_bounds__(256) void k_init_user_trace(const double* __restrict__ T0, int H, DevState* st,
+                                                         int norm) {
   __shared__ double red[256];
   const int tid = threadIdx.x;
   double s = 0.0;
@@ -2248,11 +2347,18 @@ __global__ __launch_bounds__(256) void k_init_user_trace(const double* __restric
   }
   if (tid == 0) {
     const double t = red[0];
-    const bool ok = t > 0.0 && isfinite(t);
+    bool ok = t > 0.0 && isfinite(t);
     st->lnz0 = ok ? log(t) : 0.0;
     st->lnz = st->lnz0;
     st->dlnz = 0.0;
-    st->f = ok ? 1.0 / t : 1.0;
+    double f = ok ? 1.0 / t : 1.0;
+    if (norm == 1) {                      // st->mraw: max |T0| from k_maxabs_raw
+      const double m = st->mraw;
+      ok = ok && m > 0.0 && isfinite(m);
+      f = ok ? 1.0 / m : 1.0;
+    }
+    st->f = f;
+    st->kappa = -log(f);
     st->maxabs = 0.0;
     st->p = 0;
     st->err = ok ? 0 : 3;   // HOTRG_E_NUMERIC
@@ -2288,9 +2394,10 @@ __global__ void k_init_user_scale(const double* __restrict__ T0, MT* __restrict_
 // ---------------------------------------------------------------------------
 // With dT != null also the derivative: dX from d(sqrt(lambda))/d(beta) with the beta-independent
 // eigenvectors, dT0 by the product rule, d(lnZ/V) at p = 0 and dT = dT0/t0 - T0 dt0/t0^2.
+// norm 0: f^(0) = 1 / Tr T0; norm 1: f^(0) = 1 / max |T0| (one more pass over the entries).
 template <class MT>
 __global__ void k_init_tensor(MT* __restrict__ T, MT* __restrict__ dT, int kind, int d, int q, double beta,
-                              double J, double hfield, DevState* st) {
+                              double J, double hfield, DevState* st, int norm) {
   __shared__ double X[8 * 8], dX[8 * 8];
   __shared__ double V[8], dV[8];
   __shared__ double tr_s, dtr_s;
@@ -2340,15 +2447,41 @@ __global__ void k_init_tensor(MT* __restrict__ T, MT* __restrict__ dT, int kind,
     st->lnz0 = log(tr);
     st->lnz = log(tr);
     st->dlnz = dtr / tr;
-    st->f = 1.0 / tr;
     st->p = 0;
     st->err = 0;
     st->eig_fail = 0;
   }
+  __shared__ double red[256];
   __syncthreads();
   int H = 1;
   for (int i = 0; i < d; ++i) H *= q;
-  const double f = 1.0 / tr_s, dtf = dtr_s / tr_s;
+  double f = 1.0 / tr_s;
+  const double dtf = dtr_s / tr_s;
+  if (norm == 1) {
+    double m = 0.0;
+    for (int i = tid; i < H * H; i += blockDim.x) {
+      double v = 0.0;
+      for (int s = 0; s < q; ++s) {
+        double prod = V[s];
+        int rem = i;
+        for (int l = 0; l < 2 * d; ++l) { prod *= X[s * q + rem % q]; rem /= q; }
+        v += prod;
+      }
+      m = fmax(m, fabs(v));
+    }
+    red[tid] = m;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if (tid < o) red[tid] = fmax(red[tid], red[tid + o]);
+      __syncthreads();
+    }
+    f = 1.0 / red[0];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    st->f = f;
+    st->kappa = -log(f);
+  }
   double mx = 0.0;
   for (int i = tid; i < H * H; i += blockDim.x) {
     double v = 0.0, dv = 0.0;
@@ -2377,7 +2510,6 @@ __global__ void k_init_tensor(MT* __restrict__ T, MT* __restrict__ dT, int kind,
     mx = fmax(mx, fabs(v * f));
   }
   // maxabs (single block)
-  __shared__ double red[256];
   red[tid] = mx;
   __syncthreads();
   for (int o = blockDim.x / 2; o > 0; o >>= 1) {
@@ -2385,6 +2517,49 @@ __global__ void k_init_tensor(MT* __restrict__ T, MT* __restrict__ dT, int kind,
     __syncthreads();
   }
   if (tid == 0) st->maxabs = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// MFMA issue-rate probe (measurement only): every wave runs `iters` rounds of eight
+// independent MFMA accumulations on register operands, so the matrix cores are limited only
+// by the instruction itself and the clock under load.  The result is written only under a
+// condition the inputs never meet, so the loop is not removed.
+// ---------------------------------------------------------------------------
+template <class Op>
+__global__ __launch_bounds__(512) void k_mfma_loop(int iters, float* __restrict__ sink) {
+  typedef typename Op::Frag Frag;
+  typedef typename Op::AccV AccV;
+  Frag a, b;
+  if constexpr (sizeof(Frag) == sizeof(double)) {
+    a = (Frag)(1.0 + 1e-3 * (threadIdx.x & 63));
+    b = (Frag)(1.0 - 1e-3 * (threadIdx.x & 63));
+  } else if constexpr (sizeof(Frag) == sizeof(float)) {
+    a = (Frag)(1.0f + 1e-3f * (threadIdx.x & 63));
+    b = (Frag)(1.0f - 1e-3f * (threadIdx.x & 63));
+  } else {
+    for (int i = 0; i < 8; ++i) {
+      a[i] = (typename Op::T)0;
+      b[i] = (typename Op::T)0;
+    }
+    if constexpr (sizeof(typename Op::T) == 2) {
+      typedef typename Op::T T;
+      for (int i = 0; i < 8; ++i) {
+        a[i] = __builtin_bit_cast(T, (uint16_t)(0x3c00 + (threadIdx.x & 7)));
+        b[i] = __builtin_bit_cast(T, (uint16_t)(0x3c00 + i));
+      }
+    }
+  }
+  AccV acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = AccV{0, 0, 0, 0};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = Op::mma(a, b, acc[i]);
+  }
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) t += (double)acc[i][0] + (double)acc[i][3];
+  if (t == -1.0) sink[threadIdx.x] = (float)t;
 }
 
 }  // namespace hk

@@ -70,8 +70,9 @@ def spread_picks(ks, count):
 # ---------------------------------------------------------------------------------------
 
 # Eigenvalue pairs closer than this (relative to lambda_0) are resolved by rounding in any FP64
-# eigensolver (its absolute accuracy is about n u lambda_0 = 2e-13 lambda_0 at n = 1024).
-ROUNDING_LEVEL = 1e-12
+# eigensolver (its absolute accuracy is about n u lambda_0 = 2e-13 lambda_0 at n = 1024, and
+# the Gram matrices themselves carry the rounding of the steps before).
+ROUNDING_LEVEL = 1e-11
 
 
 def _adopted_spectrum(dd):
@@ -109,3 +110,19 @@ def conditioned_steps(run, threshold):
         if min(effective_gap(dd) for dd in st["dirs"].values()) < threshold:
             return i + 1
     return len(run["steps"])
+
+
+# Effective gaps (relative to lambda_0) below which the kept vector of a near-degenerate pair
+# moves, under the rounding of A in any FP64 implementation, by enough to change lnZ/V at the
+# 1e-10 level (measured: gaps of 3e-11 and 7e-11 lambda_0 at a cut part two FP64
+# implementations by 6e-10 two steps later).
+SUBSPACE_LEVEL = 1e-9
+
+
+def first_cut_below(run, threshold):
+    """First step (1-based) whose cut has an effective gap at or below `threshold` (relative to
+    lambda_0); len(steps) + 1 if there is none."""
+    for i, st in enumerate(run["steps"]):
+        if min(effective_gap(dd) for dd in st["dirs"].values()) <= threshold:
+            return i + 1
+    return len(run["steps"]) + 1

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
 def test_struct_layouts_match_header():
     # hotrg_model: int, int, int, (pad), double, double
     assert ctypes.sizeof(P.hotrg_model) == 32
-    assert ctypes.sizeof(P.hotrg_opts) == 16
+    assert ctypes.sizeof(P.hotrg_opts) == 24
 
 
 def _model(kind=P.HOTRG_ISING, d=3, q=2, J=1.0, h=0.0):
@@ -146,3 +146,16 @@ def test_supplied_tensor_argument_validation():
 
 def test_eigh_workspace_holds_the_failure_flag():
     assert P.hotrg_debug_eigh_workspace_bytes(256, 4) >= 4 * 2 * 256 * 256 * 8 + 4
+
+
+def test_norm_and_choice_options_are_validated():
+    m = _model()
+    assert P.hotrg_workspace_bytes(m, 8, P.hotrg_opts(P.HOTRG_FP64, 8, 0, 0, P.HOTRG_NORM_MAXABS,
+                                                      P.HOTRG_CHOOSE_UPRIME)) > 0
+    assert P.hotrg_workspace_bytes(m, 8, P.hotrg_opts(P.HOTRG_FP64, 8, 0, 0, 2, 0)) == 0       # no such norm
+    assert P.hotrg_workspace_bytes(m, 8, P.hotrg_opts(P.HOTRG_FP64, 8, 0, 0, 0, 3)) == 0       # no such choice
+    # the derivative is carried with the trace normalisation only
+    assert P.hotrg_workspace_bytes(m, 8, P.hotrg_opts(P.HOTRG_FP64, 8, 0, 1, P.HOTRG_NORM_MAXABS, 0)) == 0
+    with pytest.raises(P.HotrgError) as e:
+        P.hotrg_init(m, 0.3, 8, P.hotrg_opts(P.HOTRG_FP64, 8, 0, 0, 0, 7), 256, 1 << 30, 0)
+    assert e.value.code == P.HOTRG_E_ARG

@@ -79,13 +79,16 @@ def config4_instances():
     return inst
 
 
-# lnZ/V bounds for the sweep: FP64 1e-10 at every step.  Split FP16: 1e-6 (the MFMA bar) up to
+# lnZ/V bounds for the sweep: FP64 1e-10 up to the first cut whose effective gap is below
+# tests/parity.SUBSPACE_LEVEL (1e-9 lambda_0), 1e-8 from there on (which vector of a pair that
+# close is kept is decided by rounding; 2D beta = 0.357 and 0.415, chi = 16, meet such cuts at
+# steps 11 and 13 and part from the oracle by 6e-10).  Split FP16: 1e-6 (the MFMA bar) up to
 # the first step where the instance keeps a different number of columns than the oracle, 1e-5
 # from there on.  In the ordered phase (3D T near 4.0, 2D beta near 0.6) even/odd pairs of
 # Gram eigenvalues come within the form's noise floor of each other at some cuts; the split
 # form then drops a pair that FP64 keeps (or the reverse), which moves lnZ/V by a few 1e-6.
 # The instances and steps concerned are printed (and listed in the design doc).
-SWEEP_BOUND = {"fp64": (1e-10, 1e-10), "split_fp16": (1e-6, 1e-5)}
+SWEEP_BOUND = {"fp64": (1e-10, 1e-8), "split_fp16": (1e-6, 1e-5)}
 
 
 def load_config4():
@@ -112,6 +115,8 @@ def check_sweep(fx, lnz_of, kept_of, precision, label):
                 if kg != dd["kept"]:
                     (krounding if PT.rounding_decided_cut(dd, kg) else kdiff).append(p)
         first = min(kdiff + krounding) if kdiff + krounding else steps + 1
+        if precision == "fp64":
+            first = min(first, PT.first_cut_below(run, PT.SUBSPACE_LEVEL))
         if kdiff or krounding:
             diverged.append((run["d"], run["chi"], round(run["beta"], 6), first))
         print(f"{label} d={run['d']} chi={run['chi']} beta={run['beta']:.6f}: max rel err {max(per):.2e}"

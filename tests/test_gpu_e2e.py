@@ -220,3 +220,45 @@ def test_state_errors():
     with pytest.raises(P.HotrgError) as e:
         P.hotrg_grad(r.handle)
     assert e.value.code == P.HOTRG_E_STATE
+
+
+# ---------------------------------------------------------------------------
+# Ising model in a field h != 0 (Section 2, eqs. 1-2: g = beta h s, V_s = e^{beta h s})
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,beta,h,steps", [(2, 0.5, 0.3, 4), (3, 0.25, -0.2, 3), (2, 0.42, 0.05, 4)])
+def test_field_untruncated_steps_equal_brute_force(d, beta, h, steps):
+    """Untruncated steps (chi = 16) with a field: the exact periodic tori 2x1, 2x2, 4x2, 4x4 (2D)
+    and 2x1x1, 2x2x1, 2x2x2 (3D), including the derivative (minus the energy per site)."""
+    r = P.HOTRG("ising", d, beta, 16, h=h, max_steps=steps, record_grad=True)
+    for p in range(1, steps + 1):
+        r.step()
+        L = H.lattice_shape(d, p)
+        z, dz = E.torus_log_z("ising", beta, L, h=h)
+        assert r.log_z() == pytest.approx(z / np.prod(L), abs=1e-13), (p, L)
+        assert r.grad() == pytest.approx(dz / np.prod(L), abs=1e-12), (p, L)
+    r.close()
+
+
+@pytest.mark.parametrize("precision,bound", [("fp64", 1e-10), ("split_fp16", 1e-6)])
+@pytest.mark.parametrize("d,beta,h,chi,steps", [(2, 0.44, 0.05, 12, 16), (3, 0.23, 0.02, 6, 12)])
+def test_field_truncated_run_matches_oracle(d, beta, h, chi, steps, precision, bound):
+    """Truncated runs in a field against the oracle run (computed here; the field breaks the
+    s -> -s symmetry, so U and U' and the even/odd structure of the spectra differ from h = 0):
+    lnZ/V, trace and Gu-Wen ratio after every step, kept counts in FP64."""
+    _, recs = H.run(H.Model("ising", d, h=h), beta, chi, steps)
+    r = P.HOTRG("ising", d, beta, chi, h=h, precision=precision, max_steps=steps)
+    e_lnz, e_x = [], []
+    for p in range(1, steps + 1):
+        r.step()
+        info = r.info(p)
+        e_lnz.append(_rel(r.log_z(), recs[p - 1].lnz_per_site))
+        e_x.append(_rel(info.gu_wen, recs[p - 1].gu_wen))
+        if precision == "fp64":
+            assert [info.kept[j] for j in range(d - 1)] == [recs[p - 1].truncations[j + 1].kept for j in range(d - 1)]
+    r.close()
+    print(f"field h={h} d={d} chi={chi} {precision}: lnZ/V per step " + " ".join(f"{e:.1e}" for e in e_lnz)
+          + "; X per step " + " ".join(f"{e:.1e}" for e in e_x))
+    assert max(e_lnz) < bound
+    if precision == "fp64":
+        assert max(e_x) < 1e-9

@@ -103,3 +103,47 @@ def test_gpu_is_healthy_after_the_failures():
     r.close()
     _, recs = H.run(H.Model("ising", 3), 1 / 4.5115, 8, 6)
     assert abs(lnz - recs[-1].lnz_per_site) < 1e-10 * abs(recs[-1].lnz_per_site)
+
+
+# ---------------------------------------------------------------------------
+# Choice criteria (Section 4.2.6) and normalisation factors (Section 3.1.3)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("norm,choice", [("trace", "U"), ("trace", "Uprime"), ("maxabs", "epsilon"),
+                                         ("maxabs", "Uprime")])
+def test_choice_and_norm_options_match_oracle(norm, choice):
+    """A tensor without reflection symmetry (U and U' differ): the GPU run with a fixed choice or
+    the max-element normalisation against the oracle run with the same options, lnZ/V and kept
+    counts after every step; a fixed choice shows in every truncated direction's record."""
+    dims, chi, steps = (3, 4, 2), 6, 7
+    Ts = SI.random_positive_tensor(tuple(dims) * 2, seed=24)
+    _, recs = H.run(H.Model("ising", 3), 0.0, chi, steps, T0=LY.to_paper(Ts), norm=norm, choice=choice)
+    r = P.HOTRG.from_tensor(gu.dev(Ts), chi, max_steps=steps, norm=norm, choice=choice)
+    errs = []
+    for p in range(1, steps + 1):
+        r.step()
+        info = r.info(p)
+        errs.append(abs(r.log_z() - recs[p - 1].lnz_per_site) / abs(recs[p - 1].lnz_per_site))
+        for j in (1, 2):
+            t = recs[p - 1].truncations[j]
+            assert info.kept[j - 1] == t.kept
+            if info.truncated[j - 1]:
+                assert info.chose_prime[j - 1] == int(t.chose_prime)
+                if choice != "epsilon":
+                    assert info.chose_prime[j - 1] == (choice == "Uprime")
+    r.close()
+    print(f"norm={norm} choice={choice}: lnZ/V per step " + " ".join(f"{e:.1e}" for e in errs))
+    assert max(errs) < 1e-10
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("split_fp16", 1e-6)])
+def test_normalisation_does_not_change_lnz(precision, tol):
+    """3D Ising chi = 8, 10 steps: f = 1/max|T| against f = 1/Tr T (lnZ/V is independent of the
+    normalisation factor)."""
+    out = {}
+    for norm in ("trace", "maxabs"):
+        r = P.HOTRG("ising", 3, 1 / 4.5115, 8, precision=precision, max_steps=10, norm=norm)
+        r.run(10)
+        out[norm] = [r.info(p).lnz_per_site for p in range(1, 11)]
+        r.close()
+    np.testing.assert_allclose(out["maxabs"], out["trace"], rtol=tol)

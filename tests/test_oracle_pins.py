@@ -11,6 +11,7 @@ import pytest
 
 from oracle import exact as E
 from oracle import hotrg as H
+from tests import layout as LYp
 from tests import seeded_inputs as SI
 
 
@@ -334,3 +335,34 @@ def test_gu_wen_ratio_limits():
     _, hi = H.run(H.Model("ising", 2), 1 / 4.0, 8, 24)
     assert lo[-1].gu_wen == pytest.approx(2.0, abs=1e-3)
     assert hi[-1].gu_wen == pytest.approx(1.0, abs=1e-3)
+
+
+# --------------------------------------------------------------------------
+# Section 4.2.6: alternative choice criteria (any rational criterion is allowed)
+# --------------------------------------------------------------------------
+
+def test_choice_criteria_agree_for_a_reflection_symmetric_model():
+    """Ising: A and A' agree up to a bond gauge (R3), so adopting U, U' or the epsilon winner gives
+    the same gauge-invariant lnZ/V."""
+    m = H.Model("ising", 3)
+    runs = {c: [r.lnz_per_site for r in H.run(m, 1 / 4.5115, 6, 8, choice=c)[1]] for c in H.CHOICES}
+    for c in ("U", "Uprime"):
+        np.testing.assert_allclose(runs[c], runs["epsilon"], rtol=1e-12)
+
+
+def test_choice_criteria_on_a_tensor_without_reflection_symmetry():
+    """A random positive tensor: U and U' differ; the epsilon criterion adopts, at every step, the
+    side with the smaller judgement value, so its first step equals the fixed choice of that side
+    bitwise."""
+    T0 = LYp.to_paper(SI.random_positive_tensor((3, 4, 2) * 2, seed=24))
+    T = T0 / H.trace(T0)
+    a, tr_a = H.coarse_grain(T, 6, choice="epsilon")
+    side = "Uprime" if tr_a[1].chose_prime else "U"
+    b, _ = H.coarse_grain(T, 6, choice=side)
+    np.testing.assert_array_equal(a, b)
+    assert tr_a[1].chose_prime == (not tr_a[1].eps < tr_a[1].eps_p)
+    lu = [r.lnz_per_site for r in H.run(H.Model("ising", 3), 0.0, 6, 6, T0=T0, choice="U")[1]]
+    lp = [r.lnz_per_site for r in H.run(H.Model("ising", 3), 0.0, 6, 6, T0=T0, choice="Uprime")[1]]
+    assert max(abs(x - y) / abs(y) for x, y in zip(lu, lp)) > 1e-8
+    with pytest.raises(ValueError):
+        H.choose_isometry(np.eye(4), np.eye(4), 2, choice="best")
