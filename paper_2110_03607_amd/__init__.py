@@ -132,11 +132,20 @@ def exported_symbols():
 
 
 def lib():
-    """Load libhotrg.so (raises if it has not been built)."""
+    """Load libhotrg.so (raises if it has not been built).
+
+    PyTorch is imported first when it is installed: PyTorch ships its own HIP runtime, and the
+    library must bind to the same one as the tensors and streams it is handed.  Loaded before
+    PyTorch, the library would pull in the system HIP runtime and the process would hold two,
+    each rejecting the other's device pointers and streams."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2110_03607_amd.build.build()")
+        try:
+            import torch  # noqa: F401  (one HIP runtime per process, see above)
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)

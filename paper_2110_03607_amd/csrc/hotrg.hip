@@ -430,11 +430,11 @@ template <> struct GemmCfg<F_FP16> { static constexpr int BK = 64; };
 template <> struct GemmCfg<F_SPLIT_BF16> { static constexpr int BK = 64; };
 template <> struct GemmCfg<F_SPLIT_FP16> { static constexpr int BK = 64; };
 
-// Operand tiles of the large-tile GEMM loaded straight into LDS (k_gemm_big, DL).
-#ifndef HOTRG_GEMM_DIRECT_LOADS
-#define HOTRG_GEMM_DIRECT_LOADS 0
-#endif
-constexpr bool GEMM_DIRECT_LOADS = HOTRG_GEMM_DIRECT_LOADS != 0;
+// Operand tiles of the large-tile GEMM loaded straight into LDS (k_gemm_big, DL) for the two-plane
+// forms and FP32, where it was measured faster (split FP16 bottleneck 4.76 -> 4.54 ms per launch,
+// FP32 16.3 -> 15.7 ms at chi = 16); the single-plane 16-bit forms keep the register staging
+// (2.78 ms against 3.01 ms with direct loads).
+template <int F> constexpr bool gemm_direct_loads() { return FormInfo<F>::planes == 2 || F == F_FP32; }
 
 template <int F>
 void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, long bplane, void* C, long ldc,
@@ -449,11 +449,11 @@ void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, 
       const int mt = (int)(Mp / GB_BM), nt = (int)(Np / GB_BN);
       constexpr int WAVES = 8;   // 2 waves per SIMD: one wave's LDS/barrier phase hides under the other's MFMAs
       if (fuse)
-        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, true, GEMM_DIRECT_LOADS>), dim3((unsigned)(mt * nt)),
+        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, true, gemm_direct_loads<F>()>), dim3((unsigned)(mt * nt)),
                            dim3(64 * WAVES), 0, s, (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B,
                            ldb, bplane, (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, *fuse);
       else
-        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, false, GEMM_DIRECT_LOADS>), dim3((unsigned)(mt * nt)),
+        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, false, gemm_direct_loads<F>()>), dim3((unsigned)(mt * nt)),
                            dim3(64 * WAVES), 0, s, (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B,
                            ldb, bplane, (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, FuseArgs{});
       return;
@@ -1527,7 +1527,10 @@ int hotrg_debug_contract(int d, const int* dims, const int* kdims, int precision
   for (int i = 0; i < d; ++i) H *= dims[i];
   for (int j = 0; j < d - 1; ++j) Hn *= kdims[j];
   const long ut_stride = P.need.Ut / 8;
-  HIPCHK(h, hipMemsetAsync(h->ws, 0, P.off_T, h->s));
+  {
+    const hipError_t e = hipMemsetAsync(h->ws, 0, P.off_T, h->s);
+    if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, std::string("hotrg_debug_contract: ") + hipGetErrorString(e));
+  }
   for (int j = 0; j < d - 1; ++j) {
     const long nu = (long)dims[j + 1] * dims[j + 1] * kdims[j];
     double* U = h->at<double>(P.off_Ut) + j * ut_stride;
@@ -1544,15 +1547,16 @@ int hotrg_debug_contract(int d, const int* dims, const int* kdims, int precision
     hipLaunchKernelGGL(k_f64_to_mt_f32, dim3(grid_for(H * H)), dim3(256), 0, h->s, T_dev, (float*)T, H * H);
   }
   int rc = enqueue_contract(h, T, Tn, h->ld, kdims);
-  if (rc) return rc;
+  if (rc) return fail(nullptr, rc, h->err);   // the handle is local: its message goes to the static one
   if (precision == HOTRG_FP64)
     hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (const double*)Tn, Tnext_dev,
                        Hn * Hn);
   else
     hipLaunchKernelGGL(k_mt_f32_to_f64, dim3(grid_for(Hn * Hn)), dim3(256), 0, h->s, (const float*)Tn, Tnext_dev,
                        Hn * Hn);
-  HIPCHK(h, hipGetLastError());
-  HIPCHK(h, hipStreamSynchronize(h->s));
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(h->s);
+  if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, std::string("hotrg_debug_contract: ") + hipGetErrorString(e));
   return HOTRG_OK;
 }
 
@@ -1572,8 +1576,9 @@ int hotrg_debug_gram(int d, const int* dims, int dir, int side, const double* T_
   h->ld.d = d;
   for (int i = 0; i < d; ++i) h->ld.chi[i] = dims[i];
   int rc = enqueue_gram(h, T_dev, true, h->ld, dir, side, A_dev);
-  if (rc) return rc;
-  HIPCHK(h, hipStreamSynchronize(h->s));
+  if (rc) return fail(nullptr, rc, h->err);
+  const hipError_t e = hipStreamSynchronize(h->s);
+  if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, std::string("hotrg_debug_gram: ") + hipGetErrorString(e));
   return HOTRG_OK;
 }
 

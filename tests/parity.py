@@ -113,10 +113,13 @@ def conditioned_steps(run, threshold):
 
 
 # Effective gaps (relative to lambda_0) below which the kept vector of a near-degenerate pair
-# moves, under the rounding of A in any FP64 implementation, by enough to change lnZ/V at the
-# 1e-10 level (measured: gaps of 3e-11 and 7e-11 lambda_0 at a cut part two FP64
-# implementations by 6e-10 two steps later).
-SUBSPACE_LEVEL = 1e-9
+# moves, under the rounding of A, by enough to change lnZ/V at the bound of the form: the
+# subspace rotates by about (perturbation of A) / gap.  FP64: cuts with gaps of 3e-11 to 5e-9
+# lambda_0 part two FP64 implementations by 4e-10 to 6e-10 within a few steps (2D Ising chi =
+# 16 at beta = 0.357, 0.415, 0.434), so 1e-7 leaves a margin.  Split FP16 (A perturbed at about
+# 1e-7 relative): after cuts with gaps of 7e-6 the 3D chi = 12 run at T = 4.19 parts from the
+# oracle by 1.1e-6 at step 13.
+SUBSPACE_LEVEL = {"fp64": 1e-7, "split_fp16": 1e-5}
 
 
 def first_cut_below(run, threshold):

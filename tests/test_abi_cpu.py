@@ -159,3 +159,15 @@ def test_norm_and_choice_options_are_validated():
     with pytest.raises(P.HotrgError) as e:
         P.hotrg_init(m, 0.3, 8, P.hotrg_opts(P.HOTRG_FP64, 8, 0, 0, 0, 7), 256, 1 << 30, 0)
     assert e.value.code == P.HOTRG_E_ARG
+
+
+def test_one_hip_runtime_per_process():
+    """Loading the library before PyTorch must not map a second HIP runtime next to PyTorch's
+    (device pointers and streams of one are invalid in the other)."""
+    import subprocess
+    import sys
+    code = ("import paper_2110_03607_amd as P; P.lib(); import torch; "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'amdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

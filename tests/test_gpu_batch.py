@@ -79,15 +79,14 @@ def config4_instances():
     return inst
 
 
-# lnZ/V bounds for the sweep: FP64 1e-10 up to the first cut whose effective gap is below
-# tests/parity.SUBSPACE_LEVEL (1e-9 lambda_0), 1e-8 from there on (which vector of a pair that
-# close is kept is decided by rounding; 2D beta = 0.357 and 0.415, chi = 16, meet such cuts at
-# steps 11 and 13 and part from the oracle by 6e-10).  Split FP16: 1e-6 (the MFMA bar) up to
-# the first step where the instance keeps a different number of columns than the oracle, 1e-5
-# from there on.  In the ordered phase (3D T near 4.0, 2D beta near 0.6) even/odd pairs of
-# Gram eigenvalues come within the form's noise floor of each other at some cuts; the split
-# form then drops a pair that FP64 keeps (or the reverse), which moves lnZ/V by a few 1e-6.
-# The instances and steps concerned are printed (and listed in the design doc).
+# lnZ/V bounds for the sweep, (tight, loose): the tight bound holds up to the first step where
+# the instance keeps a different number of columns than the oracle, or meets a cut whose
+# effective gap is below tests/parity.SUBSPACE_LEVEL of the form (there the kept subspace is set
+# by the rounding of A: any two implementations of the form part); the loose one from there on.
+# FP64: 1e-10, then 1e-8.  Split FP16: 1e-6 (the MFMA bar), then 1e-5.  In the ordered phase (3D
+# T near 4.0, 2D beta near 0.6) even/odd pairs of Gram eigenvalues come within the form's noise
+# of each other at some cuts; the split form then drops a pair that FP64 keeps (or the
+# reverse).  The instances and steps concerned are printed (and listed in the design doc).
 SWEEP_BOUND = {"fp64": (1e-10, 1e-8), "split_fp16": (1e-6, 1e-5)}
 
 
@@ -115,8 +114,7 @@ def check_sweep(fx, lnz_of, kept_of, precision, label):
                 if kg != dd["kept"]:
                     (krounding if PT.rounding_decided_cut(dd, kg) else kdiff).append(p)
         first = min(kdiff + krounding) if kdiff + krounding else steps + 1
-        if precision == "fp64":
-            first = min(first, PT.first_cut_below(run, PT.SUBSPACE_LEVEL))
+        first = min(first, PT.first_cut_below(run, PT.SUBSPACE_LEVEL[precision]))
         if kdiff or krounding:
             diverged.append((run["d"], run["chi"], round(run["beta"], 6), first))
         print(f"{label} d={run['d']} chi={run['chi']} beta={run['beta']:.6f}: max rel err {max(per):.2e}"

@@ -95,5 +95,5 @@ def test_rounding_decided_cut_and_gaps():
 def test_first_cut_below():
     run = {"steps": [{"dirs": {"1": _dir([1.0, 0.5, 0.1], 2, 2)}},
                      {"dirs": {"1": _dir([1.0, 2e-5, 2e-5 - 1e-14], 2, 2)}}]}
-    assert PT.first_cut_below(run, PT.SUBSPACE_LEVEL) == 2
-    assert PT.first_cut_below({"steps": run["steps"][:1]}, PT.SUBSPACE_LEVEL) == 2
+    assert PT.first_cut_below(run, PT.SUBSPACE_LEVEL["fp64"]) == 2
+    assert PT.first_cut_below({"steps": run["steps"][:1]}, PT.SUBSPACE_LEVEL["fp64"]) == 2
