@@ -434,7 +434,7 @@ template <> struct GemmCfg<F_SPLIT_FP16> { static constexpr int BK = 64; };
 // forms and FP32, where it was measured faster (split FP16 bottleneck 4.76 -> 4.54 ms per launch,
 // FP32 16.3 -> 15.7 ms at chi = 16); the single-plane 16-bit forms keep the register staging
 // (2.78 ms against 3.01 ms with direct loads).
-template <int F> constexpr bool gemm_direct_loads() { return FormInfo<F>::planes == 2 || F == F_FP32; }
+template <int F> constexpr int gemm_sched() { return (FormInfo<F>::planes == 2 || F == F_FP32) ? 1 : 0; }
 
 template <int F>
 void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, long bplane, void* C, long ldc,
@@ -449,11 +449,11 @@ void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, 
       const int mt = (int)(Mp / GB_BM), nt = (int)(Np / GB_BN);
       constexpr int WAVES = 8;   // 2 waves per SIMD: one wave's LDS/barrier phase hides under the other's MFMAs
       if (fuse)
-        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, true, gemm_direct_loads<F>()>), dim3((unsigned)(mt * nt)),
+        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, true, gemm_sched<F>()>), dim3((unsigned)(mt * nt)),
                            dim3(64 * WAVES), 0, s, (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B,
                            ldb, bplane, (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, *fuse);
       else
-        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, false, gemm_direct_loads<F>()>), dim3((unsigned)(mt * nt)),
+        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, false, gemm_sched<F>()>), dim3((unsigned)(mt * nt)),
                            dim3(64 * WAVES), 0, s, (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B,
                            ldb, bplane, (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, FuseArgs{});
       return;

@@ -389,11 +389,12 @@ struct FuseArgs {
   int chic, g0;
 };
 
-// DL: the operand tiles go from global memory straight into LDS (global_load_lds_dwordx4: each
-// lane's 16 bytes land at the wave's LDS base + 16 lane), with no staging registers and no LDS
-// store instructions.  Lane l of a load fetches the global chunk that belongs at its LDS slot
+// SCHED 0: register staging, one barrier per k-step.
+// SCHED 1 (DL): the operand tiles go from global memory straight into LDS (global_load_lds_dwordx4:
+// each lane's 16 bytes land at the wave's LDS base + 16 lane), with no staging registers and no
+// LDS store instructions.  Lane l of a load fetches the global chunk that belongs at its LDS slot
 // (the XOR swizzle is applied to the global address instead of the LDS address).
-template <class Op, int PLANES, int WAVES, bool FUSE, bool DL = false>
+template <class Op, int PLANES, int WAVES, bool FUSE, int SCHED = 0>
 __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
     const typename Op::T* __restrict__ A, long lda, long a_plane,
     const typename Op::T* __restrict__ B, long ldb, long b_plane,
@@ -444,24 +445,23 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
 
   const int nk = Kp / BKE;
   const int fr = lane & 15, fc = lane >> 4;
+  constexpr bool DL = SCHED == 1;
   if constexpr (DL) {
-    // global offsets (elements) of this lane's chunk in each of its CH slots, k excluded
-    long offa[CH], offb[CH];
-#pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int q = i * THREADS + wave * 64 + lane, r = q >> 2, c = (q & 3) ^ ((r >> 1) & 3);
-      offa[i] = (m0 + r) * lda + c * CE;
-      offb[i] = (n0 + r) * ldb + c * CE;
-    }
+    // slot i of a lane is row i THREADS / 4 + 16 wave + lane / 4, chunk (lane & 3) ^ ((row >> 1) & 3)
+    // (the same for every i): a wave-uniform base per slot plus one 32-bit byte offset per lane
+    const int r0 = wave * 16 + (lane >> 2), c0 = (lane & 3) ^ ((r0 >> 1) & 3);
+    const unsigned voa = (unsigned)(ES * (r0 * lda + c0 * CE)), vob = (unsigned)(ES * (r0 * ldb + c0 * CE));
     auto issue = [&](int stage, long k0) {
 #pragma unroll
       for (int p = 0; p < PLANES; ++p)
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
           char* la = lds + stage * STAGE + p * (GB_BM + GB_BN) * 64 + (i * THREADS + wave * 64) * 16;
-          __builtin_amdgcn_global_load_lds((const void*)(Ab + ES * (p * a_plane + offa[i] + k0)),
-                                           (__attribute__((address_space(3))) void*)la, 16, 0, 0);
-          __builtin_amdgcn_global_load_lds((const void*)(Bb + ES * (p * b_plane + offb[i] + k0)),
+          const char* ga = Ab + ES * (p * a_plane + (m0 + (long)i * (THREADS / 4)) * lda + k0);   // wave-uniform
+          const char* gb = Bb + ES * (p * b_plane + (n0 + (long)i * (THREADS / 4)) * ldb + k0);
+          __builtin_amdgcn_global_load_lds((const void*)(ga + voa), (__attribute__((address_space(3))) void*)la, 16,
+                                           0, 0);
+          __builtin_amdgcn_global_load_lds((const void*)(gb + vob),
                                            (__attribute__((address_space(3))) void*)(la + GB_BM * 64), 16, 0, 0);
         }
     };
@@ -502,7 +502,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
       __syncthreads();
     }
   }
-  if constexpr (!DL) {
+  if constexpr (SCHED == 0) {
   GB_GLOAD(0);
   GB_LSTORE(0);
   __syncthreads();
