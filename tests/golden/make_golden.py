@@ -28,6 +28,17 @@ from oracle import hotrg as H  # noqa: E402
 from oracle import tangent as TG  # noqa: E402
 from tests import seeded_inputs as SI  # noqa: E402
 
+
+def dump_json(doc, path):
+    """Write `doc` to `path` through a temporary file and a rename, so that a reader never sees
+    a partly written fixture while a long run is still adding to it."""
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(doc, f, indent=1)
+    os.replace(tmp, path)
+
+
+
 N_SPEC = 24
 
 
@@ -171,16 +182,14 @@ def run_grad_config5(beta, steps):
         doc["steps_done"] = p
         doc["wall_seconds"] = now - t0
         last[0] = now
-        with open(grad_config5_path(beta), "w") as f:
-            json.dump(doc, f, indent=1)
+        dump_json(doc, grad_config5_path(beta))
         print(f"  grad_config5 beta={beta:.2f} step {p} lnz/V={lnz:.15f} dlnz/dbeta={dlnz:.15f} "
               f"({doc['step_seconds'][-1]:.0f}s)", flush=True)
 
     lnz0, dlnz0, _ = TG.run_with_tangent(H.Model(cfg["kind"], cfg["d"], cfg["q"]), beta, cfg["chi"], steps,
                                           on_step=on_step)
     doc.update(lnz0=lnz0, dlnz0=dlnz0)
-    with open(grad_config5_path(beta), "w") as f:
-        json.dump(doc, f, indent=1)
+    dump_json(doc, grad_config5_path(beta))
     print("wrote", grad_config5_path(beta), flush=True)
 
 
@@ -198,8 +207,7 @@ def main(names):
         def write(runs):
             doc = dict(config="config4", runs=runs, steps=SI.CONFIG4_3D["steps"], provenance=provenance(),
                        source="oracle/hotrg.py (FP64 NumPy), written by tests/golden/make_golden.py")
-            with open(path, "w") as f:
-                json.dump(doc, f, indent=1)
+            dump_json(doc, path)
 
         run_config4(write)
         print("wrote", path, flush=True)
@@ -208,8 +216,7 @@ def main(names):
         doc = dict(config="grad", runs=run_grad(), provenance=provenance(),
                    source="oracle/tangent.py (FP64 NumPy), written by tests/golden/make_golden.py")
         path = os.path.join(HERE, "grad.json")
-        with open(path, "w") as f:
-            json.dump(doc, f, indent=1)
+        dump_json(doc, path)
         print("wrote", path, flush=True)
         names = [n for n in names if n != "grad"]
     table = {
@@ -225,8 +232,7 @@ def main(names):
                    steps=cfg["steps"], runs=runs, provenance=provenance(),
                    source="oracle/hotrg.py (FP64 NumPy), written by tests/golden/make_golden.py")
         path = os.path.join(HERE, f"{name}.json")
-        with open(path, "w") as f:
-            json.dump(doc, f, indent=1)
+        dump_json(doc, path)
         print("wrote", path, flush=True)
 
 
