@@ -85,21 +85,32 @@ def rounding_decided_cut(dd, kept_other):
     most 1e-10 of the pair) is then decided by the last bits of either eigensolver.  The
     disputed pair is the one at max(kept, kept_other): one side stopped there, the other
     went past it."""
-    k = max(dd["kept"], kept_other)
+    g = _gap_at(dd, max(dd["kept"], kept_other))
+    return g is not None and g <= ROUNDING_LEVEL
+
+
+def _gap_at(dd, k):
+    """(lambda_{k-1} - lambda_k) / lambda_0 of the adopted spectrum: from the recorded spectrum
+    when it reaches index k, else the recorded gap at the nominal cut chi_new when k is that cut
+    (the fixtures keep the leading part of the spectrum only, so a cut at chi = 32 lies beyond
+    it); None when it is not known or nothing is cut there."""
     sp = _adopted_spectrum(dd)
-    if k < 1 or k >= len(sp):
-        return False
-    return sp[k - 1] - sp[k] <= ROUNDING_LEVEL
+    if k < 1:
+        return None
+    if k < len(sp):
+        return sp[k - 1] - sp[k]
+    if k == dd["chi_new"]:
+        return dd.get("gap")
+    return None
 
 
 def effective_gap(dd):
     """(lambda_{kept-1} - lambda_kept) / lambda_0 at the cut actually made (1.0 when nothing
-    was truncated, or when the cut lies beyond the recorded part of the spectrum)."""
-    sp = _adopted_spectrum(dd)
-    k = dd["kept"]
-    if dd.get("gap") is None or k >= len(sp):
+    was truncated, or when the gap at the cut is not recorded)."""
+    if dd.get("gap") is None:
         return 1.0
-    return sp[k - 1] - sp[k]
+    g = _gap_at(dd, dd["kept"])
+    return 1.0 if g is None else g
 
 
 def conditioned_steps(run, threshold):

@@ -92,6 +92,23 @@ def test_rounding_decided_cut_and_gaps():
     assert PT.conditioned_steps(run, 1e-8) == 3
 
 
+def test_cut_beyond_the_recorded_spectrum():
+    # the fixtures record the leading eigenvalues only: a cut at chi_new past them is judged by
+    # the gap recorded at that cut, any other cut there is unknown (never rounding-decided)
+    dd = _dir([1.0, 0.5, 0.2], kept=4, chi_new=4, gap=2.7e-13)
+    assert PT.rounding_decided_cut(dd, 2)
+    assert PT.effective_gap(dd) == 2.7e-13
+    assert not PT.rounding_decided_cut(_dir([1.0, 0.5, 0.2], kept=4, chi_new=4, gap=1e-9), 2)
+    assert PT.effective_gap(_dir([1.0, 0.5, 0.2], kept=4, chi_new=4, gap=1e-9)) == 1e-9
+    dd = _dir([1.0, 0.5, 0.2], kept=3, chi_new=4, gap=1e-14)
+    assert not PT.rounding_decided_cut(dd, 2)
+    assert PT.effective_gap(dd) == 1.0
+    run = {"steps": [{"dirs": {"1": _dir([1.0, 0.5, 0.1], 4, 4, gap=0.05)}},
+                     {"dirs": {"1": _dir([1.0, 0.5, 0.1], 4, 4, gap=2e-12)}}]}
+    assert PT.first_cut_below(run, PT.SUBSPACE_LEVEL["fp64"]) == 2
+    assert PT.conditioned_steps(run, PT.SUBSPACE_LEVEL["fp64"]) == 2
+
+
 def test_first_cut_below():
     run = {"steps": [{"dirs": {"1": _dir([1.0, 0.5, 0.1], 2, 2)}},
                      {"dirs": {"1": _dir([1.0, 2e-5, 2e-5 - 1e-14], 2, 2)}}]}
