@@ -302,14 +302,15 @@ int hotrg_batch_log_z(hotrg_batch* b, double* lnz_per_site, int* steps_done);
 
 /* Autotuner (optional, before the first step; synchronises): for every distinct (d, chi)
  * among the instances, times the saturated new-tensor contraction of one of them with each
- * candidate launch shape (GEMM tiles of 256 x 256 or 128 x 128 for the 16-bit forms; column
- * chunks of the planned size, 1/2 and 1/4 of it) and keeps the fastest for that class.
+ * candidate launch shape (GEMM tiles: 288 x 288 with the non-prime chain in the epilogue for 3D
+ * chi = 12 in the reduced forms, 256 x 256 in the reduced forms, 128 x 128 in the 16-bit forms;
+ * column chunks of the planned size, 1/2 and 1/4 of it) and keeps the fastest for that class.
  * *nclasses (may be NULL) receives the number of classes.  Errors: HOTRG_E_STATE after the
  * first step, HOTRG_E_DEVICE. */
 int hotrg_batch_tune(hotrg_batch* b, int* nclasses);
 
 /* Result of the autotuner for class cls (0 .. nclasses-1): d, chi, the GEMM tile edge used
- * (256 or 128; always 128 in the FP64 and FP32 forms), pair groups per chunk, and the
+ * (288, 256 or 128; 0 in the FP64 form, whose GEMM is not a candidate), pair groups per chunk, and the
  * contraction time in ms.  Any output pointer may be NULL.  HOTRG_E_ARG if cls is out of
  * range. */
 int hotrg_batch_tuning(hotrg_batch* b, int cls, int* d, int* chi, int* gemm_tile, int* chunk_pairs, double* ms);

@@ -334,6 +334,7 @@ struct hotrg_handle {
   // tile GEMM instead of the 256 x 256 one for the 16-bit forms
   int tune_chunk = 0;
   bool tune_small_tiles = false;
+  bool tune_no_f12 = false;   // set by the batch autotuner: 3D chi = 12 through the 256 x 256 GEMM unfused
   bool grad = false;      // derivative mode: carry dT/dbeta through every step
   std::string err;
   // live timing: pairs of events recorded on the stream, resolved at hotrg_timings
@@ -474,6 +475,20 @@ void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, 
   hipLaunchKernelGGL((k_gemm_tn<Op, PL, T, T, GemmCfg<F>::BK>), grid, dim3(256), 0, s,
                      (const typename Op::T*)A, lda, aplane, (const typename Op::T*)B, ldb, bplane,
                      (typename Op::Acc*)C, ldc, czs, (int)kchunk, scale_ptr, smult);
+}
+
+// The 288 x 288 GEMM with the non-prime chain in its epilogue (3D, chi_1 = chi_2 = k_1 = k_2 = 12):
+// M = H rows (a multiple of 288), ncols columns (a multiple of 288), Kp a multiple of 64 bytes.
+template <int F>
+void launch_gemm_f12(const void* A, long lda, long aplane, const void* B, long ldb, long bplane, long M, long ncols,
+                     long Kp, const double* scale_ptr, const FuseArgs& fa, hipStream_t s) {
+  if constexpr (F != F_FP64) {
+    typedef typename std::conditional<F == F_FP32, OpF32v, typename OpOf<F>::type>::type OpB;
+    const int mt = (int)(M / F12_T), nt = (int)(ncols / F12_T);
+    hipLaunchKernelGGL((k_gemm_f12<OpB, FormInfo<F>::planes>), dim3((unsigned)(mt * nt)), dim3(64 * F12_WAVES), 0, s,
+                       (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B, ldb, bplane, (int)Kp, mt,
+                       nt, scale_ptr, fa);
+  }
 }
 
 // Gram matrices for direction j (1-based) into A_out[side] (n x n each, n = chi_j^2).
@@ -683,10 +698,14 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
       sp = &st->inv_scale;
     }
     // the non-prime chain runs in the GEMM epilogue when one 256 x 256 tile is one (c, g) block
+    // (chi = 16), or in the 288 x 288 kernel of 2 x 2 blocks (chi = 12, an even number of c)
     const bool fused = FormInfo<F>::fused_ok && ld.d == 3 && dm.chi1 == 16 && dm.chi2 == 16 && dm.k1 == 16 &&
                        dm.k2 == 16 && h->opts.chunk >= 0 && !h->no_fuse && !h->tune_small_tiles;
+    const bool fused12 = FormInfo<F>::fused_ok && ld.d == 3 && dm.chi1 == 12 && dm.chi2 == 12 && dm.k1 == 12 &&
+                         dm.k2 == 12 && H % F12_T == 0 && ncols % F12_T == 0 && Kp % 64 == 0 &&
+                         h->opts.chunk >= 0 && !h->no_fuse && !h->tune_small_tiles && !h->tune_no_f12;
     FuseArgs fa{};
-    if (fused) {
+    if (fused || fused12) {
       fa.U1 = (const float*)U1;
       fa.U2 = (const float*)U2;
       fa.Tn = (float*)Tn;
@@ -695,11 +714,14 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
       fa.g0 = (int)(pr0 * dm.chic);
     }
     hipEvent_t t1 = tmark(h);
-    launch_gemm<F>(Aop, Kp, aplane, Bop, Kp, bplane, Cc, Np, 0, Mp, Np, Kp, 1, Kp, sp, 1.0, h->s,
-                   fused ? &fa : nullptr, h->tune_small_tiles);
+    if (fused12)
+      launch_gemm_f12<F>(Aop, Kp, aplane, Bop, Kp, bplane, H, ncols, Kp, sp, fa, h->s);
+    else
+      launch_gemm<F>(Aop, Kp, aplane, Bop, Kp, bplane, Cc, Np, 0, Mp, Np, Kp, 1, Kp, sp, 1.0, h->s,
+                     fused ? &fa : nullptr, h->tune_small_tiles);
     tclose(h, HOTRG_T_BOTTLENECK, t1);
     if (h->profiling) h->acc.flops_bottleneck += 2.0 * (double)H * (double)ncols * (double)H;
-    if (fused) continue;
+    if (fused || fused12) continue;
     hipEvent_t t2 = tmark(h);
     const long ncell = (long)dm.chic * (pr1 - pr0) * dm.chic;   // (c, g) blocks
     const int g0 = (int)(pr0 * dm.chic), gcount = (int)((pr1 - pr0) * dm.chic);
@@ -1909,12 +1931,20 @@ int hotrg_batch_tune(hotrg_batch* b, int* nclasses) {
     for (int j = 1; j < d; ++j) k[j - 1] = chi;
     const long base = chunk_pairs_for(ld, k, h->form, h->opts.chunk);
     const bool sixteen = h->form != HOTRG_FP64 && h->form != HOTRG_FP32;
+    // GEMM variants by tile edge: 288 (3D chi = 12, non-prime chain fused), 256, 128 (16-bit forms)
+    const bool f12 = d == 3 && chi == 12 && h->form != HOTRG_FP64;
+    std::vector<int> tiles;
+    if (f12) tiles.push_back(F12_T);
+    if (h->form != HOTRG_FP64) tiles.push_back(GB_BM);
+    if (sixteen) tiles.push_back(128);
+    if (h->form == HOTRG_FP64) tiles.push_back(0);   // one GEMM path, chunks only
     hotrg_batch::Tuned best{d, chi, 0, 0, 1e300};   // tile: GEMM tile edge
-    for (int v = 0; v < (sixteen ? 2 : 1) && rc == HOTRG_OK; ++v)
+    for (size_t v = 0; v < tiles.size() && rc == HOTRG_OK; ++v)
       for (int div = 1; div <= 4 && rc == HOTRG_OK; div *= 2) {
         const long cp = std::max(1L, base / div);
         if (div > 1 && cp == std::max(1L, base / (div / 2))) continue;
-        h->tune_small_tiles = v == 1;
+        h->tune_small_tiles = tiles[v] == 128 && sixteen;
+        h->tune_no_f12 = tiles[v] != F12_T;
         h->tune_chunk = (int)cp;
         float ms = 0.f;
         for (int rep = 0; rep < 3 && rc == HOTRG_OK; ++rep) {   // first run warms up
@@ -1924,13 +1954,14 @@ int hotrg_batch_tune(hotrg_batch* b, int* nclasses) {
         if (rc == HOTRG_OK && (hipEventRecord(e1, b->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
           rc = HOTRG_E_DEVICE;
-        if (rc == HOTRG_OK && ms / 2 < best.ms) best = {d, chi, (sixteen && v == 0) ? 256 : 128, (int)cp, ms / 2.0};
+        if (rc == HOTRG_OK && ms / 2 < best.ms) best = {d, chi, tiles[v], (int)cp, ms / 2.0};
       }
     if (rc != HOTRG_OK) break;
     b->tuned.push_back(best);
     for (auto* x : b->inst)
       if (x->ld.d == d && x->chi == chi) {
         x->tune_small_tiles = best.tile == 128 && sixteen;
+        x->tune_no_f12 = best.tile != F12_T;
         x->tune_chunk = best.chunk;
       }
   }

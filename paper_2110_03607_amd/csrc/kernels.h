@@ -605,6 +605,169 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
 }
 
 // ---------------------------------------------------------------------------
+// Bottleneck GEMM with the non-prime chain in its epilogue for 3D chi_1 = chi_2 = k_1 = k_2 =
+// 12 (section 4.2.9, eqs. BottleneckPart and NonPrimePart).  A (c, g) block of C is 144 x 144
+// (rows (nh1, nh2), columns (nc1, nc2)), which no 16-aligned power-of-two tile covers, so the
+// tile is 288 x 288 = 2 c x 2 g blocks and the workgroup has 12 waves (3 per SIMD) in a 2 (M) x
+// 6 (N) grid of 144 x 48 wave tiles: a wave tile is the rows of one c and four nc1 columns of
+// one g.  The operand pipeline is the large-tile kernel's (global_load_lds into an XOR-swizzled,
+// double-buffered LDS, BK = 64 bytes).  Epilogue, per wave, in three rounds of four nh1 values:
+// the round's 48 x 48 accumulators go to LDS, and
+//   Q[nh1, nc1, n2] = sum_{nh2, nc2} C[(nh1, nh2), (nc1, nc2)] U2[(nh2 + 12 nc2), n2]
+// is one 16 x 16 (rows (nh1, nc1), columns n2 of which 12 are used) x 144 product on
+// v_mfma_f32_16x16x4f32 with U2 held in registers; then per (c, g) block
+//   T^next[n1, n2, c, g] = s sum_{nh1, nc1} U1[(nh1 + 12 nc1), n1] Q[nh1, nc1, n2]
+// from LDS.  C is never written.
+// ---------------------------------------------------------------------------
+constexpr int F12_B = 144, F12_T = 288, F12_WAVES = 12;
+constexpr int F12_STAGE1 = (F12_T + F12_T) * 64;                       // bytes per plane and stage
+constexpr int F12_EPI = (F12_WAVES * 48 * 48 + 4 * F12_B * 12 + F12_B * 12) * 4;   // epilogue bytes
+
+__device__ inline void tile_of_xcd(int b, int mt, int nt, int& tm, int& tn) {
+  // consecutive tiles (tm fastest) on the same XCD: the mt tiles that share a B row panel meet
+  // in one L2.  Workgroup b runs on XCD b % 8; XCD x takes tiles [x per + min(x, rem), ...).
+  const int total = mt * nt, per = total >> 3, rem = total & 7, x = b & 7;
+  const int t = x * per + (x < rem ? x : rem) + (b >> 3);
+  tm = t % mt;
+  tn = t / mt;
+}
+
+template <class Op, int PLANES>
+__global__ __launch_bounds__(64 * F12_WAVES) void k_gemm_f12(
+    const typename Op::T* __restrict__ A, long lda, long a_plane,
+    const typename Op::T* __restrict__ B, long ldb, long b_plane, int Kp, int mtiles, int ntiles,
+    const double* __restrict__ scale_ptr, FuseArgs fa) {
+  typedef typename Op::Frag Frag;
+  typedef typename Op::AccV AccV;
+  constexpr int ES = sizeof(typename Op::T), CE = 16 / ES, BKE = 64 / ES;
+  constexpr int STAGE = PLANES * F12_STAGE1;
+  constexpr int LDS_BYTES = 2 * STAGE > F12_EPI ? 2 * STAGE : F12_EPI;
+  __shared__ __attribute__((aligned(16))) char lds[LDS_BYTES];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / 6, wn = wave % 6;
+  int tm, tn;
+  tile_of_xcd(blockIdx.x, mtiles, ntiles, tm, tn);
+  const long m0 = (long)tm * F12_T, n0 = (long)tn * F12_T;
+  const char* Ab = (const char*)A;
+  const char* Bb = (const char*)B;
+  const int fr = lane & 15, fc = lane >> 4;
+
+  AccV acc[9][3];
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[i][j] = AccV{0, 0, 0, 0};
+
+  // A stage of one plane is 36 groups of 16 rows x 64 bytes (18 of A, then 18 of B), 1 KiB of
+  // LDS each; wave w loads groups w, 12 + w and 24 + w.  Lane l of a group load brings row
+  // l / 4 of the group, global chunk (l & 3) ^ ((row >> 1) & 3), to LDS byte 16 l of the group,
+  // which is the swizzled slot swz(row, chunk).
+  const int rl = lane >> 2, cl = (lane & 3) ^ ((rl >> 1) & 3);
+  const unsigned voa = (unsigned)(ES * (rl * lda + cl * CE)), vob = (unsigned)(ES * (rl * ldb + cl * CE));
+  auto issue = [&](int stage, long k0) {
+#pragma unroll
+    for (int p = 0; p < PLANES; ++p)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int G = t * F12_WAVES + wave;
+        char* la = lds + stage * STAGE + p * F12_STAGE1 + G * 1024;
+        const char* src = G < 18 ? Ab + ES * (p * a_plane + (m0 + 16L * G) * lda + k0) + voa
+                                 : Bb + ES * (p * b_plane + (n0 + 16L * (G - 18)) * ldb + k0) + vob;
+        __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)la, 16, 0, 0);
+      }
+  };
+  const int nk = Kp / BKE;
+  issue(0, 0);
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    // the next stage into the other buffer (last read in k-step kt - 1, before its closing
+    // barrier); the last k-step fetches its own slice again, in bounds and never read
+    issue((kt + 1) & 1, (long)(kt + 1 < nk ? kt + 1 : kt) * BKE);
+    const char* base = lds + (kt & 1) * STAGE;
+    Frag b[PLANES][3];
+#pragma unroll
+    for (int p = 0; p < PLANES; ++p)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        b[p][j] = *(const Frag*)(base + p * F12_STAGE1 + F12_T * 64 + swz(wn * 48 + j * 16 + fr, fc));
+    __builtin_amdgcn_iglp_opt(0);
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      Frag a[PLANES];
+#pragma unroll
+      for (int p = 0; p < PLANES; ++p)
+        a[p] = *(const Frag*)(base + p * F12_STAGE1 + swz(wm * F12_B + i * 16 + fr, fc));
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if constexpr (PLANES == 2) {
+          acc[i][j] = Op::mma(a[0], b[PLANES - 1][j], acc[i][j]);
+          acc[i][j] = Op::mma(a[PLANES - 1], b[0][j], acc[i][j]);
+        }
+        acc[i][j] = Op::mma(a[0], b[0][j], acc[i][j]);
+      }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's part of the next stage is in LDS
+    __syncthreads();
+  }
+
+  // ---- epilogue (every load of the pipeline has landed and been read: LDS is free) ----
+  float* cq = (float*)lds + wave * 48 * 48;             // this wave's round: [col 48][row 48]
+  float* qs = (float*)lds + F12_WAVES * 48 * 48;        // Q of the 4 blocks: [blk][(nh1 12 + nc1) 12 + n2]
+  float* u1s = qs + 4 * F12_B * 12;                     // U1[(nh1 + 12 nc1) 12 + n1]
+  for (int i = tid; i < F12_B * 12; i += 64 * F12_WAVES) u1s[i] = fa.U1[i];
+  // B operand of the Q product: k = 4 s + lane / 16 <-> (nh2, nc2) = (k / 12, k % 12), column n2 = lane % 16
+  float ub[36];
+#pragma unroll
+  for (int s = 0; s < 36; ++s) {
+    const int k = 4 * s + fc, nh2 = k / 12, nc2 = k - 12 * nh2;
+    ub[s] = fr < 12 ? fa.U2[(nh2 + 12 * nc2) * 12 + fr] : 0.f;
+  }
+  const int blk = wm * 2 + wn / 3, nc1_0 = 4 * (wn % 3);
+  // A operand row m = lane % 16 <-> (nh1 within the round, nc1 within the wave) = (m / 4, m % 4)
+  const int am_row = 12 * (fr >> 2), am_col = 12 * (fr & 3);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    // the round's rows are blocks i = 3 r .. 3 r + 2; a lane's four rows of a block are contiguous
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        *(f4*)(cq + (j * 16 + fr) * 48 + ii * 16 + 4 * fc) = acc[3 * r + ii][j];
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the round is in LDS
+    __builtin_amdgcn_wave_barrier();
+    f4 q = {0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 36; ++s) {
+      const int k = 4 * s + fc, nh2 = k / 12, nc2 = k - 12 * nh2;
+      q = __builtin_amdgcn_mfma_f32_16x16x4f32(cq[(am_col + nc2) * 48 + am_row + nh2], ub[s], q, 0, 0, 0);
+    }
+    // q[e] = Q[nh1 = 4 r + lane / 16][nc1 = nc1_0 + e][n2 = lane % 16]
+    if (fr < 12) {
+      const int nh1 = 4 * r + fc;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) qs[blk * F12_B * 12 + (nh1 * 12 + nc1_0 + e) * 12 + fr] = q[e];
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this round's reads are done before the next writes
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  const float sc = (float)(scale_ptr ? *scale_ptr : 1.0);
+  if (tid < 4 * F12_B) {
+    const int bk = tid / F12_B, o = tid - bk * F12_B, n1 = o / 12, n2 = o - 12 * n1;
+    const float* qb = qs + bk * F12_B * 12;
+    float t = 0.f;
+    for (int nh1 = 0; nh1 < 12; ++nh1)
+#pragma unroll 4
+      for (int nc1 = 0; nc1 < 12; ++nc1) t += u1s[(nh1 + 12 * nc1) * 12 + n1] * qb[(nh1 * 12 + nc1) * 12 + n2];
+    const int c = 2 * tm + (bk >> 1), g = fa.g0 + 2 * tn + (bk & 1);
+    fa.Tn[(long)((n1 * 12 + n2) * fa.chic + c) * fa.Hn + g] = t * sc;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Large-tile FP64 GEMM: C_z[m][n] = s * sum_{k in slice z} A[m][k] B[n][k], tile 256 x 128,
 // BK = 8, 512 threads: 8 waves in a 2 (M) x 4 (N) grid, 128 x 32 per wave (8 x 2 blocks of
 // 16 x 16, v_mfma_f64_16x16x4f64).  An LDS row of the tile is 8 doubles = 64 bytes, the same

@@ -121,7 +121,10 @@ def check_sweep(fx, lnz_of, kept_of, precision, label):
               + (f"; kept differs from step {first} ({kdiff}; at rounding-decided cuts {krounding})"
                  if kdiff or krounding else ""))
         if precision == "fp64":
-            assert not kdiff, (idx, kdiff)
+            # a kept count may differ only at a rounding-decided cut, or after one (from there the
+            # two runs contract different tensors and their later cuts need not agree)
+            first_rounding = min(krounding) if krounding else steps + 1
+            assert not [p for p in kdiff if p <= first_rounding], (idx, kdiff, krounding)
         for p in range(1, steps + 1):
             assert per[p - 1] < (tight if p < first else loose), (idx, p, per[p - 1])
         worst = max(worst, max(per))

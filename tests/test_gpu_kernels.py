@@ -91,8 +91,10 @@ def test_contract_fp64_matches_oracle(dims, kdims):
 @pytest.mark.parametrize("form", [P.HOTRG_FP32, P.HOTRG_SPLIT_FP16, P.HOTRG_SPLIT_BF16, P.HOTRG_FP16,
                                   P.HOTRG_BF16])
 @pytest.mark.parametrize("dims,kdims", [((8, 8, 8), (8, 8)), ((3, 5, 4), (7, 6)), ((8, 8), (16,)),
-                                       ((3, 12, 12), (12, 12))])
+                                       ((3, 12, 12), (12, 12)), ((2, 12, 12), (12, 12))])
 def test_contract_forms_match_oracle(form, dims, kdims):
+    # (3, 12, 12): chi = 12 with an odd number of c, the 256 x 256 GEMM and a separate non-prime
+    # kernel; (2, 12, 12): the 288 x 288 GEMM with the non-prime chain in its epilogue
     _check_all_slices(form, dims, kdims, seed=3)
 
 
@@ -119,6 +121,29 @@ def test_contract_full_size_sampled(form):
     worst, errs = PT.worst_slice_error(got, ref, FULL_PICKS)
     print(f"{FORM_NAME[form]} full size, 16 slices: max slice error {worst:.2e} (bound {SLICE_BOUND[form]:.0e}); "
           "per slice " + " ".join(f"{e:.1e}" for e in errs))
+    assert worst < SLICE_BOUND[form]
+
+
+FULL12_DIMS, FULL12_K, FULL12_SEED = (12, 12, 12), (12, 12), 12
+FULL12_PICKS = PT.spread_picks(FULL12_K, 16)
+
+
+@functools.lru_cache(maxsize=None)
+def _full12_reference():
+    Ts, Us = _random_case(FULL12_DIMS, FULL12_K, FULL12_SEED)
+    return Ts, Us, oracle_next_storage(LY.to_paper(Ts), Us, only=FULL12_PICKS)
+
+
+@pytest.mark.parametrize("form", [P.HOTRG_SPLIT_FP16, P.HOTRG_SPLIT_BF16, P.HOTRG_FP16, P.HOTRG_FP32, P.HOTRG_BF16])
+def test_contract_chi12_full_size_sampled(form):
+    """chi = 12 in 3D (M = K = 1728, the sweep's 3D shape): the reduced forms run the 288 x 288
+    GEMM with the non-prime chain in its epilogue; 16 spread (n'_1, n'_2) slices of the new
+    tensor against the oracle, element by element."""
+    Ts, Us, ref = _full12_reference()
+    got = gu.contract(Ts, Us, list(FULL12_K), form)
+    worst, errs = PT.worst_slice_error(got, ref, FULL12_PICKS)
+    print(f"{FORM_NAME[form]} chi=12 full size, 16 slices: max slice error {worst:.2e} "
+          f"(bound {SLICE_BOUND[form]:.0e}); per slice " + " ".join(f"{e:.1e}" for e in errs))
     assert worst < SLICE_BOUND[form]
 
 
