@@ -237,6 +237,16 @@ size_t hotrg_debug_eigh_workspace_bytes(int n, int batch);
 int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_dev,
                      void* workspace_dev, size_t workspace_bytes, void* hip_stream);
 
+/* The eigensolver of a truncating step (Section 4.2.5: only the kept eigenvectors of A and A' are
+ * needed): as hotrg_debug_eigh for the leading kvec (1 <= kvec <= n) eigenvectors only.
+ * w_dev[b][i] receives the eigenvalues resolved one by one, descending (all n up to n = 256,
+ * else the leading max(kvec + 1, 24)), zeros after them; tail_dev[b] the sum of the others
+ * (trace of the tridiagonal form minus the resolved ones; 0 when all are resolved); columns
+ * 0 .. kvec-1 of V_dev[b] (row-major n x n) the eigenvectors, the other columns untouched.
+ * Workspace: hotrg_debug_eigh_workspace_bytes(n, batch).  Errors as hotrg_debug_eigh. */
+int hotrg_debug_eigh_lead(int n, int batch, int kvec, double* A_dev, double* w_dev, double* V_dev, double* tail_dev,
+                          void* workspace_dev, size_t workspace_bytes, void* hip_stream);
+
 /* ---- measurement -------------------------------------------------------------------------
  * Issue rate of the MFMA instruction a precision form contracts with (FP64: v_mfma_f64_16x16x4,
  * FP32: v_mfma_f32_16x16x4_f32, 16-bit forms: v_mfma_f32_16x16x32_{f16,bf16}), in TFLOP/s, from

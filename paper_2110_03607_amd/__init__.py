@@ -119,6 +119,9 @@ _SIGS = {
     "hotrg_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "hotrg_debug_eigh": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "hotrg_debug_eigh_lead": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.c_void_p]),
     "hotrg_probe_mfma_rate": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "hotrg_eigh_noalloc_max_bytes": (ctypes.c_size_t, []),
     "hotrg_eigh_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
@@ -269,6 +272,13 @@ def hotrg_debug_eigh_workspace_bytes(n: int, batch: int) -> int:
 def hotrg_debug_eigh(n, batch, A_ptr, w_ptr, V_ptr, ws_ptr, ws_bytes, stream_ptr):
     rc = lib().hotrg_debug_eigh(n, batch, ctypes.c_void_p(A_ptr), ctypes.c_void_p(w_ptr), ctypes.c_void_p(V_ptr),
                                 ctypes.c_void_p(ws_ptr), ws_bytes, ctypes.c_void_p(stream_ptr))
+    _check(rc, None)
+
+
+def hotrg_debug_eigh_lead(n, batch, kvec, A_ptr, w_ptr, V_ptr, tail_ptr, ws_ptr, ws_bytes, stream_ptr):
+    rc = lib().hotrg_debug_eigh_lead(n, batch, kvec, ctypes.c_void_p(A_ptr), ctypes.c_void_p(w_ptr),
+                                     ctypes.c_void_p(V_ptr), ctypes.c_void_p(tail_ptr), ctypes.c_void_p(ws_ptr),
+                                     ws_bytes, ctypes.c_void_p(stream_ptr))
     _check(rc, None)
 
 

@@ -312,6 +312,26 @@ void enqueue_tri_steps(const EigBatch& eb, hipStream_t s) {
     hipLaunchKernelGGL(k_tri_step, dim3(gx, (unsigned)eb.count), dim3(256), 0, s, eb, st);
 }
 
+// After enqueue_tri_steps: eigenpairs of every matrix of eb, by the one-workgroup solver or,
+// for the large truncated ones (eig_split), by the split kernels.
+void enqueue_eig_finish(const EigBatch& eb, hipStream_t s) {
+  int whole = 0, wb = 0, kv = 0;
+  for (int i = 0; i < eb.count; ++i) {
+    if (eig_split(eb.n[i], eb.kvec[i])) {
+      wb = std::max(wb, (eig_nev(eb.n[i], eb.kvec[i]) + EB_EPW - 1) / EB_EPW);
+      kv = std::max(kv, eb.kvec[i]);
+    } else {
+      ++whole;
+    }
+  }
+  if (whole) hipLaunchKernelGGL(k_eigh_tri, dim3((unsigned)eb.count), dim3(EIG_THREADS), 0, s, eb);
+  if (wb) {
+    hipLaunchKernelGGL(k_eig_bisect, dim3((unsigned)wb, (unsigned)eb.count), dim3(EB_THREADS), 0, s, eb);
+    hipLaunchKernelGGL(k_eig_invit, dim3((unsigned)eb.count), dim3(EI_THREADS), 0, s, eb);
+    hipLaunchKernelGGL(k_eig_backtr, dim3((unsigned)kv, (unsigned)eb.count), dim3(64), 0, s, eb);
+  }
+}
+
 }  // namespace
 
 struct hotrg_handle {
@@ -1328,7 +1348,7 @@ int hotrg_step(hotrg_handle* h, int axis) {
       eb.V[i] = eig[i].V; eb.scratch[i] = eig[i].scratch; eb.tail[i] = eig[i].tail; eb.fail[i] = eig[i].fail;
     }
     enqueue_tri_steps(eb, h->s);
-    hipLaunchKernelGGL(k_eigh_tri, dim3(ne), dim3(EIG_THREADS), 0, h->s, eb);
+    enqueue_eig_finish(eb, h->s);
   }
   rc = enqueue_step_back(h, sp, t_dec);
   if (rc) return rc;
@@ -1612,7 +1632,13 @@ size_t hotrg_debug_eigh_workspace_bytes(int n, int batch) {
 
 int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_dev, void* workspace,
                      size_t ws_bytes, void* stream) {
-  if (n < 1 || n > EIG_MAXN || batch < 1 || batch > 4 || !A_dev || !w_dev || !V_dev || !workspace)
+  return hotrg_debug_eigh_lead(n, batch, n, A_dev, w_dev, V_dev, nullptr, workspace, ws_bytes, stream);
+}
+
+int hotrg_debug_eigh_lead(int n, int batch, int kvec, double* A_dev, double* w_dev, double* V_dev, double* tail_dev,
+                          void* workspace, size_t ws_bytes, void* stream) {
+  if (n < 1 || n > EIG_MAXN || batch < 1 || batch > 4 || kvec < 1 || kvec > n || !A_dev || !w_dev || !V_dev ||
+      !workspace)
     return fail(nullptr, HOTRG_E_ARG, "invalid argument");
   if (ws_bytes < hotrg_debug_eigh_workspace_bytes(n, batch)) return fail(nullptr, HOTRG_E_OOM, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
@@ -1622,15 +1648,16 @@ int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_d
   eb.count = batch;
   for (int b = 0; b < batch; ++b) {
     eb.n[b] = n;
-    eb.kvec[b] = n;
+    eb.kvec[b] = kvec;
     eb.A[b] = A_dev + (size_t)b * n * n;
     eb.w[b] = w_dev + (size_t)b * n;
     eb.V[b] = V_dev + (size_t)b * n * n;
     eb.scratch[b] = (double*)workspace + (size_t)b * 2 * n * n;
+    eb.tail[b] = tail_dev ? tail_dev + b : nullptr;
     eb.fail[b] = flag;
   }
   enqueue_tri_steps(eb, s);
-  hipLaunchKernelGGL(k_eigh_tri, dim3(batch), dim3(EIG_THREADS), 0, s, eb);
+  enqueue_eig_finish(eb, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
   int failed = 0;
@@ -1742,7 +1769,7 @@ int hotrg_eigh_noalloc(int n, int batch, double* A_dev, double* w_dev, double* V
     eb.fail[b] = status_dev;
   }
   enqueue_tri_steps(eb, s);
-  hipLaunchKernelGGL(k_eigh_tri, dim3(batch), dim3(EIG_THREADS), 0, s, eb);
+  enqueue_eig_finish(eb, s);
   e = hipGetLastError();
   if (e != hipSuccess) return fail(nullptr, HOTRG_E_DEVICE, hipGetErrorString(e));
   return HOTRG_OK;
@@ -1883,8 +1910,27 @@ static int batch_table(hotrg_batch* b, const std::vector<EigDesc>& descs, const 
 
 // One step of every instance: records and Gram matrices of all, one eigensolver launch,
 // then choice, contraction, trace and normalisation of each in turn.
-static int batch_enqueue(hotrg_batch* b, const std::vector<StepPlan>& sps, int ndesc, const EigDesc* table,
-                         int maxn) {
+// Launch shape of the eigensolver kernels for a step's descriptor table (host copy).
+struct EigLaunch {
+  int ndesc = 0, maxn = 0, whole = 0, bisect_blocks = 0, max_kvec = 0;
+};
+static EigLaunch eig_launch(const std::vector<EigDesc>& descs) {
+  EigLaunch L;
+  L.ndesc = (int)descs.size();
+  for (const auto& e : descs) {
+    L.maxn = std::max(L.maxn, e.n);
+    if (eig_split(e.n, e.kvec)) {
+      L.bisect_blocks = std::max(L.bisect_blocks, (eig_nev(e.n, e.kvec) + EB_EPW - 1) / EB_EPW);
+      L.max_kvec = std::max(L.max_kvec, e.kvec);
+    } else {
+      ++L.whole;
+    }
+  }
+  return L;
+}
+
+static int batch_enqueue(hotrg_batch* b, const std::vector<StepPlan>& sps, const EigLaunch& L, const EigDesc* table) {
+  const int ndesc = L.ndesc, maxn = L.maxn;
   for (int i = 0; i < b->n; ++i) {
     const int rc = enqueue_step_front(b->inst[i], -1);
     if (rc) return batch_fail(b, rc, "instance " + std::to_string(i) + ": " + b->inst[i]->err);
@@ -1894,7 +1940,13 @@ static int batch_enqueue(hotrg_batch* b, const std::vector<StepPlan>& sps, int n
       for (int st = 0; st <= maxn - 2; ++st)
         hipLaunchKernelGGL(k_tri_step_list, dim3((unsigned)((maxn - 1 + TRI_ROWS - 1) / TRI_ROWS), (unsigned)ndesc),
                            dim3(256), 0, b->s, table, st);
-    hipLaunchKernelGGL(k_eigh_list, dim3((unsigned)ndesc), dim3(EIG_THREADS), 0, b->s, table);
+    if (L.whole) hipLaunchKernelGGL(k_eigh_list, dim3((unsigned)ndesc), dim3(EIG_THREADS), 0, b->s, table);
+    if (L.bisect_blocks) {
+      hipLaunchKernelGGL(k_eig_bisect_list, dim3((unsigned)L.bisect_blocks, (unsigned)ndesc), dim3(EB_THREADS), 0, b->s,
+                         table);
+      hipLaunchKernelGGL(k_eig_invit_list, dim3((unsigned)ndesc), dim3(EI_THREADS), 0, b->s, table);
+      hipLaunchKernelGGL(k_eig_backtr_list, dim3((unsigned)L.max_kvec, (unsigned)ndesc), dim3(64), 0, b->s, table);
+    }
   }
   for (int i = 0; i < b->n; ++i) {
     const int rc = enqueue_step_back(b->inst[i], sps[i], nullptr);
@@ -1999,8 +2051,7 @@ int hotrg_batch_step(hotrg_batch* b) {
     for (int k = 0; k < c; ++k) descs.push_back(e[k]);
     if (!same_dims(sps[i].ld, sps[i].nl)) steady = false;
   }
-  int maxn = 0;
-  for (const auto& e : descs) maxn = std::max(maxn, e.n);
+  const EigLaunch L = eig_launch(descs);
   const EigDesc* table = nullptr;
   int rc = batch_table(b, descs, &table);
   if (rc) return rc;
@@ -2011,7 +2062,7 @@ int hotrg_batch_step(hotrg_batch* b) {
     if (!b->graph[parity]) {
       if (hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return batch_fail(b, HOTRG_E_DEVICE, "stream capture could not begin");
-      rc = batch_enqueue(b, sps, (int)descs.size(), table, maxn);
+      rc = batch_enqueue(b, sps, L, table);
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(b->s, &g);
       if (rc) {
@@ -2030,7 +2081,7 @@ int hotrg_batch_step(hotrg_batch* b) {
       return batch_fail(b, HOTRG_E_DEVICE, "graph launch failed");
     b->graph_launches += 1;
   } else {
-    rc = batch_enqueue(b, sps, (int)descs.size(), table, maxn);
+    rc = batch_enqueue(b, sps, L, table);
     if (rc) return rc;
     b->eager_steps += 1;
   }

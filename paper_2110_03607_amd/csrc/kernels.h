@@ -1090,6 +1090,21 @@ __device__ inline void lu_solve(double* z, int n, const double* ri, const double
   }
 }
 
+constexpr int TRI_MULTI_N = 128;
+
+// Large matrices whose kept eigenvectors are few (n >= TRI_MULTI_N, kvec <= 64 and 6 kvec <= n: the
+// Gram matrices of a truncating step) finish in the split kernels k_eig_bisect, k_eig_invit and
+// k_eig_backtr, spread over many workgroups; the others in eigh_tri_body.
+__host__ __device__ inline bool eig_split(int n, int kvec) {
+  return n >= TRI_MULTI_N && kvec >= 1 && kvec <= 64 && 6 * kvec <= n;
+}
+// Eigenvalues resolved one by one (see eigh_tri_body).
+__host__ __device__ inline int eig_nev(int n, int kvec) {
+  if (kvec >= n || n <= EIG_ALL_N) return n;
+  const int m = kvec + 1 > NSPEC ? kvec + 1 : NSPEC;
+  return m < n ? m : n;
+}
+
 // tridiag_done: the tridiagonal form was built by k_tri_step (multi-workgroup, large n):
 // reflectors in R, diagonal and subdiagonal at Z[0, n) and Z[n, 2n).
 // *fail is set to 1 (and never cleared) when the tridiagonal matrix has a non-finite entry, when
@@ -1101,6 +1116,7 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
                               double* __restrict__ tail_out, int* __restrict__ fail) {
   __shared__ double d[EIG_MAXN], e[EIG_MAXN], vv[EIG_MAXN], qv[EIG_MAXN];
   __shared__ double red[EIG_THREADS / 64];
+  if (eig_split(n, kvec)) return;                       // k_eig_bisect, k_eig_invit and k_eig_backtr
   double* Z = R + (long)n * n;                          // reflector k at R[k n ..]; tridiagonal eigenvector i at Z[i n ..)
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
 
@@ -1439,7 +1455,6 @@ __device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ 
 // Matrices of at least TRI_MULTI_N rows are tridiagonalised by k_tri_step (many workgroups
 // per matrix, one launch per reflector) before the one-workgroup kernels below finish them;
 // smaller ones are done entirely by one workgroup.
-constexpr int TRI_MULTI_N = 128;
 
 // Up to four matrices passed by value (one coarse-graining step of one instance).
 __global__ __launch_bounds__(EIG_THREADS) void k_eigh_tri(EigBatch eb) {
@@ -1561,6 +1576,427 @@ __global__ __launch_bounds__(256) void k_tri_step(EigBatch eb, int s) {
 __global__ __launch_bounds__(256) void k_tri_step_list(const EigDesc* __restrict__ list, int s) {
   const EigDesc ds = list[blockIdx.y];
   tri_step(ds.n, ds.A, ds.scratch, s);
+}
+
+// ---------------------------------------------------------------------------
+// Eigenpairs of a large tridiagonal form (Section 4.2.5: the kept eigenvectors of A and A')
+// with the work spread over many workgroups.  Input: the tridiagonal matrix built by
+// k_tri_step (diagonal Z[0, n), subdiagonal Z[n, 2n)) and its reflectors R.  Same stopping
+// rules, tolerances and failure flags as eigh_tri_body; the arithmetic of one Sturm count,
+// one factorisation and one solve is that of eigh_tri_body.
+//   k_eig_bisect: eigenvalues by multisection, EB_EPW per workgroup, EB_G points per
+//     eigenvalue and sweep (EB_P independent Sturm chains per thread);
+//   k_eig_invit: the kvec eigenvectors of the tridiagonal matrix by inverse iteration, all of
+//     them side by side (one lane each, LU factors in the unused rows of Z), the members of a
+//     cluster re-orthogonalised in order between the solves, as eigh_tri_body does one vector
+//     at a time;
+//   k_eig_backtr: V[:, iv] = H_0 ... H_{n-3} z_iv, one vector per wave.
+// ---------------------------------------------------------------------------
+constexpr int EB_THREADS = 256, EB_TPE = 16, EB_P = 4;
+constexpr int EB_EPW = EB_THREADS / EB_TPE, EB_G = EB_TPE * EB_P;   // 16 eigenvalues, 64 points
+constexpr int EI_THREADS = 256;
+
+// Gershgorin interval [lo, hi] (padded as in eigh_tri_body) and |T| of the tridiagonal (d, e)
+// held in LDS; every thread of the block takes part (red: 2 blockDim.x / 64 doubles).
+__device__ inline void tri_bounds(const double* d, const double* e, int n, double* red, double& lo, double& hi,
+                                  double& tnorm) {
+  double gl = 1e300, gu = -1e300;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+    gl = fmin(gl, d[i] - r);
+    gu = fmax(gu, d[i] + r);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    gl = fmin(gl, __shfl_xor(gl, o));
+    gu = fmax(gu, __shfl_xor(gu, o));
+  }
+  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { red[wv] = gl; red[nw + wv] = gu; }
+  __syncthreads();
+  gl = red[0];
+  gu = red[nw];
+  for (int k = 1; k < nw; ++k) { gl = fmin(gl, red[k]); gu = fmax(gu, red[nw + k]); }
+  __syncthreads();
+  tnorm = fmax(fabs(gl), fabs(gu));
+  const double pad = 2.0 * 2.2e-16 * tnorm + 1e-300;
+  lo = gl - pad;
+  hi = gu + pad;
+}
+
+__device__ void eig_bisect_body(const int n, const int kvec, const double* __restrict__ Z, double* __restrict__ w,
+                                int* __restrict__ fail) {
+  if (!eig_split(n, kvec)) return;
+  const int nev = eig_nev(n, kvec);
+  const int first = blockIdx.x * EB_EPW;
+  if (first >= nev) return;
+  __shared__ double d[EIG_MAXN], e[EIG_MAXN], e2[EIG_MAXN];
+  __shared__ double red[2 * EB_THREADS / 64];
+  const int tid = threadIdx.x, lane = tid & 63;
+  int bad = 0;
+  for (int i = tid; i < n; i += EB_THREADS) {
+    d[i] = Z[i];
+    e[i] = Z[n + i];
+    e2[i] = e[i] * e[i];
+    bad |= !isfinite(d[i]) || !isfinite(e[i]);
+  }
+  if (__syncthreads_or(bad) && tid == 0 && blockIdx.x == 0) *fail = 1;
+  double lo, hi, tnorm;
+  tri_bounds(d, e, n, red, lo, hi, tnorm);
+  const double pivmin = fmax(1e-290, 2.2e-16 * 2.2e-16 * tnorm * tnorm);
+  const int nlead = min(n, max(kvec + 1, NSPEC));
+  const double abs_tol = 4.0 * 2.2e-16 * tnorm;
+  const int idx = first + tid / EB_TPE, jl = tid % EB_TPE;
+  const bool act = idx < nev;
+  const int target = n - 1 - idx;                         // 0-based index in ascending order
+  const int gbase = (lane / EB_TPE) * EB_TPE;             // first lane of this eigenvalue's group
+  double a = lo, b = hi;
+  bool done = !act;
+  for (int it = 0; it < 200; ++it) {
+    if (b - a <= (idx < nlead ? 2.2e-16 * fmax(fabs(a), fabs(b)) + pivmin : abs_tol)) done = true;
+    double x[EB_P], q[EB_P];
+    int cnt[EB_P];
+#pragma unroll
+    for (int k = 0; k < EB_P; ++k) {
+      x[k] = a + (b - a) * (double)(EB_P * jl + k + 1) / (double)(EB_G + 1);
+      cnt[k] = 0;
+    }
+    if (!done) {
+#pragma unroll
+      for (int k = 0; k < EB_P; ++k) {
+        q[k] = d[0] - x[k];
+        if (fabs(q[k]) < pivmin) q[k] = -pivmin;
+        cnt[k] = q[k] < 0.0;
+      }
+      for (int r = 1; r < n; ++r) {
+        const double dr = d[r], er = e2[r - 1];
+#pragma unroll
+        for (int k = 0; k < EB_P; ++k) {
+          q[k] = fma(-er, recip_nr(q[k]), dr - x[k]);    // |q| >= pivmin: a normal number
+          if (fabs(q[k]) < pivmin) q[k] = -pivmin;
+          cnt[k] += q[k] < 0.0;
+        }
+      }
+    }
+    unsigned long long m[EB_P];
+#pragma unroll
+    for (int k = 0; k < EB_P; ++k) m[k] = __ballot(!done && cnt[k] > target);
+    if (__all(done)) break;
+    if (!done) {
+      int js = EB_G;                                       // first point above lambda (point p = EB_P jl + k)
+#pragma unroll
+      for (int k = 0; k < EB_P; ++k) {
+        const unsigned bits = (unsigned)((m[k] >> gbase) & ((1ull << EB_TPE) - 1ull));
+        if (bits) js = min(js, EB_P * (__ffs(bits) - 1) + k);
+      }
+      const double na = js == 0 ? a : a + (b - a) * (double)js / (double)(EB_G + 1);
+      const double nb = js == EB_G ? b : a + (b - a) * (double)(js + 1) / (double)(EB_G + 1);
+      if (!(na >= a && nb <= b && (na > a || nb < b))) done = true;   // no progress left
+      a = na;
+      b = nb;
+    }
+  }
+  if (act && jl == 0 && !done) *fail = 1;   // interval still open at the iteration cap
+  if (act && jl == 0) w[idx] = 0.5 * (a + b);
+}
+
+__global__ __launch_bounds__(EB_THREADS) void k_eig_bisect(EigBatch eb) {
+  const int b = blockIdx.y;
+  if (b >= eb.count) return;
+  eig_bisect_body(eb.n[b], eb.kvec[b], eb.scratch[b] + (long)eb.n[b] * eb.n[b], eb.w[b], eb.fail[b]);
+}
+__global__ __launch_bounds__(EB_THREADS) void k_eig_bisect_list(const EigDesc* __restrict__ list) {
+  const EigDesc ds = list[blockIdx.y];
+  eig_bisect_body(ds.n, ds.kvec, ds.scratch + (long)ds.n * ds.n, ds.w, ds.fail);
+}
+
+// One lane's inverse-iteration solve z <- (T - lam I)^{-1} z (z: the lane's row of Z).  With
+// factor = true the LU factorisation of T - lam I (as lu_shifted) is made on the way and stored
+// (f: ri, u1, u2, l, pivot flag, n doubles each); else the stored one is used (as lu_solve).
+// Loads run ahead of the serial recurrences in blocks of EI_BLK rows.
+constexpr int EI_BLK = 16;
+template <bool FACTOR>
+__device__ inline void lane_solve(const double* d, const double* e, int n, double lam, double pivlu,
+                                  double* __restrict__ z, double* __restrict__ f) {
+  double* ri = f;
+  double* u1 = f + n;
+  double* u2 = f + 2 * n;
+  double* lq = f + 3 * n;
+  double* pv = f + 4 * n;
+  // forward: row operations, the value of row r carried in cur
+  double cur = z[0];
+  double a0 = d[0] - lam, b0 = n > 1 ? e[0] : 0.0, c0 = 0.0;   // LU: current row (diag, super, super2)
+  for (int r0 = 0; r0 + 1 < n; r0 += EI_BLK) {
+    double zn[EI_BLK], lb[EI_BLK], pb[EI_BLK];
+#pragma unroll
+    for (int k = 0; k < EI_BLK; ++k) {
+      const int r = r0 + k;
+      zn[k] = r + 1 < n ? z[r + 1] : 0.0;
+      if (!FACTOR) {
+        lb[k] = r + 1 < n ? lq[r] : 0.0;
+        pb[k] = r + 1 < n ? pv[r] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < EI_BLK; ++k) {
+      const int r = r0 + k;
+      if (r + 1 >= n) break;
+      double l, p;
+      if (FACTOR) {
+        const double sub = e[r];
+        const double dn = d[r + 1] - lam, en = r + 2 < n ? e[r + 1] : 0.0;
+        if (fabs(sub) > fabs(a0)) {
+          l = a0 / sub;
+          p = 1.0;
+          ri[r] = 1.0 / sub; u1[r] = dn; u2[r] = en;
+          a0 = b0 - l * dn;
+          b0 = c0 - l * en;
+        } else {
+          const double piv = fabs(a0) < pivlu ? (a0 < 0.0 ? -pivlu : pivlu) : a0;
+          l = sub / piv;
+          p = 0.0;
+          ri[r] = 1.0 / piv; u1[r] = b0; u2[r] = c0;
+          a0 = dn - l * b0;
+          b0 = en - l * c0;
+        }
+        c0 = 0.0;
+        lq[r] = l;
+        pv[r] = p;
+      } else {
+        l = lb[k];
+        p = pb[k];
+      }
+      const double nxt = zn[k];
+      if (p != 0.0) { z[r] = nxt; cur = cur - l * nxt; }
+      else { z[r] = cur; cur = nxt - l * cur; }
+    }
+  }
+  if (FACTOR) {
+    const double piv = fabs(a0) < pivlu ? (a0 < 0.0 ? -pivlu : pivlu) : a0;
+    ri[n - 1] = 1.0 / piv; u1[n - 1] = 0.0; u2[n - 1] = 0.0; lq[n - 1] = 0.0; pv[n - 1] = 0.0;
+  }
+  z[n - 1] = cur;
+  // backward substitution with U (three diagonals)
+  double x1 = 0.0, x2 = 0.0;
+  for (int r0 = n - 1; r0 >= 0; r0 -= EI_BLK) {
+    double zb[EI_BLK], ib[EI_BLK], ab[EI_BLK], bb[EI_BLK];
+#pragma unroll
+    for (int k = 0; k < EI_BLK; ++k) {
+      const int r = r0 - k;
+      zb[k] = r >= 0 ? z[r] : 0.0;
+      ib[k] = r >= 0 ? ri[r] : 0.0;
+      ab[k] = r >= 0 ? u1[r] : 0.0;
+      bb[k] = r >= 0 ? u2[r] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < EI_BLK; ++k) {
+      const int r = r0 - k;
+      if (r < 0) break;
+      const double x = (zb[k] - ab[k] * x1 - bb[k] * x2) * ib[k];
+      z[r] = x;
+      x2 = x1;
+      x1 = x;
+    }
+  }
+}
+
+// z_iv -= sum_{j0 <= j < iv} (z_j . z_iv) z_j over the rows of Z (all coefficients first, a wave
+// per j, then one update), as cgs_cluster.
+__device__ inline void cgs_rows(double* Z, int n, int j0, int iv, double* coef) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  double* zi = Z + (long)iv * n;
+  for (int j = j0 + wv; j < iv; j += nw) {
+    const double* zj = Z + (long)j * n;
+    double dp = 0.0;
+    for (int i = lane; i < n; i += 64) dp += zj[i] * zi[i];
+    for (int o = 32; o > 0; o >>= 1) dp += __shfl_xor(dp, o);
+    if (lane == 0) coef[j - j0] = dp;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += blockDim.x) {
+    double v = zi[i];
+    for (int j = j0; j < iv; ++j) v -= coef[j - j0] * Z[(long)j * n + i];
+    zi[i] = v;
+  }
+  __syncthreads();
+}
+
+__device__ void eig_invit_body(const int n, const int kvec, double* __restrict__ w, double* __restrict__ R,
+                               double* __restrict__ tail_out, int* __restrict__ fail) {
+  if (!eig_split(n, kvec)) return;
+  __shared__ double d[EIG_MAXN], e[EIG_MAXN];
+  __shared__ double red[2 * EI_THREADS / 64], coef[64];
+  __shared__ int j0s[64];
+  double* Z = R + (long)n * n;          // tridiagonal eigenvector iv at Z[iv n ..), then LU factors
+  double* F = Z + (long)kvec * n;       // factors of vector iv at F[5 n iv ..) (rows kvec .. n-1 of Z)
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = EI_THREADS >> 6;
+  for (int i = tid; i < n; i += EI_THREADS) { d[i] = Z[i]; e[i] = Z[n + i]; }
+  double lo, hi, tnorm;
+  tri_bounds(d, e, n, red, lo, hi, tnorm);   // (barriers inside: d, e visible)
+  // eigenvalues not resolved one by one: their sum (trace minus the resolved ones), zeros in w
+  const int nev = eig_nev(n, kvec);
+  {
+    double tp = 0.0;
+    for (int i = tid; i < n; i += EI_THREADS) tp += d[i];
+    for (int o = 32; o > 0; o >>= 1) tp += __shfl_xor(tp, o);
+    if (lane == 0) red[wv] = tp;
+    __syncthreads();
+    if (tid == 0 && tail_out) {
+      double tr = 0.0;
+      for (int k = 0; k < nw; ++k) tr += red[k];
+      double tail = 0.0;
+      if (nev < n) {
+        double lead = 0.0;
+        for (int i = 0; i < nev; ++i) lead += w[i];
+        tail = fmax(tr - lead, 0.0);
+      }
+      *tail_out = tail;
+    }
+    for (int i = nev + tid; i < n; i += EI_THREADS) w[i] = 0.0;
+  }
+  const double ortol = 1e-3 * tnorm;
+  const double pivlu = fmax(1e-290, 2.2e-16 * tnorm);
+  if (tid < kvec) {
+    int j0 = tid;
+    while (j0 > 0 && fabs(w[j0 - 1] - w[tid]) <= ortol) --j0;
+    j0s[tid] = j0;
+  }
+  // deterministic zero-mean start vectors (the same as eigh_tri_body's)
+  for (long idx = tid; idx < (long)kvec * n; idx += EI_THREADS) {
+    const int iv = (int)(idx / n), i = (int)(idx % n);
+    const unsigned hsh = (unsigned)(i + 1) * 2654435761u ^ (unsigned)(iv + 7) * 40503u;
+    Z[idx] = (double)(hsh & 0xFFFFu) / 32768.0 - 1.0;
+  }
+  __syncthreads();
+  auto normalise_all = [&]() {                       // a wave per vector
+    for (int iv = wv; iv < kvec; iv += nw) {
+      double* z = Z + (long)iv * n;
+      double np = 0.0;
+      for (int i = lane; i < n; i += 64) np += z[i] * z[i];
+      for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
+      const double inv = 1.0 / sqrt(np);
+      for (int i = lane; i < n; i += 64) z[i] *= inv;
+    }
+    __syncthreads();
+  };
+  auto normalise_one = [&](int iv) {                 // the whole block, after cgs_rows
+    double* z = Z + (long)iv * n;
+    double np = 0.0;
+    for (int i = tid; i < n; i += EI_THREADS) np += z[i] * z[i];
+    for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
+    if (lane == 0) red[wv] = np;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < nw; ++k) t += red[k];
+    const double inv = 1.0 / sqrt(t);
+    for (int i = tid; i < n; i += EI_THREADS) z[i] *= inv;
+    __syncthreads();
+  };
+  // start vectors: unit length, then orthogonal to the earlier members of their cluster (inside a
+  // cluster of equal eigenvalues all solves amplify the same directions)
+  normalise_all();
+  for (int iv = 1; iv < kvec; ++iv)
+    if (j0s[iv] < iv) {
+      cgs_rows(Z, n, j0s[iv], iv, coef);
+      normalise_one(iv);
+    }
+  // three solves; after each, every vector normalised, then the members of a cluster in order
+  // against the earlier (final, unit) ones by classical Gram-Schmidt twice and normalised again
+  for (int it = 0; it < 3; ++it) {
+    if (wv == 0 && lane < kvec) {
+      if (it == 0) lane_solve<true>(d, e, n, w[lane], pivlu, Z + (long)lane * n, F + 5L * n * lane);
+      else lane_solve<false>(d, e, n, w[lane], pivlu, Z + (long)lane * n, F + 5L * n * lane);
+    }
+    __syncthreads();
+    normalise_all();
+    for (int iv = 1; iv < kvec; ++iv)
+      if (j0s[iv] < iv) {
+        cgs_rows(Z, n, j0s[iv], iv, coef);
+        cgs_rows(Z, n, j0s[iv], iv, coef);
+        normalise_one(iv);
+      }
+  }
+  // residual of every eigenpair of the tridiagonal matrix (a wave per vector); the negated
+  // comparison also flags NaN
+  for (int iv = wv; iv < kvec; iv += nw) {
+    const double* z = Z + (long)iv * n;
+    const double lam = w[iv];
+    double rr = 0.0;
+    for (int i = lane; i < n; i += 64) {
+      double r = (d[i] - lam) * z[i];
+      if (i > 0) r += e[i - 1] * z[i - 1];
+      if (i + 1 < n) r += e[i] * z[i + 1];
+      rr += r * r;
+    }
+    for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
+    if (lane == 0 && !(sqrt(rr) <= EIG_RES_TOL * tnorm)) *fail = 1;
+  }
+}
+
+__global__ __launch_bounds__(EI_THREADS) void k_eig_invit(EigBatch eb) {
+  const int b = blockIdx.x;
+  if (b >= eb.count) return;
+  eig_invit_body(eb.n[b], eb.kvec[b], eb.w[b], eb.scratch[b], eb.tail[b], eb.fail[b]);
+}
+__global__ __launch_bounds__(EI_THREADS) void k_eig_invit_list(const EigDesc* __restrict__ list) {
+  const EigDesc ds = list[blockIdx.x];
+  eig_invit_body(ds.n, ds.kvec, ds.w, ds.scratch, ds.tail, ds.fail);
+}
+
+// Back-transformation of vector iv = blockIdx.x (one wave): the reflectors are read two ahead
+// of their use.
+__device__ void eig_backtr_body(const int n, const int kvec, const double* __restrict__ R, double* __restrict__ V) {
+  if (!eig_split(n, kvec)) return;
+  const int iv = blockIdx.x;
+  if (iv >= kvec) return;
+  constexpr int PER = EIG_MAXN / 64;
+  const int lane = threadIdx.x;
+  const double* Z = R + (long)n * n;
+  double y[PER], v0[PER], v1[PER];
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int i = lane + 64 * t;
+    y[t] = i < n ? Z[(long)iv * n + i] : 0.0;
+  }
+  auto load = [&](double* v, int k) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int i = lane + 64 * t;
+      v[t] = (k >= 0 && i < n) ? R[(long)k * n + i] : 0.0;
+    }
+  };
+  auto apply = [&](const double* v) {
+    double dp = 0.0;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) dp += v[t] * y[t];
+    for (int o = 32; o > 0; o >>= 1) dp += __shfl_xor(dp, o);
+#pragma unroll
+    for (int t = 0; t < PER; ++t) y[t] -= 2.0 * dp * v[t];
+  };
+  load(v0, n - 3);
+  load(v1, n - 4);
+  for (int k = n - 3; k >= 0; k -= 2) {
+    apply(v0);
+    load(v0, k - 2);
+    if (k - 1 < 0) break;
+    apply(v1);
+    load(v1, k - 3);
+  }
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int i = lane + 64 * t;
+    if (i < n) V[(long)i * n + iv] = y[t];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_eig_backtr(EigBatch eb) {
+  const int b = blockIdx.y;
+  if (b >= eb.count) return;
+  eig_backtr_body(eb.n[b], eb.kvec[b], eb.scratch[b], eb.V[b]);
+}
+__global__ __launch_bounds__(64) void k_eig_backtr_list(const EigDesc* __restrict__ list) {
+  const EigDesc ds = list[blockIdx.y];
+  eig_backtr_body(ds.n, ds.kvec, ds.scratch, ds.V);
 }
 
 // ---------------------------------------------------------------------------

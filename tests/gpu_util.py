@@ -70,5 +70,22 @@ def eigh(A_batch):
     return w.cpu().numpy().reshape(batch, n), V.cpu().numpy().reshape(batch, n, n)
 
 
+def eigh_lead(A_batch, kvec):
+    """hotrg_debug_eigh_lead: resolved eigenvalues (descending, zeros after them), the sum of the
+    others per matrix, and the leading kvec eigenvectors as columns."""
+    batch, n, _ = A_batch.shape
+    Ad = dev(A_batch)
+    w = torch.zeros(batch * n, dtype=torch.float64, device="cuda")
+    V = torch.zeros(batch * n * n, dtype=torch.float64, device="cuda")
+    tail = torch.zeros(batch, dtype=torch.float64, device="cuda")
+    nbytes = P.hotrg_debug_eigh_workspace_bytes(n, batch)
+    ws, wptr = workspace(nbytes)
+    P.hotrg_debug_eigh_lead(n, batch, kvec, Ad.data_ptr(), w.data_ptr(), V.data_ptr(), tail.data_ptr(), wptr, nbytes,
+                            stream_ptr())
+    torch.cuda.synchronize()
+    return (w.cpu().numpy().reshape(batch, n), tail.cpu().numpy(),
+            V.cpu().numpy().reshape(batch, n, n)[:, :, :kvec])
+
+
 def relerr(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))

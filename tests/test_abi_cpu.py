@@ -144,6 +144,16 @@ def test_supplied_tensor_argument_validation():
     assert e.value.code == P.HOTRG_E_ARG
 
 
+def test_truncated_eigensolver_argument_validation():
+    # kvec outside 1 .. n and missing buffers are refused before anything touches a device
+    L = P.lib()
+    ws = ctypes.c_void_p(16)
+    for n, batch, kvec in [(256, 1, 0), (256, 1, 257), (2000, 1, 8), (256, 5, 8)]:
+        rc = L.hotrg_debug_eigh_lead(n, batch, kvec, ws, ws, ws, None, ws, 1 << 30, None)
+        assert rc == P.HOTRG_E_ARG, (n, batch, kvec)
+    assert L.hotrg_debug_eigh_lead(256, 1, 16, None, ws, ws, None, ws, 1 << 30, None) == P.HOTRG_E_ARG
+
+
 def test_eigh_workspace_holds_the_failure_flag():
     assert P.hotrg_debug_eigh_workspace_bytes(256, 4) >= 4 * 2 * 256 * 256 * 8 + 4
 

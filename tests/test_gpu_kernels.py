@@ -189,6 +189,42 @@ def test_eigh_matches_library(n):
         assert np.linalg.norm(V[b].T @ V[b] - np.eye(n)) < 1e-13 * n
 
 
+@pytest.mark.parametrize("n,kvec", [(256, 16), (576, 24), (1024, 32), (200, 40), (256, 64)])
+def test_eigh_leading_vectors_match_library(n, kvec):
+    """The solver of a truncating step: only the leading kvec eigenvectors (n >= 128 and 6 kvec <= n:
+    the kernels spread over many workgroups; (200, 40) and (256, 64): the one-workgroup solver).
+    Leading eigenvalues, the sum of the unresolved ones, residuals and orthonormality of the
+    vectors, and the kept subspace against LAPACK."""
+    rng = np.random.default_rng(n + kvec)
+    batch = 2
+    A = np.zeros((batch, n, n))
+    for b in range(batch):
+        Q = SI.random_isometry(n, n, seed=300 + n + b)
+        lam = np.exp(-0.35 * np.arange(n)) * (1 + 0.1 * rng.random(n))
+        lam[2] = lam[3]                                  # an exact doublet
+        lam[kvec + 3] = lam[kvec + 4]
+        A[b] = (Q * lam) @ Q.T
+        A[b] = 0.5 * (A[b] + A[b].T)
+    w, tail, V = gu.eigh_lead(A.copy(), kvec)
+    nev = n if n <= 256 else max(kvec + 1, 24)
+    u = 2.0 ** -52
+    for b in range(batch):
+        ref, Vr = np.linalg.eigh(A[b])
+        ref, Vr = ref[::-1], Vr[:, ::-1]
+        np.testing.assert_allclose(w[b, :nev], ref[:nev], rtol=0, atol=2 * n * u * abs(ref[0]))
+        assert np.all(w[b, nev:] == 0.0)
+        assert abs(tail[b] - ref[nev:].sum()) <= 4 * n * u * (abs(ref[0]) + np.trace(A[b]))
+        res = np.linalg.norm(A[b] @ V[b] - V[b] * w[b, :kvec][None, :])
+        orth = np.linalg.norm(V[b].T @ V[b] - np.eye(kvec))
+        gap = ref[kvec - 1] - ref[kvec]
+        sub = np.linalg.norm(V[b] @ V[b].T - Vr[:, :kvec] @ Vr[:, :kvec].T)
+        print(f"n={n} kvec={kvec}: residual {res:.1e}, orthogonality {orth:.1e}, subspace {sub:.1e} "
+              f"(gap {gap:.1e}), tail {tail[b]:.6e} vs {ref[nev:].sum():.6e}")
+        assert res < 1e-13 * abs(ref[0]) * n
+        assert orth < 1e-13 * n
+        assert sub < 100 * n * u * abs(ref[0]) / gap
+
+
 def _near_tridiagonal(n, eps, seed):
     rng = np.random.default_rng(seed)
     B = np.diag(2 + rng.random(n)) + np.diag(0.5 * rng.random(n - 1), 1)
