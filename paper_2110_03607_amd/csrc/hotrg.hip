@@ -308,8 +308,9 @@ void enqueue_tri_steps(const EigBatch& eb, hipStream_t s) {
   for (int i = 0; i < eb.count; ++i) maxn = std::max(maxn, eb.n[i]);
   if (maxn < TRI_MULTI_N) return;
   const unsigned gx = (unsigned)((maxn - 1 + TRI_ROWS - 1) / TRI_ROWS);
-  for (int st = 0; st <= maxn - 2; ++st)
+  for (int st = 0; st < tri_lds_start(maxn); ++st)
     hipLaunchKernelGGL(k_tri_step, dim3(gx, (unsigned)eb.count), dim3(256), 0, s, eb, st);
+  hipLaunchKernelGGL(k_tri_finish, dim3((unsigned)eb.count), dim3(EIG_THREADS), 0, s, eb);
 }
 
 // After enqueue_tri_steps: eigenpairs of every matrix of eb, by the one-workgroup solver or,
@@ -1936,10 +1937,12 @@ static int batch_enqueue(hotrg_batch* b, const std::vector<StepPlan>& sps, const
     if (rc) return batch_fail(b, rc, "instance " + std::to_string(i) + ": " + b->inst[i]->err);
   }
   if (ndesc > 0) {
-    if (maxn >= TRI_MULTI_N)
-      for (int st = 0; st <= maxn - 2; ++st)
+    if (maxn >= TRI_MULTI_N) {
+      for (int st = 0; st < tri_lds_start(maxn); ++st)
         hipLaunchKernelGGL(k_tri_step_list, dim3((unsigned)((maxn - 1 + TRI_ROWS - 1) / TRI_ROWS), (unsigned)ndesc),
                            dim3(256), 0, b->s, table, st);
+      hipLaunchKernelGGL(k_tri_finish_list, dim3((unsigned)ndesc), dim3(EIG_THREADS), 0, b->s, table);
+    }
     if (L.whole) hipLaunchKernelGGL(k_eigh_list, dim3((unsigned)ndesc), dim3(EIG_THREADS), 0, b->s, table);
     if (L.bisect_blocks) {
       hipLaunchKernelGGL(k_eig_bisect_list, dim3((unsigned)L.bisect_blocks, (unsigned)ndesc), dim3(EB_THREADS), 0, b->s,

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace hk {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -102,6 +104,7 @@ __device__ inline void store_vec(typename Store<F>::T* p, long i, long plane, co
 template <> struct Store<F_FP64> {
   typedef double T;
   __device__ static void put(T* p, long i, long, double x) { p[i] = x; }
+  __device__ static void putf(T* p, long i, long, float x) { p[i] = (double)x; }
   __device__ static void put4(T* p, long i, long, const double* x) {
     for (int j = 0; j < 4; ++j) p[i + j] = x[j];
   }
@@ -109,6 +112,7 @@ template <> struct Store<F_FP64> {
 template <> struct Store<F_FP32> {
   typedef float T;
   __device__ static void put(T* p, long i, long, double x) { p[i] = (float)x; }
+  __device__ static void putf(T* p, long i, long, float x) { p[i] = x; }
   __device__ static void put4(T* p, long i, long, const double* x) {
     f4v v;
     v.x = (float)x[0]; v.y = (float)x[1]; v.z = (float)x[2]; v.w = (float)x[3];
@@ -118,6 +122,7 @@ template <> struct Store<F_FP32> {
 template <> struct Store<F_BF16> {
   typedef uint16_t T;
   __device__ static void put(T* p, long i, long, double x) { p[i] = f32_to_bf16_rne((float)x); }
+  __device__ static void putf(T* p, long i, long, float x) { p[i] = f32_to_bf16_rne(x); }
   __device__ static void put4(T* p, long i, long, const double* x) {
     u16x4 v;
     v.x = f32_to_bf16_rne((float)x[0]); v.y = f32_to_bf16_rne((float)x[1]);
@@ -128,6 +133,7 @@ template <> struct Store<F_BF16> {
 template <> struct Store<F_FP16> {
   typedef _Float16 T;
   __device__ static void put(T* p, long i, long, double x) { p[i] = (_Float16)(float)x; }
+  __device__ static void putf(T* p, long i, long, float x) { p[i] = (_Float16)x; }
   __device__ static void put4(T* p, long i, long, const double* x) {
     h4v v;
     v.x = (_Float16)(float)x[0]; v.y = (_Float16)(float)x[1]; v.z = (_Float16)(float)x[2]; v.w = (_Float16)(float)x[3];
@@ -136,6 +142,11 @@ template <> struct Store<F_FP16> {
 };
 template <> struct Store<F_SPLIT_BF16> {
   typedef uint16_t T;
+  __device__ static void putf(T* p, long i, long plane, float xf) {
+    const uint16_t hi = f32_to_bf16_rne(xf);
+    p[i] = hi;
+    p[i + plane] = f32_to_bf16_rne(xf - bf16_to_f32(hi));
+  }
   __device__ static void put(T* p, long i, long plane, double x) {
     float xf = (float)x;
     uint16_t hi = f32_to_bf16_rne(xf);
@@ -157,6 +168,11 @@ template <> struct Store<F_SPLIT_BF16> {
 };
 template <> struct Store<F_SPLIT_FP16> {
   typedef _Float16 T;
+  __device__ static void putf(T* p, long i, long plane, float xf) {
+    const _Float16 hi = (_Float16)xf;
+    p[i] = hi;
+    p[i + plane] = (_Float16)(xf - (float)hi);
+  }
   __device__ static void put(T* p, long i, long plane, double x) {
     float xf = (float)x;
     _Float16 hi = (_Float16)xf;
@@ -176,6 +192,78 @@ template <> struct Store<F_SPLIT_FP16> {
     *reinterpret_cast<h4v*>(p + i + plane) = l;
   }
 };
+
+// Four consecutive elements given in FP32 (an FP32 product times a power-of-two scale, so the
+// value is the one the double path would round to FP32 first): the same stored bits as
+// store_vec<F, 4> on their double values, with the conversions in FP32 only (FP16 from FP32 is
+// one instruction; from FP64 it is a long integer sequence).
+template <int F>
+__device__ inline void store4_f32(typename Store<F>::T* p, long i, long plane, const float* x) {
+  if constexpr (F == F_FP16 || F == F_SPLIT_FP16) {
+    h4v h, l;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const _Float16 hi = (_Float16)x[j];
+      h[j] = hi;
+      l[j] = (_Float16)(x[j] - (float)hi);
+    }
+    *reinterpret_cast<h4v*>(p + i) = h;
+    if constexpr (F == F_SPLIT_FP16) *reinterpret_cast<h4v*>(p + i + plane) = l;
+  } else if constexpr (F == F_BF16 || F == F_SPLIT_BF16) {
+    u16x4 h, l;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint16_t hi = f32_to_bf16_rne(x[j]);
+      h[j] = hi;
+      l[j] = f32_to_bf16_rne(x[j] - bf16_to_f32(hi));
+    }
+    *reinterpret_cast<u16x4*>(p + i) = h;
+    if constexpr (F == F_SPLIT_BF16) *reinterpret_cast<u16x4*>(p + i + plane) = l;
+  } else if constexpr (F == F_FP32) {
+    f4v v;
+    v.x = x[0]; v.y = x[1]; v.z = x[2]; v.w = x[3];
+    *reinterpret_cast<f4v*>(p + i) = v;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) p[i + j] = (double)x[j];
+  }
+}
+
+// Element(s) of an operand computed in the master type MT and scaled by s (1, or a power of two
+// in the FP16 forms): for an FP32 master the scaled value is exact in FP32, so it is stored from
+// FP32 (the same bits as through FP64, without the compiler's FP64-to-FP16 conversion sequence).
+template <int F, class MT>
+__device__ inline void put_scaled(typename Store<F>::T* p, long i, long plane, MT x, double s) {
+  if constexpr (std::is_same<MT, float>::value) Store<F>::putf(p, i, plane, x * (float)s);
+  else Store<F>::put(p, i, plane, (double)x * s);
+}
+template <int F, int VEC, class MT>
+__device__ inline void store_vec_scaled(typename Store<F>::T* p, long i, long plane, const MT* x, double s) {
+  if constexpr (std::is_same<MT, float>::value) {
+    float v[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) v[e] = x[e] * (float)s;
+    if constexpr (VEC == 8 && (F == F_FP16 || F == F_SPLIT_FP16)) {   // one 16-byte store per plane
+      h8v h, l;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const _Float16 hi = (_Float16)v[j];
+        h[j] = hi;
+        l[j] = (_Float16)(v[j] - (float)hi);
+      }
+      *reinterpret_cast<h8v*>(p + i) = h;
+      if constexpr (F == F_SPLIT_FP16) *reinterpret_cast<h8v*>(p + i + plane) = l;
+    } else {
+#pragma unroll
+      for (int q = 0; q < VEC; q += 4) store4_f32<F>(p, i + q, plane, v + q);
+    }
+  } else {
+    double v[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) v[e] = (double)x[e] * s;
+    store_vec<F, VEC>(p, i, plane, v);
+  }
+}
 
 template <int F> struct FormInfo {
   static constexpr bool fp16 = (F == F_FP16 || F == F_SPLIT_FP16);
@@ -929,8 +1017,7 @@ __global__ void k_make_a(const MT* __restrict__ T, int H, typename Store<F>::T* 
   const long plane = Mp * ld;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < Mp * Kp; i += (long)gridDim.x * blockDim.x) {
     const long m = i / Kp, k = i % Kp;
-    const double x = (m < H && k < H) ? (double)T[m * H + k] * sA : 0.0;
-    Store<F>::put(A, m * ld + off + k, plane, x);
+    put_scaled<F>(A, m * ld + off + k, plane, (m < H && k < H) ? T[m * H + k] : (MT)0, sA);
   }
 }
 
@@ -1092,11 +1179,11 @@ __device__ inline void lu_solve(double* z, int n, const double* ri, const double
 
 constexpr int TRI_MULTI_N = 128;
 
-// Large matrices whose kept eigenvectors are few (n >= TRI_MULTI_N, kvec <= 64 and 6 kvec <= n: the
+// Large matrices whose kept eigenvectors are few (n >= TRI_MULTI_N, kvec <= 64 and 7 kvec <= n: the
 // Gram matrices of a truncating step) finish in the split kernels k_eig_bisect, k_eig_invit and
 // k_eig_backtr, spread over many workgroups; the others in eigh_tri_body.
 __host__ __device__ inline bool eig_split(int n, int kvec) {
-  return n >= TRI_MULTI_N && kvec >= 1 && kvec <= 64 && 6 * kvec <= n;
+  return n >= TRI_MULTI_N && kvec >= 1 && kvec <= 64 && 7 * kvec <= n;
 }
 // Eigenvalues resolved one by one (see eigh_tri_body).
 __host__ __device__ inline int eig_nev(int n, int kvec) {
@@ -1490,8 +1577,13 @@ __device__ inline double block_sum256(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
+// Trailing blocks of up to TRI_LDS_M rows are finished in LDS by one workgroup (k_tri_finish):
+// the multi-workgroup steps run for s < tri_lds_start(n) only.
+constexpr int TRI_LDS_M = 128;
+__host__ __device__ inline int tri_lds_start(int n) { return n > TRI_LDS_M ? n - TRI_LDS_M : 0; }
+
 __device__ void tri_step(const int n, double* __restrict__ A, double* __restrict__ R, const int s) {
-  if (n < TRI_MULTI_N || s > n - 2) return;
+  if (n < TRI_MULTI_N || s >= tri_lds_start(n)) return;
   __shared__ double vp[EIG_MAXN], pp[EIG_MAXN], vs[EIG_MAXN];
   __shared__ double red[4];
   double* Z = R + (long)n * n;
@@ -1565,6 +1657,113 @@ __device__ void tri_step(const int n, double* __restrict__ A, double* __restrict
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (lane == 0) qcur[i] = acc;
   }
+}
+
+// The last TRI_LDS_M - 2 reflectors of a large matrix, one workgroup with the trailing block
+// [s0, n)^2 (s0 = tri_lds_start(n)) in LDS, in k_tri_step's lazy order: step k forms column k
+// with the pending rank-2 update of reflector k - 1, then one pass over the trailing rows
+// applies that update and forms q_k = A' v_k (a wave per row, the wave's share of v . q on the
+// side, so p_k = q_k - (v_k . q_k) v_k needs no reduction of its own).  Four barriers per
+// reflector.  The reflectors, the diagonal and the subdiagonal go where k_tri_step writes them.
+__device__ void tri_finish(const int n, const double* __restrict__ A, double* __restrict__ R) {
+  if (n < TRI_MULTI_N) return;
+  __shared__ double B[TRI_LDS_M * TRI_LDS_M];
+  __shared__ double vb[2][TRI_LDS_M], qb[2][TRI_LDS_M], yv[TRI_LDS_M];
+  __shared__ double red[EIG_THREADS / 64], vq[EIG_THREADS / 64];
+  const int s0 = tri_lds_start(n), m = n - s0;
+  double* Z = R + (long)n * n;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+  // pending update of reflector s0 - 1 (none when s0 = 0): v and q over [s0, n), v . q into vq
+  {
+    const double* qprev = Z + 2 * n + ((s0 - 1) & 1) * n;
+    double cp = 0.0;
+    for (int i = tid; i < m; i += nt) {
+      const double v = s0 > 0 ? R[(long)(s0 - 1) * n + s0 + i] : 0.0;
+      const double q = s0 > 0 ? qprev[s0 + i] : 0.0;
+      vb[1][i] = v;
+      qb[1][i] = q;
+      cp += v * q;
+    }
+    const double c0 = block_sum(cp, red);
+    if (tid < nw) vq[tid] = tid == 0 ? c0 : 0.0;
+    for (int idx = tid; idx < m * m; idx += nt) B[idx] = A[(long)(s0 + idx / m) * n + s0 + idx % m];
+    __syncthreads();
+  }
+  for (int k = 0; k + 2 < m; ++k) {
+    const int s = s0 + k, cur = k & 1, prv = cur ^ 1;
+    const double* vp = vb[prv];
+    const double* qp = qb[prv];
+    double c = 0.0;
+    for (int w = 0; w < nw; ++w) c += vq[w];                 // v . q of the pending reflector
+    // column k with the pending update: y_i = B[i][k] - 2 (v_i p_k + p_i v_k), p = q - c v
+    const double pk = qp[k] - c * vp[k], vk = vp[k];
+    double ss = 0.0;
+    for (int i = k + tid; i < m; i += nt) {
+      const double y = B[i * m + k] - 2.0 * (vp[i] * pk + (qp[i] - c * vp[i]) * vk);
+      yv[i] = y;
+      if (i >= k + 2) ss += y * y;
+    }
+    const double tail = block_sum(ss, red);                  // (barriers inside: yv visible)
+    const double x0 = yv[k + 1];
+    const bool refl = tail > 0.0;
+    const double sigma = x0 * x0 + tail;
+    const double alpha = (x0 >= 0.0 ? -1.0 : 1.0) * sqrt(sigma);
+    const double inv = refl ? 1.0 / sqrt(2.0 * (sigma - x0 * alpha)) : 0.0;
+    double* vc = vb[cur];
+    for (int i = tid; i < m; i += nt) vc[i] = i <= k ? 0.0 : (i == k + 1 ? x0 - alpha : yv[i]) * inv;
+    if (tid == 0) {
+      Z[s] = yv[k];
+      Z[n + s] = refl ? alpha : x0;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += nt) R[(long)s * n + i] = i > s ? vc[i - s0] : 0.0;
+    // rows k+1 .. m-1: apply the pending update, q_k = A' v_k, and this wave's share of v_k . q_k
+    double* qc = qb[cur];
+    double part = 0.0;
+    for (int i = k + 1 + wv; i < m; i += nw) {
+      double* row = B + i * m;
+      const double vi = vp[i], pi = qp[i] - c * vp[i];
+      double acc = 0.0;
+      for (int j = k + 1 + lane; j < m; j += 64) {
+        const double a = row[j] - 2.0 * (vi * (qp[j] - c * vp[j]) + pi * vp[j]);
+        row[j] = a;
+        acc += a * vc[j];
+      }
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (lane == 0) qc[i] = acc;
+      part += acc * vc[i];
+    }
+    if (lane == 0) vq[wv] = part;   // (c was read before the barriers of block_sum above)
+    __syncthreads();
+  }
+  // last two rows: the pending update of the last reflector on the 2 x 2 block (as k_tri_step)
+  {
+    const int cur = (m - 2) & 1, prv = cur ^ 1;
+    const double* vp = vb[prv];
+    const double* qp = qb[prv];
+    double c = 0.0;
+    for (int w = 0; w < nw; ++w) c += vq[w];
+    if (tid == 0) {
+      const int a = m - 2, b = m - 1;
+      const double pa = qp[a] - c * vp[a], pbv = qp[b] - c * vp[b];
+      Z[n - 2] = B[a * m + a] - 4.0 * vp[a] * pa;
+      Z[n + n - 2] = B[b * m + a] - 2.0 * (vp[b] * pa + pbv * vp[a]);
+      Z[n - 1] = B[b * m + b] - 4.0 * vp[b] * pbv;
+      Z[n + n - 1] = 0.0;
+    }
+  }
+  for (int i = tid; i < 2 * n; i += nt) R[(long)(n - 2) * n + i] = 0.0;   // no reflector for the last two
+}
+
+__global__ __launch_bounds__(EIG_THREADS) void k_tri_finish(EigBatch eb) {
+  const int b = blockIdx.x;
+  if (b >= eb.count) return;
+  tri_finish(eb.n[b], eb.A[b], eb.scratch[b]);
+}
+
+__global__ __launch_bounds__(EIG_THREADS) void k_tri_finish_list(const EigDesc* __restrict__ list) {
+  const EigDesc ds = list[blockIdx.x];
+  tri_finish(ds.n, ds.A, ds.scratch);
 }
 
 __global__ __launch_bounds__(256) void k_tri_step(EigBatch eb, int s) {
@@ -1710,19 +1909,22 @@ __global__ __launch_bounds__(EB_THREADS) void k_eig_bisect_list(const EigDesc* _
   eig_bisect_body(ds.n, ds.kvec, ds.scratch + (long)ds.n * ds.n, ds.w, ds.fail);
 }
 
-// One lane's inverse-iteration solve z <- (T - lam I)^{-1} z (z: the lane's row of Z).  With
-// factor = true the LU factorisation of T - lam I (as lu_shifted) is made on the way and stored
-// (f: ri, u1, u2, l, pivot flag, n doubles each); else the stored one is used (as lu_solve).
-// Loads run ahead of the serial recurrences in blocks of EI_BLK rows.
+// One lane's inverse-iteration solve z <- (T - lam I)^{-1} z.  The lanes' vectors and factors are
+// interleaved (element r of a lane's array at [r S], S = the number of lanes), so one load of row r
+// is one contiguous run across the lanes.  With factor = true the LU factorisation of T - lam I
+// (as lu_shifted) is made on the way and stored (f: ri, u1, u2, l, pivot flag, n S doubles each);
+// else the stored one is used (as lu_solve).  Loads run ahead of the serial recurrences in blocks
+// of EI_BLK rows.
 constexpr int EI_BLK = 16;
 template <bool FACTOR>
 __device__ inline void lane_solve(const double* d, const double* e, int n, double lam, double pivlu,
-                                  double* __restrict__ z, double* __restrict__ f) {
+                                  double* __restrict__ z, double* __restrict__ f, int S) {
+  const long NS = (long)n * S;
   double* ri = f;
-  double* u1 = f + n;
-  double* u2 = f + 2 * n;
-  double* lq = f + 3 * n;
-  double* pv = f + 4 * n;
+  double* u1 = f + NS;
+  double* u2 = f + 2 * NS;
+  double* lq = f + 3 * NS;
+  double* pv = f + 4 * NS;
   // forward: row operations, the value of row r carried in cur
   double cur = z[0];
   double a0 = d[0] - lam, b0 = n > 1 ? e[0] : 0.0, c0 = 0.0;   // LU: current row (diag, super, super2)
@@ -1731,16 +1933,17 @@ __device__ inline void lane_solve(const double* d, const double* e, int n, doubl
 #pragma unroll
     for (int k = 0; k < EI_BLK; ++k) {
       const int r = r0 + k;
-      zn[k] = r + 1 < n ? z[r + 1] : 0.0;
+      zn[k] = r + 1 < n ? z[(long)(r + 1) * S] : 0.0;
       if (!FACTOR) {
-        lb[k] = r + 1 < n ? lq[r] : 0.0;
-        pb[k] = r + 1 < n ? pv[r] : 0.0;
+        lb[k] = r + 1 < n ? lq[(long)r * S] : 0.0;
+        pb[k] = r + 1 < n ? pv[(long)r * S] : 0.0;
       }
     }
 #pragma unroll
     for (int k = 0; k < EI_BLK; ++k) {
       const int r = r0 + k;
       if (r + 1 >= n) break;
+      const long o = (long)r * S;
       double l, p;
       if (FACTOR) {
         const double sub = e[r];
@@ -1748,34 +1951,35 @@ __device__ inline void lane_solve(const double* d, const double* e, int n, doubl
         if (fabs(sub) > fabs(a0)) {
           l = a0 / sub;
           p = 1.0;
-          ri[r] = 1.0 / sub; u1[r] = dn; u2[r] = en;
+          ri[o] = 1.0 / sub; u1[o] = dn; u2[o] = en;
           a0 = b0 - l * dn;
           b0 = c0 - l * en;
         } else {
           const double piv = fabs(a0) < pivlu ? (a0 < 0.0 ? -pivlu : pivlu) : a0;
           l = sub / piv;
           p = 0.0;
-          ri[r] = 1.0 / piv; u1[r] = b0; u2[r] = c0;
+          ri[o] = 1.0 / piv; u1[o] = b0; u2[o] = c0;
           a0 = dn - l * b0;
           b0 = en - l * c0;
         }
         c0 = 0.0;
-        lq[r] = l;
-        pv[r] = p;
+        lq[o] = l;
+        pv[o] = p;
       } else {
         l = lb[k];
         p = pb[k];
       }
       const double nxt = zn[k];
-      if (p != 0.0) { z[r] = nxt; cur = cur - l * nxt; }
-      else { z[r] = cur; cur = nxt - l * cur; }
+      if (p != 0.0) { z[o] = nxt; cur = cur - l * nxt; }
+      else { z[o] = cur; cur = nxt - l * cur; }
     }
   }
+  const long last = (long)(n - 1) * S;
   if (FACTOR) {
     const double piv = fabs(a0) < pivlu ? (a0 < 0.0 ? -pivlu : pivlu) : a0;
-    ri[n - 1] = 1.0 / piv; u1[n - 1] = 0.0; u2[n - 1] = 0.0; lq[n - 1] = 0.0; pv[n - 1] = 0.0;
+    ri[last] = 1.0 / piv; u1[last] = 0.0; u2[last] = 0.0; lq[last] = 0.0; pv[last] = 0.0;
   }
-  z[n - 1] = cur;
+  z[last] = cur;
   // backward substitution with U (three diagonals)
   double x1 = 0.0, x2 = 0.0;
   for (int r0 = n - 1; r0 >= 0; r0 -= EI_BLK) {
@@ -1783,17 +1987,18 @@ __device__ inline void lane_solve(const double* d, const double* e, int n, doubl
 #pragma unroll
     for (int k = 0; k < EI_BLK; ++k) {
       const int r = r0 - k;
-      zb[k] = r >= 0 ? z[r] : 0.0;
-      ib[k] = r >= 0 ? ri[r] : 0.0;
-      ab[k] = r >= 0 ? u1[r] : 0.0;
-      bb[k] = r >= 0 ? u2[r] : 0.0;
+      const long o = (long)r * S;
+      zb[k] = r >= 0 ? z[o] : 0.0;
+      ib[k] = r >= 0 ? ri[o] : 0.0;
+      ab[k] = r >= 0 ? u1[o] : 0.0;
+      bb[k] = r >= 0 ? u2[o] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < EI_BLK; ++k) {
       const int r = r0 - k;
       if (r < 0) break;
       const double x = (zb[k] - ab[k] * x1 - bb[k] * x2) * ib[k];
-      z[r] = x;
+      z[(long)r * S] = x;
       x2 = x1;
       x1 = x;
     }
@@ -1827,8 +2032,9 @@ __device__ void eig_invit_body(const int n, const int kvec, double* __restrict__
   __shared__ double d[EIG_MAXN], e[EIG_MAXN];
   __shared__ double red[2 * EI_THREADS / 64], coef[64];
   __shared__ int j0s[64];
-  double* Z = R + (long)n * n;          // tridiagonal eigenvector iv at Z[iv n ..), then LU factors
-  double* F = Z + (long)kvec * n;       // factors of vector iv at F[5 n iv ..) (rows kvec .. n-1 of Z)
+  double* Z = R + (long)n * n;          // tridiagonal eigenvector iv at Z[iv n ..)
+  double* Y = Z + (long)kvec * n;       // the vectors interleaved for the solves: Y[r kvec + iv]
+  double* F = Y + (long)kvec * n;       // their LU factors, interleaved the same way (5 n kvec)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = EI_THREADS >> 6;
   for (int i = tid; i < n; i += EI_THREADS) { d[i] = Z[i]; e[i] = Z[n + i]; }
   double lo, hi, tnorm;
@@ -1903,9 +2109,19 @@ __device__ void eig_invit_body(const int n, const int kvec, double* __restrict__
   // three solves; after each, every vector normalised, then the members of a cluster in order
   // against the earlier (final, unit) ones by classical Gram-Schmidt twice and normalised again
   for (int it = 0; it < 3; ++it) {
+    for (long idx = tid; idx < (long)kvec * n; idx += EI_THREADS) {   // Z rows -> Y
+      const int r = (int)(idx / kvec), iv = (int)(idx % kvec);
+      Y[idx] = Z[(long)iv * n + r];
+    }
+    __syncthreads();
     if (wv == 0 && lane < kvec) {
-      if (it == 0) lane_solve<true>(d, e, n, w[lane], pivlu, Z + (long)lane * n, F + 5L * n * lane);
-      else lane_solve<false>(d, e, n, w[lane], pivlu, Z + (long)lane * n, F + 5L * n * lane);
+      if (it == 0) lane_solve<true>(d, e, n, w[lane], pivlu, Y + lane, F + lane, kvec);
+      else lane_solve<false>(d, e, n, w[lane], pivlu, Y + lane, F + lane, kvec);
+    }
+    __syncthreads();
+    for (long idx = tid; idx < (long)kvec * n; idx += EI_THREADS) {   // Y -> Z rows
+      const int iv = (int)(idx / n), r = (int)(idx % n);
+      Z[idx] = Y[(long)r * kvec + iv];
     }
     __syncthreads();
     normalise_all();
@@ -2130,7 +2346,7 @@ __global__ __launch_bounds__(256) void k_pstage(const MT* __restrict__ T, const 
       for (int nc2 = 0; nc2 < chi2; ++nc2) s += z[nc2] * (MT)U2[(nh2 + chi2 * nc2) * dm.k2 + n2];
       const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
       if constexpr (ACC) B[row * ldb + (long)rho * b + r] += s;
-      else Store<F>::put(B, row * ldb + (long)rho * b + r, bplane, (double)s * sB);
+      else put_scaled<F>(B, row * ldb + (long)rho * b + r, bplane, s, sB);
     }
   } else {
     for (int i = tid; i < npairs * b; i += blockDim.x) {
@@ -2139,7 +2355,7 @@ __global__ __launch_bounds__(256) void k_pstage(const MT* __restrict__ T, const 
       for (int nc1 = 0; nc1 < chi1; ++nc1) s += (MT)U1[(nh1 + chi1 * nc1) * dm.k1 + pr] * X[nc1];
       const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
       if constexpr (ACC) B[row * ldb + (long)rho * b + nh1] += s;
-      else Store<F>::put(B, row * ldb + (long)rho * b + nh1, bplane, (double)s * sB);
+      else put_scaled<F>(B, row * ldb + (long)rho * b + nh1, bplane, s, sB);
     }
   }
 }
@@ -2204,7 +2420,7 @@ __global__ __launch_bounds__(256) void k_pstage3(const MT* __restrict__ T, const
             if (nc2 < chi2) s += z[nc2] * u[nc2 * chi2];
           const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
           if constexpr (ACC) B[row * ldb + (long)rho * b + r] += s;
-          else Store<F>::put(B, row * ldb + (long)rho * b + r, bplane, (double)s * sB);
+          else put_scaled<F>(B, row * ldb + (long)rho * b + r, bplane, s, sB);
         }
       }
     }
@@ -2279,11 +2495,8 @@ __global__ __launch_bounds__(256) void k_pstage3v(const MT* __restrict__ T, cons
 #pragma unroll
             for (int e = 0; e < VEC; ++e) sv[e] += z[nc2] * uu[e];
           }
-        double v[VEC];
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) v[e] = (double)sv[e] * sB;
         const long row = (long)((pr - pr0) * dm.chic + cp) * b + nc;
-        store_vec<F, VEC>(B, row * ldb + (long)rho * b + r0, bplane, v);
+        store_vec_scaled<F, VEC>(B, row * ldb + (long)rho * b + r0, bplane, sv, sB);
       }
     }
   }
@@ -2315,6 +2528,7 @@ __global__ __launch_bounds__(256) void k_pstage3m(const float* __restrict__ T, c
   if constexpr (ALL16) dm = Dims{3, 16, 16, 16, 16, 16, 256, 4096};
   const int b = dm.b, chi1 = dm.chi1, chi2 = dm.chi2, k1 = dm.k1, k2 = dm.k2, chic = dm.chic;
   const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * sqrt((double)b)) : 1.0;
+  const float sBf = (float)sB;
   const int rho = h / b, nc = h % b;
   const int mtot = k2 * chi2, nmb = (mtot + 15) >> 4;
   {
@@ -2362,11 +2576,11 @@ __global__ __launch_bounds__(256) void k_pstage3m(const float* __restrict__ T, c
         // acc[i] = OUT[m = 16 mb + 4 bq + i][nh1' = bn]
         const int m = 16 * mb + 4 * bq, n2 = m / chi2, nh2 = m % chi2, pr = n1 * k2 + n2;
         if (m >= mtot || bn >= chi1 || pr < pr0 || pr >= pr1) continue;
-        double v[4];
+        float v[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = (double)acc[i] * sB;
+        for (int i = 0; i < 4; ++i) v[i] = acc[i] * sBf;   // sB is a power of two: exact
         const long row = (long)((pr - pr0) * chic + cp) * b + nc;
-        store_vec<F, 4>(B, row * ldb + (long)rho * b + bn * chi2 + nh2, bplane, v);
+        store4_f32<F>(B, row * ldb + (long)rho * b + bn * chi2 + nh2, bplane, v);
       }
     }
   }

@@ -191,7 +191,7 @@ def test_eigh_matches_library(n):
 
 @pytest.mark.parametrize("n,kvec", [(256, 16), (576, 24), (1024, 32), (200, 40), (256, 64)])
 def test_eigh_leading_vectors_match_library(n, kvec):
-    """The solver of a truncating step: only the leading kvec eigenvectors (n >= 128 and 6 kvec <= n:
+    """The solver of a truncating step: only the leading kvec eigenvectors (n >= 128 and 7 kvec <= n:
     the kernels spread over many workgroups; (200, 40) and (256, 64): the one-workgroup solver).
     Leading eigenvalues, the sum of the unresolved ones, residuals and orthonormality of the
     vectors, and the kept subspace against LAPACK."""
