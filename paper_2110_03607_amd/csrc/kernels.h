@@ -1198,7 +1198,7 @@ __host__ __device__ inline int eig_nev(int n, int kvec) {
 // an eigenvalue interval is still open after the bisection's iteration cap, or when a computed
 // eigenpair has a residual ||T z - lambda z||_2 above EIG_RES_TOL |T| (|z| = 1).
 constexpr double EIG_RES_TOL = 1e-9;
-__device__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ A, double* __restrict__ w,
+__device__ __forceinline__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ A, double* __restrict__ w,
                               double* __restrict__ V, double* __restrict__ R, const bool tridiag_done,
                               double* __restrict__ tail_out, int* __restrict__ fail) {
   __shared__ double d[EIG_MAXN], e[EIG_MAXN], vv[EIG_MAXN], qv[EIG_MAXN];
@@ -1582,7 +1582,7 @@ __device__ inline double block_sum256(double v, double* red) {
 constexpr int TRI_LDS_M = 128;
 __host__ __device__ inline int tri_lds_start(int n) { return n > TRI_LDS_M ? n - TRI_LDS_M : 0; }
 
-__device__ void tri_step(const int n, double* __restrict__ A, double* __restrict__ R, const int s) {
+__device__ __forceinline__ void tri_step(const int n, double* __restrict__ A, double* __restrict__ R, const int s) {
   if (n < TRI_MULTI_N || s >= tri_lds_start(n)) return;
   __shared__ double vp[EIG_MAXN], pp[EIG_MAXN], vs[EIG_MAXN];
   __shared__ double red[4];
@@ -1660,17 +1660,21 @@ __device__ void tri_step(const int n, double* __restrict__ A, double* __restrict
 }
 
 // The last TRI_LDS_M - 2 reflectors of a large matrix, one workgroup with the trailing block
-// [s0, n)^2 (s0 = tri_lds_start(n)) in LDS, in k_tri_step's lazy order: step k forms column k
-// with the pending rank-2 update of reflector k - 1, then one pass over the trailing rows
-// applies that update and forms q_k = A' v_k (a wave per row, the wave's share of v . q on the
-// side, so p_k = q_k - (v_k . q_k) v_k needs no reduction of its own).  Four barriers per
-// reflector.  The reflectors, the diagonal and the subdiagonal go where k_tri_step writes them.
-__device__ void tri_finish(const int n, const double* __restrict__ A, double* __restrict__ R) {
+// [s0, n)^2 (s0 = tri_lds_start(n)) in LDS (rows padded to an odd number of doubles, so a column
+// read spreads over the banks), in k_tri_step's lazy order: step k forms column k with the
+// pending rank-2 update of reflector k - 1, then one pass over the trailing rows applies that
+// update and forms q_k = A' v_k (a wave per row, each lane's two columns of v, p and v_k in
+// registers; the wave's share of v_k . q_k on the side, so p_k = q_k - (v_k . q_k) v_k needs no
+// reduction of its own).  Four barriers per reflector.  The reflectors, the diagonal and the
+// subdiagonal go where k_tri_step writes them.
+constexpr int TRI_LDS_LD = TRI_LDS_M + 1;
+__device__ __forceinline__ void tri_finish(const int n, const double* __restrict__ A, double* __restrict__ R) {
   if (n < TRI_MULTI_N) return;
-  __shared__ double B[TRI_LDS_M * TRI_LDS_M];
+  __shared__ double B[TRI_LDS_M * TRI_LDS_LD];
   __shared__ double vb[2][TRI_LDS_M], qb[2][TRI_LDS_M], yv[TRI_LDS_M];
   __shared__ double red[EIG_THREADS / 64], vq[EIG_THREADS / 64];
   const int s0 = tri_lds_start(n), m = n - s0;
+  constexpr int L = TRI_LDS_LD;
   double* Z = R + (long)n * n;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
   // pending update of reflector s0 - 1 (none when s0 = 0): v and q over [s0, n), v . q into vq
@@ -1686,7 +1690,10 @@ __device__ void tri_finish(const int n, const double* __restrict__ A, double* __
     }
     const double c0 = block_sum(cp, red);
     if (tid < nw) vq[tid] = tid == 0 ? c0 : 0.0;
-    for (int idx = tid; idx < m * m; idx += nt) B[idx] = A[(long)(s0 + idx / m) * n + s0 + idx % m];
+    for (int idx = tid; idx < m * m; idx += nt) {
+      const int i = idx / m, j = idx - i * m;
+      B[i * L + j] = A[(long)(s0 + i) * n + s0 + j];
+    }
     __syncthreads();
   }
   for (int k = 0; k + 2 < m; ++k) {
@@ -1699,7 +1706,7 @@ __device__ void tri_finish(const int n, const double* __restrict__ A, double* __
     const double pk = qp[k] - c * vp[k], vk = vp[k];
     double ss = 0.0;
     for (int i = k + tid; i < m; i += nt) {
-      const double y = B[i * m + k] - 2.0 * (vp[i] * pk + (qp[i] - c * vp[i]) * vk);
+      const double y = B[i * L + k] - 2.0 * (vp[i] * pk + (qp[i] - c * vp[i]) * vk);
       yv[i] = y;
       if (i >= k + 2) ss += y * y;
     }
@@ -1717,17 +1724,27 @@ __device__ void tri_finish(const int n, const double* __restrict__ A, double* __
     }
     __syncthreads();
     for (int i = tid; i < n; i += nt) R[(long)s * n + i] = i > s ? vc[i - s0] : 0.0;
-    // rows k+1 .. m-1: apply the pending update, q_k = A' v_k, and this wave's share of v_k . q_k
+    // rows k+1 .. m-1: apply the pending update, q_k = A' v_k, and this wave's share of v_k . q_k;
+    // lane l owns columns j0 = k + 1 + l and j1 = j0 + 64 (m <= 128)
+    const int j0 = k + 1 + lane, j1 = j0 + 64;
+    const bool h0 = j0 < m, h1 = j1 < m;
+    const double vp0 = h0 ? vp[j0] : 0.0, pp0 = h0 ? qp[j0] - c * vp[j0] : 0.0, vc0 = h0 ? vc[j0] : 0.0;
+    const double vp1 = h1 ? vp[j1] : 0.0, pp1 = h1 ? qp[j1] - c * vp[j1] : 0.0, vc1 = h1 ? vc[j1] : 0.0;
     double* qc = qb[cur];
     double part = 0.0;
     for (int i = k + 1 + wv; i < m; i += nw) {
-      double* row = B + i * m;
+      double* row = B + i * L;
       const double vi = vp[i], pi = qp[i] - c * vp[i];
       double acc = 0.0;
-      for (int j = k + 1 + lane; j < m; j += 64) {
-        const double a = row[j] - 2.0 * (vi * (qp[j] - c * vp[j]) + pi * vp[j]);
-        row[j] = a;
-        acc += a * vc[j];
+      if (h0) {
+        const double a = row[j0] - 2.0 * (vi * pp0 + pi * vp0);
+        row[j0] = a;
+        acc += a * vc0;
+      }
+      if (h1) {
+        const double a = row[j1] - 2.0 * (vi * pp1 + pi * vp1);
+        row[j1] = a;
+        acc += a * vc1;
       }
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
       if (lane == 0) qc[i] = acc;
@@ -1746,9 +1763,9 @@ __device__ void tri_finish(const int n, const double* __restrict__ A, double* __
     if (tid == 0) {
       const int a = m - 2, b = m - 1;
       const double pa = qp[a] - c * vp[a], pbv = qp[b] - c * vp[b];
-      Z[n - 2] = B[a * m + a] - 4.0 * vp[a] * pa;
-      Z[n + n - 2] = B[b * m + a] - 2.0 * (vp[b] * pa + pbv * vp[a]);
-      Z[n - 1] = B[b * m + b] - 4.0 * vp[b] * pbv;
+      Z[n - 2] = B[a * L + a] - 4.0 * vp[a] * pa;
+      Z[n + n - 2] = B[b * L + a] - 2.0 * (vp[b] * pa + pbv * vp[a]);
+      Z[n - 1] = B[b * L + b] - 4.0 * vp[b] * pbv;
       Z[n + n - 1] = 0.0;
     }
   }
@@ -1823,7 +1840,7 @@ __device__ inline void tri_bounds(const double* d, const double* e, int n, doubl
   hi = gu + pad;
 }
 
-__device__ void eig_bisect_body(const int n, const int kvec, const double* __restrict__ Z, double* __restrict__ w,
+__device__ __forceinline__ void eig_bisect_body(const int n, const int kvec, const double* __restrict__ Z, double* __restrict__ w,
                                 int* __restrict__ fail) {
   if (!eig_split(n, kvec)) return;
   const int nev = eig_nev(n, kvec);
@@ -1942,7 +1959,7 @@ __device__ inline void lane_solve(const double* d, const double* e, int n, doubl
 #pragma unroll
     for (int k = 0; k < EI_BLK; ++k) {
       const int r = r0 + k;
-      if (r + 1 >= n) break;
+      if (r + 1 < n) {
       const long o = (long)r * S;
       double l, p;
       if (FACTOR) {
@@ -1972,6 +1989,7 @@ __device__ inline void lane_solve(const double* d, const double* e, int n, doubl
       const double nxt = zn[k];
       if (p != 0.0) { z[o] = nxt; cur = cur - l * nxt; }
       else { z[o] = cur; cur = nxt - l * cur; }
+      }
     }
   }
   const long last = (long)(n - 1) * S;
@@ -1996,45 +2014,51 @@ __device__ inline void lane_solve(const double* d, const double* e, int n, doubl
 #pragma unroll
     for (int k = 0; k < EI_BLK; ++k) {
       const int r = r0 - k;
-      if (r < 0) break;
-      const double x = (zb[k] - ab[k] * x1 - bb[k] * x2) * ib[k];
-      z[(long)r * S] = x;
-      x2 = x1;
-      x1 = x;
+      if (r >= 0) {
+        const double x = (zb[k] - ab[k] * x1 - bb[k] * x2) * ib[k];
+        z[(long)r * S] = x;
+        x2 = x1;
+        x1 = x;
+      }
     }
   }
 }
 
-// z_iv -= sum_{j0 <= j < iv} (z_j . z_iv) z_j over the rows of Z (all coefficients first, a wave
-// per j, then one update), as cgs_cluster.
-__device__ inline void cgs_rows(double* Z, int n, int j0, int iv, double* coef) {
+// Working vectors of k_eig_invit, interleaved: element r of vector iv at Y[r S + iv], S = kvec.
+// In LDS when n kvec <= EI_LDS doubles (n = 256 with kvec <= 48), else in the free rows of Z.
+constexpr int EI_LDS = 12288;
+
+// y_iv -= sum_{j0 <= j < iv} (y_j . y_iv) y_j (all coefficients first, a wave per j, then one
+// update), as cgs_cluster.
+__device__ inline void cgs_cols(double* Y, int n, int S, int j0, int iv, double* coef) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-  double* zi = Z + (long)iv * n;
   for (int j = j0 + wv; j < iv; j += nw) {
-    const double* zj = Z + (long)j * n;
     double dp = 0.0;
-    for (int i = lane; i < n; i += 64) dp += zj[i] * zi[i];
+    for (int r = lane; r < n; r += 64) dp += Y[(long)r * S + j] * Y[(long)r * S + iv];
     for (int o = 32; o > 0; o >>= 1) dp += __shfl_xor(dp, o);
     if (lane == 0) coef[j - j0] = dp;
   }
   __syncthreads();
-  for (int i = tid; i < n; i += blockDim.x) {
-    double v = zi[i];
-    for (int j = j0; j < iv; ++j) v -= coef[j - j0] * Z[(long)j * n + i];
-    zi[i] = v;
+  for (int r = tid; r < n; r += blockDim.x) {
+    double* y = Y + (long)r * S;
+    double v = y[iv];
+    for (int j = j0; j < iv; ++j) v -= coef[j - j0] * y[j];
+    y[iv] = v;
   }
   __syncthreads();
 }
 
-__device__ void eig_invit_body(const int n, const int kvec, double* __restrict__ w, double* __restrict__ R,
+__device__ __forceinline__ void eig_invit_body(const int n, const int kvec, double* __restrict__ w, double* __restrict__ R,
                                double* __restrict__ tail_out, int* __restrict__ fail) {
   if (!eig_split(n, kvec)) return;
   __shared__ double d[EIG_MAXN], e[EIG_MAXN];
+  __shared__ double ys[EI_LDS];
   __shared__ double red[2 * EI_THREADS / 64], coef[64];
   __shared__ int j0s[64];
-  double* Z = R + (long)n * n;          // tridiagonal eigenvector iv at Z[iv n ..)
-  double* Y = Z + (long)kvec * n;       // the vectors interleaved for the solves: Y[r kvec + iv]
-  double* F = Y + (long)kvec * n;       // their LU factors, interleaved the same way (5 n kvec)
+  double* Z = R + (long)n * n;                 // tridiagonal eigenvector iv at Z[iv n ..) at the end
+  const int S = kvec;
+  double* Y = (long)n * kvec <= EI_LDS ? ys : Z + (long)kvec * n;
+  double* F = Z + 2L * kvec * n;               // LU factors, interleaved the same way (5 n kvec)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = EI_THREADS >> 6;
   for (int i = tid; i < n; i += EI_THREADS) { d[i] = Z[i]; e[i] = Z[n + i]; }
   double lo, hi, tnorm;
@@ -2069,33 +2093,31 @@ __device__ void eig_invit_body(const int n, const int kvec, double* __restrict__
   }
   // deterministic zero-mean start vectors (the same as eigh_tri_body's)
   for (long idx = tid; idx < (long)kvec * n; idx += EI_THREADS) {
-    const int iv = (int)(idx / n), i = (int)(idx % n);
+    const int i = (int)(idx / S), iv = (int)(idx % S);
     const unsigned hsh = (unsigned)(i + 1) * 2654435761u ^ (unsigned)(iv + 7) * 40503u;
-    Z[idx] = (double)(hsh & 0xFFFFu) / 32768.0 - 1.0;
+    Y[idx] = (double)(hsh & 0xFFFFu) / 32768.0 - 1.0;
   }
   __syncthreads();
   auto normalise_all = [&]() {                       // a wave per vector
     for (int iv = wv; iv < kvec; iv += nw) {
-      double* z = Z + (long)iv * n;
       double np = 0.0;
-      for (int i = lane; i < n; i += 64) np += z[i] * z[i];
+      for (int r = lane; r < n; r += 64) np += Y[(long)r * S + iv] * Y[(long)r * S + iv];
       for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
       const double inv = 1.0 / sqrt(np);
-      for (int i = lane; i < n; i += 64) z[i] *= inv;
+      for (int r = lane; r < n; r += 64) Y[(long)r * S + iv] *= inv;
     }
     __syncthreads();
   };
-  auto normalise_one = [&](int iv) {                 // the whole block, after cgs_rows
-    double* z = Z + (long)iv * n;
+  auto normalise_one = [&](int iv) {                 // the whole block, after cgs_cols
     double np = 0.0;
-    for (int i = tid; i < n; i += EI_THREADS) np += z[i] * z[i];
+    for (int r = tid; r < n; r += EI_THREADS) np += Y[(long)r * S + iv] * Y[(long)r * S + iv];
     for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o);
     if (lane == 0) red[wv] = np;
     __syncthreads();
     double t = 0.0;
     for (int k = 0; k < nw; ++k) t += red[k];
     const double inv = 1.0 / sqrt(t);
-    for (int i = tid; i < n; i += EI_THREADS) z[i] *= inv;
+    for (int r = tid; r < n; r += EI_THREADS) Y[(long)r * S + iv] *= inv;
     __syncthreads();
   };
   // start vectors: unit length, then orthogonal to the earlier members of their cluster (inside a
@@ -2103,35 +2125,30 @@ __device__ void eig_invit_body(const int n, const int kvec, double* __restrict__
   normalise_all();
   for (int iv = 1; iv < kvec; ++iv)
     if (j0s[iv] < iv) {
-      cgs_rows(Z, n, j0s[iv], iv, coef);
+      cgs_cols(Y, n, S, j0s[iv], iv, coef);
       normalise_one(iv);
     }
   // three solves; after each, every vector normalised, then the members of a cluster in order
   // against the earlier (final, unit) ones by classical Gram-Schmidt twice and normalised again
   for (int it = 0; it < 3; ++it) {
-    for (long idx = tid; idx < (long)kvec * n; idx += EI_THREADS) {   // Z rows -> Y
-      const int r = (int)(idx / kvec), iv = (int)(idx % kvec);
-      Y[idx] = Z[(long)iv * n + r];
-    }
-    __syncthreads();
     if (wv == 0 && lane < kvec) {
-      if (it == 0) lane_solve<true>(d, e, n, w[lane], pivlu, Y + lane, F + lane, kvec);
-      else lane_solve<false>(d, e, n, w[lane], pivlu, Y + lane, F + lane, kvec);
-    }
-    __syncthreads();
-    for (long idx = tid; idx < (long)kvec * n; idx += EI_THREADS) {   // Y -> Z rows
-      const int iv = (int)(idx / n), r = (int)(idx % n);
-      Z[idx] = Y[(long)r * kvec + iv];
+      if (it == 0) lane_solve<true>(d, e, n, w[lane], pivlu, Y + lane, F + lane, S);
+      else lane_solve<false>(d, e, n, w[lane], pivlu, Y + lane, F + lane, S);
     }
     __syncthreads();
     normalise_all();
     for (int iv = 1; iv < kvec; ++iv)
       if (j0s[iv] < iv) {
-        cgs_rows(Z, n, j0s[iv], iv, coef);
-        cgs_rows(Z, n, j0s[iv], iv, coef);
+        cgs_cols(Y, n, S, j0s[iv], iv, coef);
+        cgs_cols(Y, n, S, j0s[iv], iv, coef);
         normalise_one(iv);
       }
   }
+  for (long idx = tid; idx < (long)kvec * n; idx += EI_THREADS) {   // Y -> rows of Z
+    const int iv = (int)(idx / n), r = (int)(idx % n);
+    Z[idx] = Y[(long)r * S + iv];
+  }
+  __syncthreads();
   // residual of every eigenpair of the tridiagonal matrix (a wave per vector); the negated
   // comparison also flags NaN
   for (int iv = wv; iv < kvec; iv += nw) {
@@ -2161,7 +2178,7 @@ __global__ __launch_bounds__(EI_THREADS) void k_eig_invit_list(const EigDesc* __
 
 // Back-transformation of vector iv = blockIdx.x (one wave): the reflectors are read two ahead
 // of their use.
-__device__ void eig_backtr_body(const int n, const int kvec, const double* __restrict__ R, double* __restrict__ V) {
+__device__ __forceinline__ void eig_backtr_body(const int n, const int kvec, const double* __restrict__ R, double* __restrict__ V) {
   if (!eig_split(n, kvec)) return;
   const int iv = blockIdx.x;
   if (iv >= kvec) return;
@@ -2174,30 +2191,29 @@ __device__ void eig_backtr_body(const int n, const int kvec, const double* __res
     const int i = lane + 64 * t;
     y[t] = i < n ? Z[(long)iv * n + i] : 0.0;
   }
-  auto load = [&](double* v, int k) {
-#pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      const int i = lane + 64 * t;
-      v[t] = (k >= 0 && i < n) ? R[(long)k * n + i] : 0.0;
-    }
-  };
-  auto apply = [&](const double* v) {
-    double dp = 0.0;
-#pragma unroll
-    for (int t = 0; t < PER; ++t) dp += v[t] * y[t];
-    for (int o = 32; o > 0; o >>= 1) dp += __shfl_xor(dp, o);
-#pragma unroll
-    for (int t = 0; t < PER; ++t) y[t] -= 2.0 * dp * v[t];
-  };
-  load(v0, n - 3);
-  load(v1, n - 4);
-  for (int k = n - 3; k >= 0; k -= 2) {
-    apply(v0);
-    load(v0, k - 2);
-    if (k - 1 < 0) break;
-    apply(v1);
-    load(v1, k - 3);
+#define BT_LOAD(v, k)                                                   \
+  _Pragma("unroll") for (int t = 0; t < PER; ++t) {                     \
+    const int i_ = lane + 64 * t;                                       \
+    v[t] = ((k) >= 0 && i_ < n) ? R[(long)(k) * n + i_] : 0.0;          \
   }
+#define BT_APPLY(v)                                                     \
+  {                                                                     \
+    double dp = 0.0;                                                    \
+    _Pragma("unroll") for (int t = 0; t < PER; ++t) dp += v[t] * y[t];  \
+    for (int o = 32; o > 0; o >>= 1) dp += __shfl_xor(dp, o);           \
+    _Pragma("unroll") for (int t = 0; t < PER; ++t) y[t] -= 2.0 * dp * v[t]; \
+  }
+  BT_LOAD(v0, n - 3)
+  BT_LOAD(v1, n - 4)
+  for (int k = n - 3; k >= 0; k -= 2) {
+    BT_APPLY(v0)
+    BT_LOAD(v0, k - 2)
+    if (k - 1 < 0) break;
+    BT_APPLY(v1)
+    BT_LOAD(v1, k - 3)
+  }
+#undef BT_LOAD
+#undef BT_APPLY
 #pragma unroll
   for (int t = 0; t < PER; ++t) {
     const int i = lane + 64 * t;
