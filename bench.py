@@ -43,10 +43,11 @@ PRODUCTS = {"split_bf16": 3, "split_fp16": 3}
 CEILING_KEY = {"fp64": "fp64", "fp32": "fp32", "bf16": "bf16", "fp16": "fp16", "split_bf16": "bf16",
                "split_fp16": "fp16"}
 # HBM bytes per launch of the bottleneck kernel of the split FP16 form at chi = 16 (16 pair
-# groups per launch), from two rocprofv3 counter runs of `bench.py --counter-steps 6`
+# groups per launch), from two rocprofv3 counter runs of `bench.py --counter-steps 5`
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors read off a 1 GiB copy);
-# profiles/hotrg3d_chi16_split_fp16_trace_and_traffic.md. Valid only while that kernel is unchanged.
-GEMM_TRAFFIC_BYTES = {"split_fp16": 6.459e9}
+# profiles/hotrg3d_chi16_split_fp16_gemm_counters.md (the direct-load kernel). Valid only while
+# that kernel is unchanged.
+GEMM_TRAFFIC_BYTES = {"split_fp16": 6.475e9}
 # Algorithmic bytes of the same launch: A operand (2 planes x 4096^2 x 2 B), B chunk
 # (2 planes x 65536 x 4096 x 2 B) and the new-tensor chunk written (4096 x 256 x 4 B).
 GEMM_ALGO_BYTES = {"split_fp16": 2 * 4096 * 4096 * 2 + 2 * 65536 * 4096 * 2 + 4096 * 256 * 4}

@@ -332,7 +332,8 @@ int hotrg_batch_info(hotrg_batch* b, int* graph_launches, int* eager_steps);
  * hotrg_log_z); it must not be stepped or destroyed.  NULL if i is out of range. */
 hotrg_handle* hotrg_batch_instance(hotrg_batch* b, int i);
 
-/* Idempotent on NULL. */
+/* Waits for the batch's stream, then frees the recorded graphs and the instances (the workspace
+ * stays the caller's).  Idempotent on NULL. */
 void hotrg_batch_destroy(hotrg_batch* b);
 
 /* Message of the last error of b (NULL: of the last failed hotrg_batch_init). */

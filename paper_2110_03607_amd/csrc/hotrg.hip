@@ -2123,8 +2123,9 @@ hotrg_handle* hotrg_batch_instance(hotrg_batch* b, int i) {
 
 void hotrg_batch_destroy(hotrg_batch* b) {
   if (!b) return;
+  (void)hipStreamSynchronize(b->s);   // no graph launch may still be running when its exec goes
   for (auto& g : b->graph)
-    if (g) hipGraphExecDestroy(g);
+    if (g) (void)hipGraphExecDestroy(g);
   for (auto* h : b->inst) hotrg_destroy(h);
   delete b;
 }
