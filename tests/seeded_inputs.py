@@ -31,6 +31,9 @@ CONFIG4_3D = dict(kind="ising", d=3, q=2, temps=tuple(np.linspace(4.0, 5.0, 64))
 CONFIG4_2D = dict(kind="ising", d=2, q=2, betas=tuple(np.linspace(0.3, 0.6, 48)),
                   chis=(16, 24, 32), steps=20)
 CONFIG5 = dict(kind="potts", d=3, q=3, betas=(0.50, 0.55, 0.60), chi=16, steps=20)
+# 4D Ising (the paper's own model, Section 5) at a bond dimension the oracle runs in seconds per
+# step; T around the 4D critical temperature (about 6.68)
+CONFIG6 = dict(kind="ising", d=4, q=2, temps=(6.0, 6.68, 7.5), chi=4, steps=12)
 
 
 def random_positive_tensor(shape, seed=0, spread=0.5):
