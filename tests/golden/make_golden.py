@@ -225,6 +225,7 @@ def main(names):
         "config3": (SI.CONFIG3, [1.0 / T for T in SI.CONFIG3["temps"]]),
         "config5": (SI.CONFIG5, list(SI.CONFIG5["betas"])),
         "config6": (SI.CONFIG6, [1.0 / T for T in SI.CONFIG6["temps"]]),
+        "config7": (SI.CONFIG7, [1.0 / T for T in SI.CONFIG7["temps"]]),
     }
     for name in names:
         cfg, betas = table[name]

@@ -34,6 +34,8 @@ CONFIG5 = dict(kind="potts", d=3, q=3, betas=(0.50, 0.55, 0.60), chi=16, steps=2
 # 4D Ising (the paper's own model, Section 5) at a bond dimension the oracle runs in seconds per
 # step; T around the 4D critical temperature (about 6.68)
 CONFIG6 = dict(kind="ising", d=4, q=2, temps=(6.0, 6.68, 7.5), chi=4, steps=12)
+# ... and at chi = 5 (H = 625: no dimension a multiple of a GEMM tile), one temperature
+CONFIG7 = dict(kind="ising", d=4, q=2, temps=(6.68,), chi=5, steps=8)
 
 
 def random_positive_tensor(shape, seed=0, spread=0.5):
