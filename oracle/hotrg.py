@@ -15,7 +15,7 @@ where (c, c') are the legs in the Current direction and (n_j, n'_j) those of the
 direction Next j.  Merged indices follow Section 3.2: (a b) = a + b * chi_{n_j},
 with a on the hat copy and b on the check copy.
 
-Readings of points the paper leaves open (each also listed in the design doc):
+Readings of points the paper leaves open:
   R1  Section 3.2 / 4.2.5 speak of an SVD of A and A'.  A = M M^T is symmetric
       positive semi-definite, so a symmetric eigendecomposition is used; the
       "singular values" are its eigenvalues, sorted in descending order.

@@ -28,7 +28,7 @@ HOTRG_CHOOSE_EPSILON, HOTRG_CHOOSE_U, HOTRG_CHOOSE_UPRIME = 0, 1, 2
 CHOICES = {"epsilon": HOTRG_CHOOSE_EPSILON, "U": HOTRG_CHOOSE_U, "Uprime": HOTRG_CHOOSE_UPRIME}
 FORMS = {"fp64": HOTRG_FP64, "fp32": HOTRG_FP32, "bf16": HOTRG_BF16, "fp16": HOTRG_FP16,
          "split_bf16": HOTRG_SPLIT_BF16, "split_fp16": HOTRG_SPLIT_FP16}
-HOTRG_MAX_DIRS = 3
+HOTRG_MAX_DIRS = 4
 
 
 class hotrg_model(ctypes.Structure):

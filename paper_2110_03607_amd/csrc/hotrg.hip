@@ -32,8 +32,14 @@ namespace {
 constexpr long TILE_M = 256, TILE_N = 256, TILE_K = 64;   // operand padding (multiple of every tile)
 constexpr long GRAM_TILE = 128;                             // tile of the FP64 Gram GEMM
 constexpr int MAX_CHI_3D = 16, MAX_CHI_2D = 32;
+// 4D: b = chi^3 <= 512 (k_pstage4) and the non-prime chain's LDS (n4_lds_cap): chi <= 8 in the
+// reduced forms, chi <= 7 in FP64.
+constexpr int MAX_CHI_4D = 8, MAX_CHI_4D_FP64 = 7;
+inline int max_chi_for(int d, int form) {
+  return d == 2 ? MAX_CHI_2D : d == 3 ? MAX_CHI_3D : (form == HOTRG_FP64 ? MAX_CHI_4D_FP64 : MAX_CHI_4D);
+}
 constexpr size_t ALIGN = 256;
-constexpr int EIG_SLOTS = 4;    // (direction, side) matrices decomposed per step
+constexpr int EIG_SLOTS = EIG_BATCH;   // (direction, side) matrices decomposed per step, at most
 
 inline long roundup(long x, long m) { return (x + m - 1) / m * m; }
 
@@ -60,10 +66,12 @@ Dims make_dims(const LocalDims& ld, const int* k) {
   dm.d = ld.d;
   dm.chic = ld.chi[0];
   dm.chi1 = ld.chi[1];
-  dm.chi2 = ld.d == 3 ? ld.chi[2] : 1;
+  dm.chi2 = ld.d >= 3 ? ld.chi[2] : 1;
+  dm.chi3 = ld.d >= 4 ? ld.chi[3] : 1;
   dm.k1 = k[0];
-  dm.k2 = ld.d == 3 ? k[1] : 1;
-  dm.b = dm.chi1 * dm.chi2;
+  dm.k2 = ld.d >= 3 ? k[1] : 1;
+  dm.k3 = ld.d >= 4 ? k[2] : 1;
+  dm.b = dm.chi1 * dm.chi2 * dm.chi3;
   dm.H = dm.chic * dm.b;
   return dm;
 }
@@ -669,7 +677,8 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
   MT* Tn = (MT*)Tnv;
   const Dims dm = make_dims(ld, k);
   const long H = dm.H, Mp = roundup(H, TILE_M), Kp = roundup(H, TILE_K);
-  const long pairs_total = (ld.d == 3) ? (long)k[0] * k[1] : k[0];
+  long pairs_total = 1;
+  for (int j = 1; j < ld.d; ++j) pairs_total *= k[j - 1];
   long cp = chunk_pairs_for(ld, k, h->form, h->opts.chunk);
   if (h->tune_chunk > 0) cp = std::min<long>(cp, h->tune_chunk);   // never above what the plan holds
   ST* Aop = h->at<ST>(h->plan.off_Aop);
@@ -681,6 +690,8 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
   const size_t ut_stride = h->plan.need.Ut / 8;   // elements per direction
   const void* U2 = F == F_FP64 ? (const void*)(h->at<double>(h->plan.off_Ut) + ut_stride)
                                : (const void*)(h->at<float>(h->plan.off_Ut32) + ut_stride);
+  const void* U3 = F == F_FP64 ? (const void*)(h->at<double>(h->plan.off_Ut) + 2 * ut_stride)
+                               : (const void*)(h->at<float>(h->plan.off_Ut32) + 2 * ut_stride);
   typedef typename std::conditional<F == F_FP64, double, float>::type UT;
   const long aplane = Mp * Kp;
   hipEvent_t t_all = tmark(h);
@@ -698,6 +709,10 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
                             launch_prime_mfma<F>(h->s, dm, T, U1, U2, pr0, pr1, Bop, Kp, bplane, st);
     if (mfma_prime)
       ;                                    // launched above
+    else if (ld.d == 4)
+      hipLaunchKernelGGL((k_pstage4<MT, UT, F>), dim3((unsigned)(H * dm.chic)), dim3(256), 0, h->s, T,
+                         (const UT*)U1, (const UT*)U2, (const UT*)U3, dm, (int)pr0, (int)pr1, Bop, Kp, bplane,
+                         (const DevState*)st);
     else if (ld.d == 3 && dm.chi2 % 8 == 0 && !h->scalar_prime)
       hipLaunchKernelGGL((k_pstage3v<MT, UT, F, 8>), dim3((unsigned)H), dim3(256), 0, h->s, T, (const UT*)U1,
                          (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane, (const DevState*)st);
@@ -747,7 +762,10 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     const long ncell = (long)dm.chic * (pr1 - pr0) * dm.chic;   // (c, g) blocks
     const int g0 = (int)(pr0 * dm.chic), gcount = (int)((pr1 - pr0) * dm.chic);
     const dim3 gnc((unsigned)(dm.chic * gcount));
-    if (ld.d == 3 && nstage3c_ok(dm) && dm.chi2 == 16)
+    if (ld.d == 4)
+      hipLaunchKernelGGL((k_nstage4<AT, MT, UT>), gnc, dim3(256), 0, h->s, (const AT*)Cc, Np, (const UT*)U1,
+                         (const UT*)U2, (const UT*)U3, dm, g0, gcount, Tn);
+    else if (ld.d == 3 && nstage3c_ok(dm) && dm.chi2 == 16)
       hipLaunchKernelGGL((k_nstage3p<AT, MT, UT, 16>), gnc, dim3(256), 0, h->s, (const AT*)Cc, Np, (const UT*)U1,
                          (const UT*)U2, dm, g0, gcount, Tn);
     else if (ld.d == 3 && nstage3c_ok(dm) && dm.chi2 == 12)
@@ -771,8 +789,13 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
   if (h->profiling) {
     // algorithmic MACs of the three stages as factorised here (all chunks of this step)
     const double c = dm.chic, b = dm.b, k1 = dm.k1, k2 = dm.k2, x1 = dm.chi1, x2 = dm.chi2, Hd = (double)H;
-    double macs = Hd * Hd * (k1 * k2 * c * b);                 // bottleneck: M = K = H, N = k1 k2 c b
-    if (ld.d == 3) {
+    const double k3 = dm.k3, x3 = dm.chi3;
+    double macs = Hd * Hd * (k1 * k2 * k3 * c * b);            // bottleneck: M = K = H, N = k1 k2 k3 c b
+    if (ld.d == 4) {
+      macs += Hd * c * b * (k1 * x1 + k1 * k2 * x2 + k1 * k2 * k3 * x3);   // prime chain, leg by leg
+      macs += c * c * k1 * k2 * k3 *                                       // non-prime chain per block
+              ((x1 * x2) * (x1 * x2) * x3 * x3 * k3 + x1 * x1 * k2 * k3 * x2 * x2 + k1 * k2 * k3 * x1 * x1);
+    } else if (ld.d == 3) {
       macs += Hd * c * k1 * b * x1 + Hd * c * k1 * k2 * b * x2; // prime chain: n'^check_1, then n'^check_2
       macs += c * c * k1 * k2 * (x1 * x1 * k2 * x2 * x2 + x1 * x1 * k1 * k2);  // non-prime chain
     } else {
@@ -803,7 +826,8 @@ int enqueue_contract_grad(hotrg_handle* h, const void* Tv, void* Tnv, const void
   MT* dTn = (MT*)dTnv;
   const Dims dm = make_dims(ld, k);
   const long H = dm.H, Mp = roundup(H, TILE_M), Kp = roundup(H, TILE_K), L2 = 2 * Kp;
-  const long pairs_total = (ld.d == 3) ? (long)k[0] * k[1] : k[0];
+  long pairs_total = 1;
+  for (int j = 1; j < ld.d; ++j) pairs_total *= k[j - 1];
   const long cp = chunk_pairs_for(ld, k, h->form, h->opts.chunk, true);
   MT* Aop = h->at<MT>(h->plan.off_Aop);
   MT* Bop = h->at<MT>(h->plan.off_Bop);
@@ -1072,7 +1096,7 @@ bool same_dims(const LocalDims& a, const LocalDims& b) {
 int enqueue_step_front(hotrg_handle* h, int axis_rec) {
   const LocalDims& ld = h->ld;
   hipLaunchKernelGGL(k_rec_init, dim3(1), dim3(256), 0, h->s, h->rec(0), h->st(), axis_rec, ld.d,
-                     ld.chi[0], ld.chi[1], ld.d == 3 ? ld.chi[2] : 0);
+                     ld.chi[0], ld.chi[1], ld.d >= 3 ? ld.chi[2] : 0, ld.d >= 4 ? ld.chi[3] : 0);
   void* dT = h->grad ? h->at<void>(h->plan.off_dT) : nullptr;
   return enqueue_grams(h, h->at<void>(h->plan.off_T), ld, dT);
 }
@@ -1167,9 +1191,9 @@ int sync_state(hotrg_handle* h, DevState* out) {
 
 extern "C" {
 
-static int check_model(const hotrg_model* m, int chi) {
+static int check_model(const hotrg_model* m, int chi, int form) {
   if (!m) return HOTRG_E_ARG;
-  if (m->d != 2 && m->d != 3) return HOTRG_E_ARG;
+  if (m->d < 2 || m->d > 4) return HOTRG_E_ARG;
   if (m->kind == HOTRG_ISING) {
     if (m->q != 2) return HOTRG_E_ARG;
   } else if (m->kind == HOTRG_POTTS) {
@@ -1178,8 +1202,7 @@ static int check_model(const hotrg_model* m, int chi) {
     return HOTRG_E_ARG;
   }
   if (!std::isfinite(m->J) || !std::isfinite(m->h)) return HOTRG_E_ARG;
-  const int maxchi = m->d == 3 ? MAX_CHI_3D : MAX_CHI_2D;
-  if (chi < m->q || chi > maxchi) return HOTRG_E_ARG;
+  if (chi < m->q || chi > max_chi_for(m->d, form)) return HOTRG_E_ARG;
   return HOTRG_OK;
 }
 
@@ -1192,15 +1215,18 @@ static bool opts_valid(const hotrg_opts* o) {
 }
 
 size_t hotrg_workspace_bytes(const hotrg_model* model, int chi, const hotrg_opts* opts) {
-  if (!opts_valid(opts) || check_model(model, chi) != HOTRG_OK) return 0;
+  if (!opts_valid(opts) || check_model(model, chi, opts->precision) != HOTRG_OK) return 0;
   if (opts->record_grad && opts->precision != HOTRG_FP64 && opts->precision != HOTRG_FP32) return 0;
+  if (opts->record_grad && model->d == 4) return 0;
   return make_plan(model->d, {model->q}, chi, opts->precision, opts->chunk, opts->max_steps, opts->record_grad != 0)
       .total;
 }
 
 static int check_init_args(const hotrg_model* model, double beta, int chi, const hotrg_opts* opts) {
   if (!opts || !model) return fail(nullptr, HOTRG_E_ARG, "model or opts is NULL");
-  if (check_model(model, chi) != HOTRG_OK) return fail(nullptr, HOTRG_E_ARG, "invalid model or chi");
+  if (check_model(model, chi, opts->precision) != HOTRG_OK)
+    return fail(nullptr, HOTRG_E_ARG, "invalid model or chi");
+  if (opts->record_grad && model->d == 4) return fail(nullptr, HOTRG_E_ARG, "the derivative is available for d = 2, 3");
   if (!opts_valid(opts))
     return fail(nullptr, HOTRG_E_ARG, "invalid options (form, max_steps, chunk, norm, choice; the derivative needs "
                                       "the trace normalisation)");
@@ -1269,8 +1295,8 @@ int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts*
 }
 
 static int check_tensor_args(int d, const int* dims, int chi, const hotrg_opts* opts) {
-  if ((d != 2 && d != 3) || !dims || !opts) return fail(nullptr, HOTRG_E_ARG, "invalid d, dims or opts");
-  const int maxchi = d == 3 ? MAX_CHI_3D : MAX_CHI_2D;
+  if (d < 2 || d > 4 || !dims || !opts) return fail(nullptr, HOTRG_E_ARG, "invalid d, dims or opts");
+  const int maxchi = max_chi_for(d, opts->precision);
   if (chi < 1 || chi > maxchi) return fail(nullptr, HOTRG_E_ARG, "chi out of range");
   for (int i = 0; i < d; ++i)
     if (dims[i] < 1 || dims[i] > maxchi) return fail(nullptr, HOTRG_E_ARG, "tensor dimension out of range");
@@ -1463,9 +1489,10 @@ const char* hotrg_last_error(const hotrg_handle* h) {
 // Kernel-level entry points
 // ---------------------------------------------------------------------------
 
-static bool debug_dims_ok(int d, const int* dims, const int* kdims) {
-  if ((d != 2 && d != 3) || !dims) return false;
-  const int maxchi = d == 3 ? MAX_CHI_3D : MAX_CHI_2D;
+static bool debug_dims_ok(int d, const int* dims, const int* kdims, int form = HOTRG_FP32) {
+  if (d < 2 || d > 4 || !dims) return false;
+  // the form only limits the contraction (kdims given); the Gram matrices are FP64 in every form
+  const int maxchi = max_chi_for(d, kdims ? form : HOTRG_FP32);
   for (int i = 0; i < d; ++i)
     if (dims[i] < 1 || dims[i] > maxchi) return false;
   if (kdims)
@@ -1515,7 +1542,7 @@ static Plan debug_plan(int d, const int* dims, const int* kdims, int form) {
 }
 
 size_t hotrg_debug_workspace_bytes(int d, const int* dims, const int* kdims, int precision) {
-  if (!debug_dims_ok(d, dims, kdims) || !form_valid(precision)) return 0;
+  if (!debug_dims_ok(d, dims, kdims, precision) || !form_valid(precision)) return 0;
   return debug_plan(d, dims, kdims, precision).total;
 }
 
@@ -1549,7 +1576,7 @@ __global__ void k_maxabs_f64(const double* src, long n, DevState* st) {
 int hotrg_debug_contract(int d, const int* dims, const int* kdims, int precision, const double* T_dev,
                          const double* const* U_dev, double* Tnext_dev, void* workspace, size_t ws_bytes,
                          void* stream) {
-  if (!debug_dims_ok(d, dims, kdims) || !kdims || !form_valid(precision) || !T_dev || !U_dev || !Tnext_dev ||
+  if (!debug_dims_ok(d, dims, kdims, precision) || !kdims || !form_valid(precision) || !T_dev || !U_dev || !Tnext_dev ||
       !workspace)
     return fail(nullptr, HOTRG_E_ARG, "invalid argument");
   for (int j = 0; j < d - 1; ++j)
@@ -1807,6 +1834,7 @@ static int batch_layout(const hotrg_instance* inst, int n, const hotrg_opts* o, 
   for (int i = 0; i < n; ++i) {
     const int rc = check_init_args(&inst[i].model, inst[i].beta, inst[i].chi, o);
     if (rc) return rc;
+    if (inst[i].model.d == 4) return HOTRG_E_ARG;   // batches hold 2D and 3D runs
     needs[i] = plan_need(inst[i].model.d, {inst[i].model.q}, inst[i].chi, o->precision, o->chunk, false);
     need_max(shared, needs[i]);
   }

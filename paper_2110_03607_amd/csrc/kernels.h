@@ -21,7 +21,7 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 
 constexpr int NSPEC = 24;       // normalised eigenvalues kept per decomposition
-constexpr int MAXD = 3;
+constexpr int MAXD = 4;
 
 // Device-resident state of one run: lnZ/V bookkeeping of Section 4.1.1.
 struct DevState {
@@ -1068,15 +1068,16 @@ __device__ inline double block_sum(double v, double* red) {
 
 constexpr int EIG_ALL_N = 256;   // every eigenvalue resolved up to this size (see eigh_tri_body)
 
+constexpr int EIG_BATCH = 2 * (MAXD - 1);   // (direction, side) matrices of one step at most
 struct EigBatch {
   int count;
-  int n[4], kvec[4];
-  double* A[4];
-  double* w[4];
-  double* V[4];
-  double* scratch[4];
-  double* tail[4];   // may be null: where the sum of the eigenvalues not resolved one by one goes
-  int* fail[4];      // set to 1 when the decomposition failed (see eigh_tri_body); never cleared here
+  int n[EIG_BATCH], kvec[EIG_BATCH];
+  double* A[EIG_BATCH];
+  double* w[EIG_BATCH];
+  double* V[EIG_BATCH];
+  double* scratch[EIG_BATCH];
+  double* tail[EIG_BATCH];   // may be null: where the sum of the eigenvalues not resolved one by one goes
+  int* fail[EIG_BATCH];      // set to 1 when the decomposition failed (see eigh_tri_body); never cleared here
 };
 
 // zs -= sum_{j0 <= j < j1} (Z_j . zs) Z_j: all coefficients first (a wave per vector,
@@ -2326,6 +2327,7 @@ __global__ void k_choose(const double* __restrict__ w0, const double* __restrict
 // ---------------------------------------------------------------------------
 struct Dims {
   int d, chic, chi1, chi2, k1, k2, b, H;   // chi2 = k2 = 1 for d = 2
+  int chi3, k3;                            // d = 4 (1 otherwise)
 };
 
 template <class MT, class UT, int F, bool ACC = false>
@@ -2880,6 +2882,130 @@ __global__ __launch_bounds__(64) void k_nstage2(const AT* __restrict__ C, long l
 }
 
 // ---------------------------------------------------------------------------
+// 4D contraction stages (Section 4.2.9 with three Next directions, eqs. TU1..TUNCD and
+// AfterBNNCD..AfterBN1), for b = chi_1 chi_2 chi_3 <= 512 (chi <= 8).
+//
+// Prime chain: workgroup (h, c') with h = (rho, nc) a row of the check copy; X = T[h][(c', nc')],
+// then the three U contractions one leg at a time,
+//   Z1[nh1][nc2][nc3] = sum_{nc1} U1[nh1 + chi1 nc1][n1] X[nc1][nc2][nc3],
+//   Z2[nh1][nh2][nc3] = sum_{nc2} U2[nh2 + chi2 nc2][n2] Z1[nh1][nc2][nc3],
+//   B[(pair, c', nc)][(rho, nh1, nh2, nh3)] = sum_{nc3} U3[nh3 + chi3 nc3][n3] Z2[nh1][nh2][nc3],
+// pairs (n1, n2, n3) in [pr0, pr1) with n1 outermost; Z1 is made once per n1, Z2 once per (n1, n2).
+// ---------------------------------------------------------------------------
+constexpr int B4_MAX = 512;
+template <class MT, class UT, int F>
+__global__ __launch_bounds__(256) void k_pstage4(const MT* __restrict__ T, const UT* __restrict__ U1,
+                                                 const UT* __restrict__ U2, const UT* __restrict__ U3, Dims dm,
+                                                 int pr0, int pr1, typename Store<F>::T* __restrict__ B, long ldb,
+                                                 long bplane, const DevState* __restrict__ st) {
+  __shared__ MT X[B4_MAX], Z1[B4_MAX], Z2[B4_MAX];
+  const int tid = threadIdx.x;
+  const int h = blockIdx.x / dm.chic, cp = blockIdx.x % dm.chic;
+  const int b = dm.b, c1 = dm.chi1, c2 = dm.chi2, c3 = dm.chi3, k1 = dm.k1, k2 = dm.k2, k3 = dm.k3;
+  const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * sqrt((double)b)) : 1.0;
+  const int rho = h / b, nc = h % b;
+  for (int i = tid; i < b; i += blockDim.x) X[i] = T[(long)h * dm.H + (long)cp * b + i];
+  int n1cur = -1;
+  for (int pr = pr0; pr < pr1;) {
+    const int n1 = pr / (k2 * k3), n2 = (pr / k3) % k2;
+    const int pe = min(pr1, (n1 * k2 + n2 + 1) * k3);   // end of this (n1, n2) group
+    __syncthreads();                                   // X staged / Z1, Z2 of the last group consumed
+    if (n1 != n1cur) {
+      for (int i = tid; i < b; i += blockDim.x) {      // i = (nh1, nc2, nc3)
+        const int nh1 = i / (c2 * c3), r = i % (c2 * c3);
+        MT s = 0;
+        for (int m = 0; m < c1; ++m) s += (MT)U1[(nh1 + c1 * m) * k1 + n1] * X[m * c2 * c3 + r];
+        Z1[i] = s;
+      }
+      n1cur = n1;
+      __syncthreads();
+    }
+    for (int i = tid; i < b; i += blockDim.x) {        // i = (nh1, nh2, nc3)
+      const int nh1 = i / (c2 * c3), nh2 = (i / c3) % c2, nc3 = i % c3;
+      MT s = 0;
+      for (int m = 0; m < c2; ++m) s += (MT)U2[(nh2 + c2 * m) * k2 + n2] * Z1[(nh1 * c2 + m) * c3 + nc3];
+      Z2[i] = s;
+    }
+    __syncthreads();
+    for (int q = pr; q < pe; ++q) {
+      const int n3 = q % k3;
+      const long row = (long)((q - pr0) * dm.chic + cp) * b + nc;
+      for (int i = tid; i < b; i += blockDim.x) {      // i = (nh1, nh2, nh3)
+        const int nh3 = i % c3, base = (i / c3) * c3;
+        MT s = 0;
+        for (int m = 0; m < c3; ++m) s += (MT)U3[(nh3 + c3 * m) * k3 + n3] * Z2[base + m];
+        put_scaled<F>(B, row * ldb + (long)rho * b + i, bplane, s, sB);
+      }
+    }
+    pr = pe;
+  }
+}
+
+// Non-prime chain (4D): workgroup (c, g); the (c, g) block of C is b x b, rows (nh1, nh2, nh3),
+// columns (nc1, nc2, nc3):
+//   W3[(nh1, nh2, nc1, nc2)][n3] = sum_{nh3, nc3} U3[nh3 + chi3 nc3][n3] C[..][..]  (each thread
+//     reads chi3 x chi3 sub-blocks straight from memory),
+//   W2[(nh1, nc1)][(n2, n3)] = sum_{nh2, nc2} U2[nh2 + chi2 nc2][n2] W3[..][n3],
+//   T^next[(n1, n2, n3, c)][g] = sum_{nh1, nc1} U1[nh1 + chi1 nc1][n1] W2[..][(n2, n3)].
+// W3 and W2 in LDS in the accumulation type AT: (chi1 chi2)^2 k3 + chi1^2 k2 k3 elements, at most
+// n4_lds_cap<AT>() (chi <= 8 in FP32, chi <= 7 in FP64; checked by the host).
+template <class AT> __host__ __device__ constexpr int n4_lds_cap() { return sizeof(AT) == 4 ? 36864 : 19456; }
+__host__ __device__ inline long n4_lds_need(int c1, int c2, int k2, int k3) {
+  return (long)(c1 * c2) * (c1 * c2) * k3 + (long)c1 * c1 * k2 * k3;
+}
+template <class AT, class MT, class UT>
+__global__ __launch_bounds__(256) void k_nstage4(const AT* __restrict__ C, long ldc, const UT* __restrict__ U1,
+                                                 const UT* __restrict__ U2, const UT* __restrict__ U3, Dims dm,
+                                                 int g0, int gcount, MT* __restrict__ Tn) {
+  __shared__ AT lds[n4_lds_cap<AT>()];
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x / gcount, gl = blockIdx.x % gcount;
+  const int b = dm.b, c1 = dm.chi1, c2 = dm.chi2, c3 = dm.chi3, k1 = dm.k1, k2 = dm.k2, k3 = dm.k3;
+  const int Hn = k1 * k2 * k3 * dm.chic;
+  const int p12 = c1 * c2, ncomb = p12 * p12;
+  AT* W3 = lds;                       // [(nh1 c2 + nh2) (c1 c2) + nc1 c2 + nc2][n3]
+  AT* W2 = lds + (long)ncomb * k3;    // [(nh1 c1 + nc1)][n2 k3 + n3]
+  const AT* Cb = C + (long)c * b * ldc + (long)gl * b;
+  for (int t = tid; t < ncomb; t += blockDim.x) {
+    const int hp = t / p12, cpp = t % p12;   // (nh1, nh2), (nc1, nc2)
+    AT acc[8];
+#pragma unroll
+    for (int n3 = 0; n3 < 8; ++n3) acc[n3] = 0;
+    for (int nh3 = 0; nh3 < c3; ++nh3) {
+      const AT* row = Cb + (long)(hp * c3 + nh3) * ldc + cpp * c3;
+      for (int nc3 = 0; nc3 < c3; ++nc3) {
+        const AT x = row[nc3];
+        const UT* u = U3 + (nh3 + c3 * nc3) * k3;
+#pragma unroll
+        for (int n3 = 0; n3 < 8; ++n3)
+          if (n3 < k3) acc[n3] += x * (AT)u[n3];
+      }
+    }
+#pragma unroll
+    for (int n3 = 0; n3 < 8; ++n3)
+      if (n3 < k3) W3[t * k3 + n3] = acc[n3];
+  }
+  __syncthreads();
+  const int n23 = k2 * k3;
+  for (int o = tid; o < c1 * c1 * n23; o += blockDim.x) {   // o = ((nh1, nc1), (n2, n3))
+    const int hc = o / n23, q = o % n23, nh1 = hc / c1, nc1 = hc % c1, n2 = q / k3, n3 = q % k3;
+    AT s = 0;
+    for (int nh2 = 0; nh2 < c2; ++nh2)
+      for (int nc2 = 0; nc2 < c2; ++nc2)
+        s += (AT)U2[(nh2 + c2 * nc2) * k2 + n2] * W3[((nh1 * c2 + nh2) * p12 + nc1 * c2 + nc2) * k3 + n3];
+    W2[o] = s;
+  }
+  __syncthreads();
+  for (int o = tid; o < k1 * n23; o += blockDim.x) {        // o = (n1, n2, n3)
+    const int q = o % n23, n1 = o / n23;
+    AT s = 0;
+    for (int nh1 = 0; nh1 < c1; ++nh1)
+      for (int nc1 = 0; nc1 < c1; ++nc1) s += (AT)U1[(nh1 + c1 * nc1) * k1 + n1] * W2[(nh1 * c1 + nc1) * n23 + q];
+    Tn[(long)(o * dm.chic + c) * Hn + (g0 + gl)] = (MT)s;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Trace, Gu-Wen ratio and lnZ/V (eqs. Trace_LocalTensor, ratio_X, eq_lnZ, K_recurrence):
 // t_p = Tr T^new = sum_h T[h][h];  lnZ^(p)/V^(p) = lnZ^(p-1)/V^(p-1) + ln(t_p) / 2^p;
 // f^(p) = 1/t_p.  Y[c][c'] = sum_n T^new[n.., n.., c, c'] where, in the renamed storage,
@@ -3139,7 +3265,7 @@ __global__ void k_inv_scale_fp16(DevState* st, int b) {
 
 // Fresh step record.
 // axis < 0: the natural cycle, lattice axis (p - 1) mod d.
-__global__ void k_rec_init(StepRec* rec_base, DevState* st, int axis, int d, int c0, int c1, int c2) {
+__global__ void k_rec_init(StepRec* rec_base, DevState* st, int axis, int d, int c0, int c1, int c2, int c3) {
   const int p = st->p + 1;
   StepRec* rec = rec_base + (p - 1);
   if (axis < 0) axis = (p - 1) % d;
@@ -3152,7 +3278,8 @@ __global__ void k_rec_init(StepRec* rec_base, DevState* st, int axis, int d, int
     rec->axis = axis;
     rec->dims_before[0] = c0;
     rec->dims_before[1] = c1;
-    rec->dims_before[2] = d == 3 ? c2 : 0;
+    rec->dims_before[2] = d >= 3 ? c2 : 0;
+    rec->dims_before[3] = d >= 4 ? c3 : 0;
   }
 }
 

@@ -86,7 +86,7 @@ def config4_instances():
 # FP64: 1e-10, then 1e-8.  Split FP16: 1e-6 (the MFMA bar), then 1e-5.  In the ordered phase (3D
 # T near 4.0, 2D beta near 0.6) even/odd pairs of Gram eigenvalues come within the form's noise
 # of each other at some cuts; the split form then drops a pair that FP64 keeps (or the
-# reverse).  The instances and steps concerned are printed (and listed in the design doc).
+# reverse).  The instances and steps concerned are printed.
 SWEEP_BOUND = {"fp64": (1e-10, 1e-8), "split_fp16": (1e-6, 1e-5)}
 
 

@@ -50,6 +50,8 @@ def load(name):
     ("ising", 3, 2, 0.2216544, 16, 3),
     ("potts", 3, 3, 0.55, 9, 1),
     ("potts", 2, 3, 0.9, 9, 1),
+    # 4D: one step is exact (legs of dimension 4); FP64 runs 4D up to chi = 7
+    ("ising", 4, 2, 0.15, 7, 1),
 ])
 def test_untruncated_steps_equal_brute_force(kind, d, q, beta, chi, steps):
     r, lnz = run_gpu(kind, d, beta, chi, steps, q=q)
@@ -60,8 +62,8 @@ def test_untruncated_steps_equal_brute_force(kind, d, q, beta, chi, steps):
 
 
 def test_initial_lnz_closed_form():
-    for d in (2, 3):
-        r = P.HOTRG("ising", d, 0.3, 8)
+    for d in (2, 3, 4):
+        r = P.HOTRG("ising", d, 0.3, 4)
         assert r.log_z() == pytest.approx(math.log(2) + d * 0.3, abs=1e-15)
 
 
@@ -150,6 +152,34 @@ def test_config3_3d_ising_chi16(precision, bound):
     r, lnz = run_gpu("ising", 3, run["beta"], fx["chi"], fx["steps"], precision=precision)
     print(f"config3 {precision} beta={run['beta']:.7f}")
     emax, elast = compare_run(r, run, lnz, precision, dirs=(1, 2))
+    print(f"  max rel err={emax:.2e} final={elast:.2e}")
+    assert emax < bound
+
+
+@pytest.mark.parametrize("precision,bound", [("fp64", 1e-10), ("split_fp16", 1e-6), ("fp32", 1e-6)])
+def test_config6_4d_ising_chi4(precision, bound):
+    """4D Ising (the paper's own model), chi = 4, T = 6.0, 6.68, 7.5, 12 steps: three Next
+    directions per step, against the oracle fixture after every step (lnZ/V, trace, Gu-Wen
+    ratio, and in FP64 the kept column counts)."""
+    fx = load("config6.json")
+    worst = 0.0
+    for run in fx["runs"]:
+        r, lnz = run_gpu("ising", 4, run["beta"], fx["chi"], fx["steps"], precision=precision)
+        print(f"config6 {precision} beta={run['beta']:.6f}")
+        emax, elast = compare_run(r, run, lnz, precision, dirs=(1, 2, 3))
+        print(f"  max rel err={emax:.2e} final={elast:.2e}")
+        worst = max(worst, emax)
+    assert worst < bound
+
+
+@pytest.mark.parametrize("precision,bound", [("fp64", 1e-10), ("split_fp16", 1e-6)])
+def test_config7_4d_ising_chi5(precision, bound):
+    """4D Ising, chi = 5 (H = 625, no dimension a multiple of a tile), T = 6.68, 8 steps."""
+    fx = load("config7.json")
+    run = fx["runs"][0]
+    r, lnz = run_gpu("ising", 4, run["beta"], fx["chi"], fx["steps"], precision=precision)
+    print(f"config7 {precision} beta={run['beta']:.6f}")
+    emax, elast = compare_run(r, run, lnz, precision, dirs=(1, 2, 3))
     print(f"  max rel err={emax:.2e} final={elast:.2e}")
     assert emax < bound
 

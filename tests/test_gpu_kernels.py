@@ -25,10 +25,9 @@ P = gu.P
 
 # Per-slice bound of max|got - ref| / max|ref| per precision form, for the seeded N(0, 1)
 # tensors and QR isometries below.  Each bound is at most ten times the largest error
-# measured on an MI355X over all the shapes of this file (the measured maxima are listed in
-# the design doc, section 6): a change that loses a term, a plane or a scale factor fails.
-# Measured maxima (MI355X, all shapes): FP64 3.3e-15, FP32 1.6e-6, split FP16 9.4e-7, split
-# BF16 6.7e-6, FP16 4.4e-4, BF16 3.6e-3.
+# measured on an MI355X over all the shapes of this file: a change that loses a term, a plane
+# or a scale factor fails.  Measured maxima (MI355X, all shapes, 2D to 4D): FP64 3.3e-15, FP32
+# 1.6e-6, split FP16 1.0e-6, split BF16 6.7e-6, FP16 5.2e-4, BF16 4.1e-3.
 SLICE_BOUND = {P.HOTRG_FP64: 3e-14, P.HOTRG_FP32: 1.5e-5, P.HOTRG_SPLIT_FP16: 9e-6,
                P.HOTRG_SPLIT_BF16: 6e-5, P.HOTRG_FP16: 4e-3, P.HOTRG_BF16: 3e-2}
 # Gram matrices (FP64 in every form): measured max 3.3e-15.
@@ -51,6 +50,7 @@ CASES_3D = [
     ((4, 4, 2), (16, 4)),
 ]
 CASES_2D = [((8, 8), (16,)), ((5, 7), (9,)), ((32, 32), (32,))]
+CASES_4D = [((2, 3, 2, 2), (4, 3, 2)), ((3, 2, 3, 2), (4, 4, 4)), ((4, 4, 4, 4), (7, 7, 7))]
 
 
 def _random_case(dims, kdims, seed):
@@ -83,7 +83,7 @@ def _gpu():
     gu.require_gpu()
 
 
-@pytest.mark.parametrize("dims,kdims", CASES_3D + CASES_2D)
+@pytest.mark.parametrize("dims,kdims", CASES_3D + CASES_2D + CASES_4D)
 def test_contract_fp64_matches_oracle(dims, kdims):
     _check_all_slices(P.HOTRG_FP64, dims, kdims, seed=0)
 
@@ -91,7 +91,8 @@ def test_contract_fp64_matches_oracle(dims, kdims):
 @pytest.mark.parametrize("form", [P.HOTRG_FP32, P.HOTRG_SPLIT_FP16, P.HOTRG_SPLIT_BF16, P.HOTRG_FP16,
                                   P.HOTRG_BF16])
 @pytest.mark.parametrize("dims,kdims", [((8, 8, 8), (8, 8)), ((3, 5, 4), (7, 6)), ((8, 8), (16,)),
-                                       ((3, 12, 12), (12, 12)), ((2, 12, 12), (12, 12))])
+                                       ((3, 12, 12), (12, 12)), ((2, 12, 12), (12, 12)),
+                                       ((3, 3, 3, 3), (4, 4, 4))])
 def test_contract_forms_match_oracle(form, dims, kdims):
     # (3, 12, 12): chi = 12 with an odd number of c, the 256 x 256 GEMM and a separate non-prime
     # kernel; (2, 12, 12): the 288 x 288 GEMM with the non-prime chain in its epilogue
@@ -124,6 +125,28 @@ def test_contract_full_size_sampled(form):
     assert worst < SLICE_BOUND[form]
 
 
+FULL4D_DIMS, FULL4D_K, FULL4D_SEED = (8, 8, 8, 8), (8, 8, 8), 14
+FULL4D_PICKS = PT.spread_picks(FULL4D_K, 8)
+
+
+@functools.lru_cache(maxsize=None)
+def _full4d_reference():
+    Ts, Us = _random_case(FULL4D_DIMS, FULL4D_K, FULL4D_SEED)
+    return Ts, Us, oracle_next_storage(LY.to_paper(Ts), Us, only=FULL4D_PICKS)
+
+
+@pytest.mark.parametrize("form", [P.HOTRG_SPLIT_FP16, P.HOTRG_FP32, P.HOTRG_SPLIT_BF16, P.HOTRG_FP16, P.HOTRG_BF16])
+def test_contract_4d_full_size_sampled(form):
+    """4D chi = 8 (M = K = 4096, the three-leg prime and non-prime chains, the 256 x 256 GEMM):
+    8 spread (n'_1, n'_2, n'_3) slices of the new tensor against the oracle, element by element."""
+    Ts, Us, ref = _full4d_reference()
+    got = gu.contract(Ts, Us, list(FULL4D_K), form)
+    worst, errs = PT.worst_slice_error(got, ref, FULL4D_PICKS)
+    print(f"{FORM_NAME[form]} 4D chi=8 full size, 8 slices: max slice error {worst:.2e} "
+          f"(bound {SLICE_BOUND[form]:.0e}); per slice " + " ".join(f"{e:.1e}" for e in errs))
+    assert worst < SLICE_BOUND[form]
+
+
 FULL12_DIMS, FULL12_K, FULL12_SEED = (12, 12, 12), (12, 12), 12
 FULL12_PICKS = PT.spread_picks(FULL12_K, 16)
 
@@ -147,7 +170,8 @@ def test_contract_chi12_full_size_sampled(form):
     assert worst < SLICE_BOUND[form]
 
 
-@pytest.mark.parametrize("dims", [(4, 4, 4), (3, 5, 2), (8, 8, 8), (12, 12, 12), (8, 8), (16, 24), (32, 32)])
+@pytest.mark.parametrize("dims", [(4, 4, 4), (3, 5, 2), (8, 8, 8), (12, 12, 12), (8, 8), (16, 24), (32, 32),
+                                  (3, 4, 3, 2), (8, 8, 8, 8)])
 def test_gram_matches_oracle(dims):
     # (16, 24) and (32, 32): Gram matrices of size 576 and 1024, third step as a GEMM;
     # (12, 12, 12) and (32, 32): first two steps on the 256 x 128 FP64 tiles (ragged rows: 144 of 256)
