@@ -222,6 +222,44 @@ def run_4d(P, torch, form, chi=8, temp=6.68, warmup=8, timed=4):
                        "169 and 196 Xeon Phi nodes (chi=8..12 only plotted); not comparable hardware or size"}
 
 
+def scan_4d(P, torch, form, chis, steps=6, first_timed=5, temp=6.68):
+    """Time per coarse-graining step of 4D Ising HOTRG against chi (the paper's Section 5
+    measurement: steps 1-4 excluded, the rest averaged), and the exponent p of a least-squares
+    fit tau = alpha chi^p over the scanned chi."""
+    import math
+    rows = []
+    for chi in chis:
+        r = P.HOTRG("ising", 4, 1.0 / temp, chi, precision=form, max_steps=steps)
+        per = []
+        for p in range(1, steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r.step()
+            r.log_z()
+            torch.cuda.synchronize()
+            per.append(time.perf_counter() - t0)
+            print(f"4D chi={chi} step {p}: {per[-1]:.3f} s", file=sys.stderr, flush=True)
+        lz = r.log_z()
+        r.close()
+        timed = per[first_timed - 1:]
+        rows.append({"chi": chi, "s_per_step": round(sum(timed) / len(timed), 4),
+                     "s_per_step_all": [round(x, 4) for x in per], "lnz_per_site": lz})
+    fit = None
+    if len(rows) >= 2:
+        xs = [math.log(x["chi"]) for x in rows]
+        ys = [math.log(x["s_per_step"]) for x in rows]
+        n = len(xs)
+        mx, my = sum(xs) / n, sum(ys) / n
+        slope = sum((x - mx) * (y - my) for x, y in zip(xs, ys)) / sum((x - mx) ** 2 for x in xs)
+        alpha = math.exp(my - slope * mx)
+        fit = {"exponent": round(slope, 2), "alpha_s": alpha,
+               "projected_s_per_step": {str(c): round(alpha * c ** slope, 1) for c in (13, 14)}}
+    return {"workload": f"4D Ising HOTRG, T={temp}, J=1, h=0; steps {first_timed}-{steps} averaged",
+            "form": form, "rows": rows, "fit": fit,
+            "context": "the paper fits tau = alpha chi^13 and reports 510.76 s (chi=13, 169 nodes) and "
+                       "1247.65 s (chi=14, 196 nodes) per step on Xeon Phi; not comparable hardware"}
+
+
 def host_info():
     """CPU model and BLAS library of the host that ran the oracle."""
     model = None
@@ -286,6 +324,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched temperature sweep")
     ap.add_argument("--no-4d", action="store_true", help="skip the 4D HOTRG line")
     ap.add_argument("--only-4d", action="store_true", help="only the 4D HOTRG line (profiling)")
+    ap.add_argument("--scan-4d", default="", help="only the 4D time per step at these chi (comma-separated)")
+    ap.add_argument("--scan-steps", type=int, default=6, help="steps per chi of --scan-4d (steps 5.. timed)")
     ap.add_argument("--batch-only", action="store_true", help="only the batched temperature sweep (profiling)")
     ap.add_argument("--batch-no-graphs", action="store_true",
                     help="batched sweep enqueued kernel by kernel (for kernel tracing)")
@@ -320,6 +360,10 @@ def main():
         return
     if args.batch_only:
         print(json.dumps({"batch_sweep": run_batch(P, torch, args.form, graphs=not args.batch_no_graphs)}), flush=True)
+        return
+    if args.scan_4d:
+        chis = [int(x) for x in args.scan_4d.split(",")]
+        print(json.dumps({"hotrg_4d_scan": scan_4d(P, torch, args.form, chis, args.scan_steps)}), flush=True)
         return
     if args.only_4d:
         print(json.dumps({"hotrg_4d": run_4d(P, torch, args.form)}), flush=True)

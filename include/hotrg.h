@@ -119,8 +119,8 @@ size_t hotrg_workspace_bytes(const hotrg_model* model, int chi, const hotrg_opts
 /* Build the initial tensor of eq. (4) on the device, normalise it by
  * f^(0) = 1/Tr T (Section 3.1.3) and record lnZ/V at p = 0.  The first Current
  * direction is lattice axis 0.  beta >= 0 and finite; chi >= q and chi <= 32 (d = 2), 16
- * (d = 3), 8 (d = 4; 7 in the FP64 form: the 4D non-prime chain keeps two χ^4-sized arrays in
- * LDS).  d = 4 runs have no derivative mode and are not batched.
+ * (d = 3), 12 (d = 4: the register width of the 4D chain kernels).  d = 4 runs have no
+ * derivative mode and are not batched.
  * Errors: HOTRG_E_ARG, HOTRG_E_NOT_PSD, HOTRG_E_OOM, HOTRG_E_DEVICE. */
 int hotrg_init(const hotrg_model* model, double beta, int chi, const hotrg_opts* opts,
                void* workspace_dev, size_t workspace_bytes, void* hip_stream,
@@ -133,8 +133,8 @@ size_t hotrg_tensor_workspace_bytes(int d, const int* dims, int chi, const hotrg
 /* Start a run from a caller-supplied local tensor instead of a lattice model: the method of
  * Sections 3-4 coarse-grains any translation-invariant network of one local tensor.  T0_dev is
  * FP64 device memory in the storage order above with dims[0] = chi_c (lattice axis 0, the first
- * Current direction), dims[j] = chi_{n_j}; 1 <= dims[i], chi <= 32 (d = 2), 16 (d = 3), 8 (d = 4,
- * 7 in FP64).  T0
+ * Current direction), dims[j] = chi_{n_j}; 1 <= dims[i], chi <= 32 (d = 2), 16 (d = 3), 12 (d = 4).
+ * T0
  * is read (the caller keeps ownership; it may be freed once the stream has passed this call),
  * normalised by f^(0) = 1/Tr T0 (Section 3.1.3), and lnZ/V at p = 0 is ln Tr T0.  opts.record_grad
  * must be 0.  A non-positive or non-finite Tr T0 is reported as HOTRG_E_NUMERIC by the first

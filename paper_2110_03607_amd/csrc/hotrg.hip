@@ -32,11 +32,14 @@ namespace {
 constexpr long TILE_M = 256, TILE_N = 256, TILE_K = 64;   // operand padding (multiple of every tile)
 constexpr long GRAM_TILE = 128;                             // tile of the FP64 Gram GEMM
 constexpr int MAX_CHI_3D = 16, MAX_CHI_2D = 32;
-// 4D: b = chi^3 <= 512 (k_pstage4) and the non-prime chain's LDS (n4_lds_cap): chi <= 8 in the
-// reduced forms, chi <= 7 in FP64.
-constexpr int MAX_CHI_4D = 8, MAX_CHI_4D_FP64 = 7;
-inline int max_chi_for(int d, int form) {
-  return d == 2 ? MAX_CHI_2D : d == 3 ? MAX_CHI_3D : (form == HOTRG_FP64 ? MAX_CHI_4D_FP64 : MAX_CHI_4D);
+// 4D: the register width of the 4D chain kernels (every chi_j, k_j <= 12), and element counts of
+// order H^2 = chi^8 that stay within 32-bit indices.
+constexpr int MAX_CHI_4D = 12;
+inline int max_chi_for(int d, int) { return d == 2 ? MAX_CHI_2D : d == 3 ? MAX_CHI_3D : MAX_CHI_4D; }
+// register width of the 4D chain kernels for these dims (8 when every chi_j and k_j is at most 8)
+inline int cn4_for(const Dims& dm) {
+  const int m = std::max(std::max(std::max(dm.chi1, dm.chi2), std::max(dm.chi3, dm.k1)), std::max(dm.k2, dm.k3));
+  return m <= 8 ? 8 : 12;
 }
 constexpr size_t ALIGN = 256;
 constexpr int EIG_SLOTS = EIG_BATCH;   // (direction, side) matrices decomposed per step, at most
@@ -97,7 +100,7 @@ GramGeo gram_geo(long H, long R) {
 
 // Byte sizes of every workspace region for given dims (max over the run is allocated).
 struct Need {
-  size_t T, Aop, Bop, Cc, X, part, G, Amat, w, Ut, comb;
+  size_t T, Aop, Bop, Cc, X, part, G, Amat, w, Ut, comb, W2;
 };
 
 // The third Gram step as a GEMM (large directions): P[(fh, gh)][(r, e)] from Gh, Q likewise
@@ -145,6 +148,9 @@ Need need_for(const LocalDims& ld, int chi, int form, int user_chunk, bool grad 
   n.Aop = (size_t)Mp * Kp * op_esize(form) * op_planes(form) * grad_mult(grad);
   n.Bop = (size_t)Np * Kp * op_esize(form) * op_planes(form) * grad_mult(grad);
   n.Cc = (size_t)Mp * Np * acc_size(form);
+  // 4D non-prime chain scratch: W2[(c, g)][(nh1, nc1)][(n2, n3)] of one chunk (8-byte elements)
+  if (ld.d == 4)
+    n.W2 = (size_t)pairs * dm.chic * dm.chic * dm.chi1 * dm.chi1 * dm.k2 * dm.k3 * 8;
   size_t X = 0, part = 0, G = 0, Am = 0;
   for (int j = 1; j < ld.d; ++j) {
     const GramGeo g = gram_geo(H, (long)ld.chi[j] * ld.chi[0]);
@@ -171,7 +177,7 @@ void need_max(Need& a, const Need& b) {
   a.T = std::max(a.T, b.T); a.Aop = std::max(a.Aop, b.Aop); a.Bop = std::max(a.Bop, b.Bop);
   a.Cc = std::max(a.Cc, b.Cc); a.X = std::max(a.X, b.X); a.part = std::max(a.part, b.part);
   a.G = std::max(a.G, b.G); a.Amat = std::max(a.Amat, b.Amat); a.w = std::max(a.w, b.w);
-  a.Ut = std::max(a.Ut, b.Ut);
+  a.Ut = std::max(a.Ut, b.Ut); a.W2 = std::max(a.W2, b.W2);
   a.comb = std::max(a.comb, b.comb);
 }
 
@@ -193,7 +199,7 @@ std::vector<int> reachable_dims(const std::vector<int>& starts, int chi) {
 struct Plan {
   Need need;
   size_t off_state, off_rec, off_T, off_Tn, off_Aop, off_Bop, off_Cc, off_X, off_part, off_Gh, off_Gc,
-      off_A, off_Vw, off_Vo, off_w, off_Ut, off_Ut32, off_comb, total;
+      off_A, off_Vw, off_Vo, off_w, off_Ut, off_Ut32, off_comb, off_W2, total;
   // derivative mode (0 when off)
   size_t off_dT, off_dTn, off_dCc, off_Xd, off_dGh, off_dGc, off_dA, off_dUt, off_dUt32, off_dUw;
   bool grad;
@@ -257,6 +263,7 @@ void place_scratch(Plan& P, size_t& o, const Need& nd, bool grad) {
   P.off_Gh = take_at(o, nd.G);
   P.off_Gc = take_at(o, nd.G);
   P.off_comb = take_at(o, nd.comb);
+  P.off_W2 = take_at(o, nd.W2);
   if (grad) {
     P.off_dCc = take_at(o, nd.Cc);
     P.off_Xd = take_at(o, nd.X);
@@ -709,8 +716,12 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
                             launch_prime_mfma<F>(h->s, dm, T, U1, U2, pr0, pr1, Bop, Kp, bplane, st);
     if (mfma_prime)
       ;                                    // launched above
+    else if (ld.d == 4 && cn4_for(dm) == 8)
+      hipLaunchKernelGGL((k_pstage4<MT, UT, F, 8>), dim3((unsigned)(H * dm.chic)), dim3(256), 0, h->s, T,
+                         (const UT*)U1, (const UT*)U2, (const UT*)U3, dm, (int)pr0, (int)pr1, Bop, Kp, bplane,
+                         (const DevState*)st);
     else if (ld.d == 4)
-      hipLaunchKernelGGL((k_pstage4<MT, UT, F>), dim3((unsigned)(H * dm.chic)), dim3(256), 0, h->s, T,
+      hipLaunchKernelGGL((k_pstage4<MT, UT, F, 12>), dim3((unsigned)(H * dm.chic)), dim3(256), 0, h->s, T,
                          (const UT*)U1, (const UT*)U2, (const UT*)U3, dm, (int)pr0, (int)pr1, Bop, Kp, bplane,
                          (const DevState*)st);
     else if (ld.d == 3 && dm.chi2 % 8 == 0 && !h->scalar_prime)
@@ -762,9 +773,20 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     const long ncell = (long)dm.chic * (pr1 - pr0) * dm.chic;   // (c, g) blocks
     const int g0 = (int)(pr0 * dm.chic), gcount = (int)((pr1 - pr0) * dm.chic);
     const dim3 gnc((unsigned)(dm.chic * gcount));
-    if (ld.d == 4)
-      hipLaunchKernelGGL((k_nstage4<AT, MT, UT>), gnc, dim3(256), 0, h->s, (const AT*)Cc, Np, (const UT*)U1,
-                         (const UT*)U2, (const UT*)U3, dm, g0, gcount, Tn);
+    if (ld.d == 4) {
+      AT* W2 = h->at<AT>(h->plan.off_W2);
+      if (cn4_for(dm) == 8) {
+        hipLaunchKernelGGL((k_nstage4w<AT, UT, 8>), gnc, dim3(256), 0, h->s, (const AT*)Cc, Np, (const UT*)U2,
+                           (const UT*)U3, dm, gcount, W2);
+        hipLaunchKernelGGL((k_nstage4n<AT, MT, UT, 8>), gnc, dim3(256), 0, h->s, (const AT*)W2, (const UT*)U1, dm,
+                           g0, gcount, Tn);
+      } else {
+        hipLaunchKernelGGL((k_nstage4w<AT, UT, 12>), gnc, dim3(256), 0, h->s, (const AT*)Cc, Np, (const UT*)U2,
+                           (const UT*)U3, dm, gcount, W2);
+        hipLaunchKernelGGL((k_nstage4n<AT, MT, UT, 12>), gnc, dim3(256), 0, h->s, (const AT*)W2, (const UT*)U1, dm,
+                           g0, gcount, Tn);
+      }
+    }
     else if (ld.d == 3 && nstage3c_ok(dm) && dm.chi2 == 16)
       hipLaunchKernelGGL((k_nstage3p<AT, MT, UT, 16>), gnc, dim3(256), 0, h->s, (const AT*)Cc, Np, (const UT*)U1,
                          (const UT*)U2, dm, g0, gcount, Tn);
@@ -1531,6 +1553,7 @@ static Plan debug_plan(int d, const int* dims, const int* kdims, int form) {
   P.off_Gh = take(nd.G);
   P.off_Gc = take(nd.G);
   P.off_comb = take(nd.comb);
+  P.off_W2 = take(nd.W2);
   P.off_A = take(EIG_SLOTS * nd.Amat);
   P.off_Vw = take(EIG_SLOTS * 2 * nd.Amat);
   P.off_Vo = take(EIG_SLOTS * nd.Amat);

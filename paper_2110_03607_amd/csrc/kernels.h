@@ -2883,125 +2883,245 @@ __global__ __launch_bounds__(64) void k_nstage2(const AT* __restrict__ C, long l
 
 // ---------------------------------------------------------------------------
 // 4D contraction stages (Section 4.2.9 with three Next directions, eqs. TU1..TUNCD and
-// AfterBNNCD..AfterBN1), for b = chi_1 chi_2 chi_3 <= 512 (chi <= 8).
+// AfterBNNCD..AfterBN1).  CN is the register width of the kernels: every chi_j and k_j is at
+// most CN (8 or 12; chosen by the host from the dims).
 //
-// Prime chain: workgroup (h, c') with h = (rho, nc) a row of the check copy; X = T[h][(c', nc')],
-// then the three U contractions one leg at a time,
-//   Z1[nh1][nc2][nc3] = sum_{nc1} U1[nh1 + chi1 nc1][n1] X[nc1][nc2][nc3],
-//   Z2[nh1][nh2][nc3] = sum_{nc2} U2[nh2 + chi2 nc2][n2] Z1[nh1][nc2][nc3],
+// Prime chain: workgroup (h, c') with h = (rho, nc) a row of the check copy; X = T[h][(c', nc')]
+// in LDS, then the three U contractions one leg at a time,
+//   Z1[nh1][nc2][nc3] = sum_{nc1} U1[nh1 + chi1 nc1][n1] X[nc1][nc2][nc3]        (once per n1),
+//   Z2[nh1][nh2][nc3] = sum_{nc2} U2[nh2 + chi2 nc2][n2] Z1[nh1][nc2][nc3]      (once per (n1, n2)),
 //   B[(pair, c', nc)][(rho, nh1, nh2, nh3)] = sum_{nc3} U3[nh3 + chi3 nc3][n3] Z2[nh1][nh2][nc3],
-// pairs (n1, n2, n3) in [pr0, pr1) with n1 outermost; Z1 is made once per n1, Z2 once per (n1, n2).
+// pairs (n1, n2, n3) in [pr0, pr1) with n1 outermost.  Each contraction has one thread per
+// column of its input ((nc2, nc3), then (nh1, nc3), then (pair, nh1, nh2)) that forms all
+// outputs of the column in registers; the U slices sit in LDS as rows of CN (zero-padded), so
+// a thread reads one row per input element (the same address across the wave).  The B rows of
+// a batch of pairs go through LDS and are written in consecutive 16-byte runs.
 // ---------------------------------------------------------------------------
-constexpr int B4_MAX = 512;
-template <class MT, class UT, int F>
+template <class MT, class UT, int F, int CN>
 __global__ __launch_bounds__(256) void k_pstage4(const MT* __restrict__ T, const UT* __restrict__ U1,
                                                  const UT* __restrict__ U2, const UT* __restrict__ U3, Dims dm,
                                                  int pr0, int pr1, typename Store<F>::T* __restrict__ B, long ldb,
                                                  long bplane, const DevState* __restrict__ st) {
-  __shared__ MT X[B4_MAX], Z1[B4_MAX], Z2[B4_MAX];
+  constexpr int BM = CN * CN * CN;                                   // b <= BM
+  __shared__ __attribute__((aligned(16))) MT X[BM], Z1[BM], Z2[BM], O[BM];
+  __shared__ __attribute__((aligned(16))) MT u1s[CN * CN], u2s[CN * CN];   // [m][nh]
+  __shared__ __attribute__((aligned(16))) MT u3s[CN * CN * CN];            // [n3][m][nh3]
   const int tid = threadIdx.x;
   const int h = blockIdx.x / dm.chic, cp = blockIdx.x % dm.chic;
   const int b = dm.b, c1 = dm.chi1, c2 = dm.chi2, c3 = dm.chi3, k1 = dm.k1, k2 = dm.k2, k3 = dm.k3;
+  const int c23 = c2 * c3, c12 = c1 * c2;
   const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * sqrt((double)b)) : 1.0;
   const int rho = h / b, nc = h % b;
-  for (int i = tid; i < b; i += blockDim.x) X[i] = T[(long)h * dm.H + (long)cp * b + i];
+  for (int i = tid; i < b; i += 256) X[i] = T[(long)h * dm.H + (long)cp * b + i];
+  for (int i = tid; i < k3 * c3 * CN; i += 256) {
+    const int nh3 = i % CN, m = (i / CN) % c3, n3 = i / (CN * c3);
+    u3s[i] = nh3 < c3 ? (MT)U3[(nh3 + c3 * m) * k3 + n3] : (MT)0;
+  }
+  const int PB = max(1, min(256 / c12, BM / b));                    // pairs per batch of B rows
   int n1cur = -1;
   for (int pr = pr0; pr < pr1;) {
     const int n1 = pr / (k2 * k3), n2 = (pr / k3) % k2;
-    const int pe = min(pr1, (n1 * k2 + n2 + 1) * k3);   // end of this (n1, n2) group
-    __syncthreads();                                   // X staged / Z1, Z2 of the last group consumed
-    if (n1 != n1cur) {
-      for (int i = tid; i < b; i += blockDim.x) {      // i = (nh1, nc2, nc3)
-        const int nh1 = i / (c2 * c3), r = i % (c2 * c3);
-        MT s = 0;
-        for (int m = 0; m < c1; ++m) s += (MT)U1[(nh1 + c1 * m) * k1 + n1] * X[m * c2 * c3 + r];
-        Z1[i] = s;
+    const int pe = min(pr1, (n1 * k2 + n2 + 1) * k3);                // end of this (n1, n2) group
+    const bool new1 = n1 != n1cur;
+    __syncthreads();                                                 // the last group's LDS consumed
+    if (new1)
+      for (int i = tid; i < c1 * CN; i += 256) {
+        const int nh = i % CN, m = i / CN;
+        u1s[i] = nh < c1 ? (MT)U1[(nh + c1 * m) * k1 + n1] : (MT)0;
+      }
+    for (int i = tid; i < c2 * CN; i += 256) {
+      const int nh = i % CN, m = i / CN;
+      u2s[i] = nh < c2 ? (MT)U2[(nh + c2 * m) * k2 + n2] : (MT)0;
+    }
+    __syncthreads();
+    if (new1) {
+      if (tid < c23) {                                               // column (nc2, nc3): all nh1
+        MT acc[CN];
+#pragma unroll
+        for (int e = 0; e < CN; ++e) acc[e] = 0;
+        for (int m = 0; m < c1; ++m) {
+          const MT x = X[m * c23 + tid];
+          const MT* u = &u1s[m * CN];
+#pragma unroll
+          for (int e = 0; e < CN; ++e) acc[e] += u[e] * x;
+        }
+#pragma unroll
+        for (int e = 0; e < CN; ++e)
+          if (e < c1) Z1[e * c23 + tid] = acc[e];
       }
       n1cur = n1;
       __syncthreads();
     }
-    for (int i = tid; i < b; i += blockDim.x) {        // i = (nh1, nh2, nc3)
-      const int nh1 = i / (c2 * c3), nh2 = (i / c3) % c2, nc3 = i % c3;
-      MT s = 0;
-      for (int m = 0; m < c2; ++m) s += (MT)U2[(nh2 + c2 * m) * k2 + n2] * Z1[(nh1 * c2 + m) * c3 + nc3];
-      Z2[i] = s;
+    if (tid < c1 * c3) {                                             // column (nh1, nc3): all nh2
+      const int nh1 = tid / c3, nc3 = tid % c3;
+      MT acc[CN];
+#pragma unroll
+      for (int e = 0; e < CN; ++e) acc[e] = 0;
+      for (int m = 0; m < c2; ++m) {
+        const MT z = Z1[(nh1 * c2 + m) * c3 + nc3];
+        const MT* u = &u2s[m * CN];
+#pragma unroll
+        for (int e = 0; e < CN; ++e) acc[e] += u[e] * z;
+      }
+#pragma unroll
+      for (int e = 0; e < CN; ++e)
+        if (e < c2) Z2[(nh1 * c2 + e) * c3 + nc3] = acc[e];
     }
-    __syncthreads();
-    for (int q = pr; q < pe; ++q) {
-      const int n3 = q % k3;
-      const long row = (long)((q - pr0) * dm.chic + cp) * b + nc;
-      for (int i = tid; i < b; i += blockDim.x) {      // i = (nh1, nh2, nh3)
-        const int nh3 = i % c3, base = (i / c3) * c3;
-        MT s = 0;
-        for (int m = 0; m < c3; ++m) s += (MT)U3[(nh3 + c3 * m) * k3 + n3] * Z2[base + m];
-        put_scaled<F>(B, row * ldb + (long)rho * b + i, bplane, s, sB);
+    for (int q0 = pr; q0 < pe; q0 += PB) {
+      const int np = min(PB, pe - q0);
+      __syncthreads();                                               // Z2 complete / O consumed
+      {
+        const int ps = tid / c12, a = tid % c12;                     // pair q0 + ps, row (nh1, nh2)
+        if (ps < np) {
+          const int n3 = (q0 + ps) % k3;
+          MT acc[CN];
+#pragma unroll
+          for (int e = 0; e < CN; ++e) acc[e] = 0;
+          for (int m = 0; m < c3; ++m) {
+            const MT z = Z2[a * c3 + m];
+            const MT* u = &u3s[(n3 * c3 + m) * CN];
+#pragma unroll
+            for (int e = 0; e < CN; ++e) acc[e] += u[e] * z;
+          }
+#pragma unroll
+          for (int e = 0; e < CN; ++e)
+            if (e < c3) O[ps * b + a * c3 + e] = acc[e];
+        }
+      }
+      __syncthreads();
+      // row (q, c', nc) of B, columns rho b + i (Kp and b multiples of the vector width)
+      auto row_of = [&](int ps) { return (long)((q0 + ps - pr0) * dm.chic + cp) * b + nc; };
+      if (b % 8 == 0) {
+        const int nv = b / 8;
+        for (int v = tid; v < np * nv; v += 256) {
+          const int ps = v / nv, i = (v % nv) * 8;
+          store_vec_scaled<F, 8>(B, row_of(ps) * ldb + (long)rho * b + i, bplane, &O[ps * b + i], sB);
+        }
+      } else if (b % 4 == 0) {
+        const int nv = b / 4;
+        for (int v = tid; v < np * nv; v += 256) {
+          const int ps = v / nv, i = (v % nv) * 4;
+          store_vec_scaled<F, 4>(B, row_of(ps) * ldb + (long)rho * b + i, bplane, &O[ps * b + i], sB);
+        }
+      } else {
+        for (int v = tid; v < np * b; v += 256) {
+          const int ps = v / b, i = v % b;
+          put_scaled<F>(B, row_of(ps) * ldb + (long)rho * b + i, bplane, O[ps * b + i], sB);
+        }
       }
     }
     pr = pe;
   }
 }
 
-// Non-prime chain (4D): workgroup (c, g); the (c, g) block of C is b x b, rows (nh1, nh2, nh3),
-// columns (nc1, nc2, nc3):
-//   W3[(nh1, nh2, nc1, nc2)][n3] = sum_{nh3, nc3} U3[nh3 + chi3 nc3][n3] C[..][..]  (each thread
-//     reads chi3 x chi3 sub-blocks straight from memory),
-//   W2[(nh1, nc1)][(n2, n3)] = sum_{nh2, nc2} U2[nh2 + chi2 nc2][n2] W3[..][n3],
-//   T^next[(n1, n2, n3, c)][g] = sum_{nh1, nc1} U1[nh1 + chi1 nc1][n1] W2[..][(n2, n3)].
-// W3 and W2 in LDS in the accumulation type AT: (chi1 chi2)^2 k3 + chi1^2 k2 k3 elements, at most
-// n4_lds_cap<AT>() (chi <= 8 in FP32, chi <= 7 in FP64; checked by the host).
-template <class AT> __host__ __device__ constexpr int n4_lds_cap() { return sizeof(AT) == 4 ? 36864 : 19456; }
-__host__ __device__ inline long n4_lds_need(int c1, int c2, int k2, int k3) {
-  return (long)(c1 * c2) * (c1 * c2) * k3 + (long)c1 * c1 * k2 * k3;
+// Non-prime chain (4D) in two kernels, through a scratch array W2[(c, g)][(nh1, nc1)][(n2, n3)].
+// k_nstage4w: workgroup (c, g), one wave per (nh1, nc1) at a time.  Lane x = (nh2, nc2) reads
+// its chi3 x chi3 sub-block of the (c, g) block of C straight from memory (each element once)
+// and forms W3[x][n3] = sum_{nh3, nc3} U3[nh3 + chi3 nc3][n3] C[(nh1, nh2, nh3)][(nc1, nc2, nc3)]
+// in registers; the wave stages W3 in LDS, and lane o = (n2, n3) forms
+//   W2[(nh1, nc1)][o] = sum_{nh2, nc2} U2[nh2 + chi2 nc2][n2] W3[(nh2, nc2)][n3].
+// k_nstage4n: workgroup (c, g), thread o = (n2, n3):
+//   T^next[(n1, n2, n3, c)][g] = sum_{nh1, nc1} U1[nh1 + chi1 nc1][n1] W2[(nh1, nc1)][o].
+// ---------------------------------------------------------------------------
+template <class AT, class UT, int CN>
+__global__ __launch_bounds__(256) void k_nstage4w(const AT* __restrict__ C, long ldc, const UT* __restrict__ U2,
+                                                  const UT* __restrict__ U3, Dims dm, int gcount,
+                                                  AT* __restrict__ W2) {
+  __shared__ __attribute__((aligned(16))) AT u3s[CN * CN * CN];     // [(nh3 chi3 + nc3)][n3 < CN]
+  __shared__ __attribute__((aligned(16))) AT u2s[CN * CN * CN];     // [(nh2 chi2 + nc2)][n2 < k2]
+  __shared__ __attribute__((aligned(16))) AT w3s[4][CN * CN * CN];  // per wave: [(nh2 chi2 + nc2)][n3 < CN]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = blockIdx.x / gcount, gl = blockIdx.x % gcount;
+  const int b = dm.b, c1 = dm.chi1, c2 = dm.chi2, c3 = dm.chi3, k2 = dm.k2, k3 = dm.k3;
+  const int c22 = c2 * c2, n23 = k2 * k3, c11 = c1 * c1;
+  for (int i = tid; i < c3 * c3 * CN; i += 256) {
+    const int n3 = i % CN, x = i / CN, nh3 = x / c3, nc3 = x % c3;
+    u3s[i] = n3 < k3 ? (AT)U3[(nh3 + c3 * nc3) * k3 + n3] : (AT)0;
+  }
+  for (int i = tid; i < c22 * k2; i += 256) {
+    const int n2 = i % k2, x = i / k2, nh2 = x / c2, nc2 = x % c2;
+    u2s[i] = (AT)U2[(nh2 + c2 * nc2) * k2 + n2];
+  }
+  AT* w3 = w3s[wave];
+  const AT* Cb = C + (long)c * b * ldc + (long)gl * b;
+  AT* W2b = W2 + (long)blockIdx.x * c11 * n23;
+  const bool vec4 = c3 % 4 == 0;      // FP32: rows of a sub-block as 16-byte loads (ldc, b multiples of 4)
+  for (int it0 = 0; it0 < c11; it0 += 4) {                          // the same trip count in every wave
+    const int it = it0 + wave, nh1 = it / c1, nc1 = it % c1;
+    __syncthreads();                                                // u2s, u3s staged / w3 consumed
+    if (it < c11)
+      for (int x = lane; x < c22; x += 64) {
+        const int nh2 = x / c2, nc2 = x % c2;
+        AT acc[CN];
+#pragma unroll
+        for (int e = 0; e < CN; ++e) acc[e] = 0;
+        const AT* Cs = Cb + (long)((nh1 * c2 + nh2) * c3) * ldc + (nc1 * c2 + nc2) * c3;
+        for (int nh3 = 0; nh3 < c3; ++nh3) {
+          const AT* row = Cs + (long)nh3 * ldc;
+          const AT* ur = &u3s[nh3 * c3 * CN];
+          if constexpr (sizeof(AT) == 4) {
+            if (vec4) {
+              for (int q = 0; q < c3; q += 4) {
+                const f4v v4 = *reinterpret_cast<const f4v*>(row + q);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                  const AT v = v4[t];
+                  const AT* u = ur + (q + t) * CN;
+#pragma unroll
+                  for (int e = 0; e < CN; ++e) acc[e] += v * u[e];
+                }
+              }
+              continue;
+            }
+          }
+          for (int nc3 = 0; nc3 < c3; ++nc3) {
+            const AT v = row[nc3];
+            const AT* u = ur + nc3 * CN;
+#pragma unroll
+            for (int e = 0; e < CN; ++e) acc[e] += v * u[e];
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < CN; ++e) w3[x * CN + e] = acc[e];
+      }
+    __syncthreads();
+    if (it < c11)
+      for (int o = lane; o < n23; o += 64) {
+        const int n2 = o / k3, n3 = o % k3;
+        AT sacc = 0;
+        for (int x = 0; x < c22; ++x) sacc += u2s[x * k2 + n2] * w3[x * CN + n3];
+        W2b[(long)it * n23 + o] = sacc;
+      }
+  }
 }
-template <class AT, class MT, class UT>
-__global__ __launch_bounds__(256) void k_nstage4(const AT* __restrict__ C, long ldc, const UT* __restrict__ U1,
-                                                 const UT* __restrict__ U2, const UT* __restrict__ U3, Dims dm,
-                                                 int g0, int gcount, MT* __restrict__ Tn) {
-  __shared__ AT lds[n4_lds_cap<AT>()];
+
+template <class AT, class MT, class UT, int CN>
+__global__ __launch_bounds__(256) void k_nstage4n(const AT* __restrict__ W2, const UT* __restrict__ U1, Dims dm,
+                                                  int g0, int gcount, MT* __restrict__ Tn) {
+  __shared__ __attribute__((aligned(16))) AT u1s[CN * CN * CN];     // [(nh1 chi1 + nc1)][n1 < CN]
   const int tid = threadIdx.x;
   const int c = blockIdx.x / gcount, gl = blockIdx.x % gcount;
-  const int b = dm.b, c1 = dm.chi1, c2 = dm.chi2, c3 = dm.chi3, k1 = dm.k1, k2 = dm.k2, k3 = dm.k3;
-  const int Hn = k1 * k2 * k3 * dm.chic;
-  const int p12 = c1 * c2, ncomb = p12 * p12;
-  AT* W3 = lds;                       // [(nh1 c2 + nh2) (c1 c2) + nc1 c2 + nc2][n3]
-  AT* W2 = lds + (long)ncomb * k3;    // [(nh1 c1 + nc1)][n2 k3 + n3]
-  const AT* Cb = C + (long)c * b * ldc + (long)gl * b;
-  for (int t = tid; t < ncomb; t += blockDim.x) {
-    const int hp = t / p12, cpp = t % p12;   // (nh1, nh2), (nc1, nc2)
-    AT acc[8];
+  const int c1 = dm.chi1, k1 = dm.k1, n23 = dm.k2 * dm.k3, c11 = c1 * c1;
+  for (int i = tid; i < c11 * CN; i += 256) {
+    const int n1 = i % CN, x = i / CN, nh1 = x / c1, nc1 = x % c1;
+    u1s[i] = n1 < k1 ? (AT)U1[(nh1 + c1 * nc1) * k1 + n1] : (AT)0;
+  }
+  __syncthreads();
+  const long Hn = (long)k1 * n23 * dm.chic;
+  const AT* W2b = W2 + (long)blockIdx.x * c11 * n23;
+  for (int o = tid; o < n23; o += 256) {
+    AT acc[CN];
 #pragma unroll
-    for (int n3 = 0; n3 < 8; ++n3) acc[n3] = 0;
-    for (int nh3 = 0; nh3 < c3; ++nh3) {
-      const AT* row = Cb + (long)(hp * c3 + nh3) * ldc + cpp * c3;
-      for (int nc3 = 0; nc3 < c3; ++nc3) {
-        const AT x = row[nc3];
-        const UT* u = U3 + (nh3 + c3 * nc3) * k3;
+    for (int e = 0; e < CN; ++e) acc[e] = 0;
+    for (int x = 0; x < c11; ++x) {
+      const AT w = W2b[(long)x * n23 + o];
+      const AT* u = &u1s[x * CN];
 #pragma unroll
-        for (int n3 = 0; n3 < 8; ++n3)
-          if (n3 < k3) acc[n3] += x * (AT)u[n3];
-      }
+      for (int e = 0; e < CN; ++e) acc[e] += u[e] * w;
     }
 #pragma unroll
-    for (int n3 = 0; n3 < 8; ++n3)
-      if (n3 < k3) W3[t * k3 + n3] = acc[n3];
-  }
-  __syncthreads();
-  const int n23 = k2 * k3;
-  for (int o = tid; o < c1 * c1 * n23; o += blockDim.x) {   // o = ((nh1, nc1), (n2, n3))
-    const int hc = o / n23, q = o % n23, nh1 = hc / c1, nc1 = hc % c1, n2 = q / k3, n3 = q % k3;
-    AT s = 0;
-    for (int nh2 = 0; nh2 < c2; ++nh2)
-      for (int nc2 = 0; nc2 < c2; ++nc2)
-        s += (AT)U2[(nh2 + c2 * nc2) * k2 + n2] * W3[((nh1 * c2 + nh2) * p12 + nc1 * c2 + nc2) * k3 + n3];
-    W2[o] = s;
-  }
-  __syncthreads();
-  for (int o = tid; o < k1 * n23; o += blockDim.x) {        // o = (n1, n2, n3)
-    const int q = o % n23, n1 = o / n23;
-    AT s = 0;
-    for (int nh1 = 0; nh1 < c1; ++nh1)
-      for (int nc1 = 0; nc1 < c1; ++nc1) s += (AT)U1[(nh1 + c1 * nc1) * k1 + n1] * W2[(nh1 * c1 + nc1) * n23 + q];
-    Tn[(long)(o * dm.chic + c) * Hn + (g0 + gl)] = (MT)s;
+    for (int e = 0; e < CN; ++e)
+      if (e < k1) Tn[((long)(e * n23 + o) * dm.chic + c) * Hn + g0 + gl] = (MT)acc[e];
   }
 }
 

@@ -134,8 +134,8 @@ def test_supplied_tensor_argument_validation():
     assert P.hotrg_tensor_workspace_bytes(3, [17, 4, 2], 6, o) == 0       # above the 3D maximum
     assert P.hotrg_tensor_workspace_bytes(3, [0, 4, 2], 6, o) == 0
     assert P.hotrg_tensor_workspace_bytes(5, [2, 2, 2, 2, 2], 6, o) == 0
-    assert P.hotrg_tensor_workspace_bytes(4, [2, 2, 2, 2], 8, o) == 0      # FP64 4D: chi <= 7
-    assert P.hotrg_tensor_workspace_bytes(4, [2, 2, 2, 2], 6, o) > 0
+    assert P.hotrg_tensor_workspace_bytes(4, [2, 2, 2, 2], 13, o) == 0     # 4D: chi <= 12
+    assert P.hotrg_tensor_workspace_bytes(4, [2, 2, 2, 2], 12, o) > 0
     assert P.hotrg_tensor_workspace_bytes(3, [3, 4, 2], 6, P.hotrg_opts(P.HOTRG_FP64, 8, 0, 1)) == 0   # no beta
     # the plan covers the dims the run reaches from (3, 4, 2): it is at least that of a model run
     # whose dims pass through the same values
@@ -157,17 +157,18 @@ def test_truncated_eigensolver_argument_validation():
 
 
 def test_four_dimensional_limits():
-    # 4D: chi <= 8 in the reduced forms, 7 in FP64 (the non-prime chain's LDS); no derivative mode
-    # and no batches for d = 4
+    # 4D: chi <= 12 in every form (the register width of the 4D chain kernels); no derivative
+    # mode and no batches for d = 4
     ising4 = P.hotrg_model(P.HOTRG_ISING, 4, 2, 1.0, 0.0)
-    for prec, chi, ok in [(P.HOTRG_SPLIT_FP16, 8, True), (P.HOTRG_FP32, 8, True), (P.HOTRG_SPLIT_FP16, 9, False),
-                          (P.HOTRG_FP64, 7, True), (P.HOTRG_FP64, 8, False)]:
+    for prec, chi, ok in [(P.HOTRG_SPLIT_FP16, 8, True), (P.HOTRG_FP32, 12, True), (P.HOTRG_SPLIT_FP16, 13, False),
+                          (P.HOTRG_FP64, 12, True), (P.HOTRG_FP64, 13, False)]:
         assert (P.hotrg_workspace_bytes(ising4, chi, P.hotrg_opts(prec, 8, 0, 0)) > 0) == ok, (prec, chi)
     assert P.hotrg_workspace_bytes(ising4, 4, P.hotrg_opts(P.HOTRG_FP64, 8, 0, 1)) == 0
     inst = (P.hotrg_instance * 1)(P.hotrg_instance(ising4, 0.15, 4, 0))
     assert P.lib().hotrg_batch_workspace_bytes(inst, 1, ctypes.byref(P.hotrg_opts(P.HOTRG_FP64, 8, 0, 0))) == 0
     assert P.hotrg_debug_workspace_bytes(4, [8, 8, 8, 8], [8, 8, 8], P.HOTRG_SPLIT_FP16) > 0
-    assert P.hotrg_debug_workspace_bytes(4, [8, 8, 8, 8], [8, 8, 8], P.HOTRG_FP64) == 0
+    assert P.hotrg_debug_workspace_bytes(4, [12, 12, 12, 12], [12, 12, 12], P.HOTRG_FP64) > 0
+    assert P.hotrg_debug_workspace_bytes(4, [13, 2, 2, 2], [4, 4, 4], P.HOTRG_FP32) == 0
 
 
 def test_eigh_workspace_holds_the_failure_flag():

@@ -50,7 +50,11 @@ CASES_3D = [
     ((4, 4, 2), (16, 4)),
 ]
 CASES_2D = [((8, 8), (16,)), ((5, 7), (9,)), ((32, 32), (32,))]
-CASES_4D = [((2, 3, 2, 2), (4, 3, 2)), ((3, 2, 3, 2), (4, 4, 4)), ((4, 4, 4, 4), (7, 7, 7))]
+# 4D: b = chi1 chi2 chi3 a multiple of 8, of 4 only, and odd (the three store widths of the prime
+# chain); every dim <= 8 (register width 8) and some dim above 8 (width 12), with chi3 a multiple
+# of 4 (16-byte loads in the non-prime chain) and not
+CASES_4D = [((2, 3, 2, 2), (4, 3, 2)), ((3, 2, 3, 2), (4, 4, 4)), ((4, 4, 4, 4), (7, 7, 7)),
+            ((3, 3, 3, 3), (5, 6, 7)), ((2, 12, 2, 4), (12, 4, 12)), ((2, 9, 3, 10), (12, 9, 11))]
 
 
 def _random_case(dims, kdims, seed):
@@ -92,7 +96,7 @@ def test_contract_fp64_matches_oracle(dims, kdims):
                                   P.HOTRG_BF16])
 @pytest.mark.parametrize("dims,kdims", [((8, 8, 8), (8, 8)), ((3, 5, 4), (7, 6)), ((8, 8), (16,)),
                                        ((3, 12, 12), (12, 12)), ((2, 12, 12), (12, 12)),
-                                       ((3, 3, 3, 3), (4, 4, 4))])
+                                       ((3, 3, 3, 3), (4, 4, 4)), ((2, 12, 2, 4), (12, 4, 12))])
 def test_contract_forms_match_oracle(form, dims, kdims):
     # (3, 12, 12): chi = 12 with an odd number of c, the 256 x 256 GEMM and a separate non-prime
     # kernel; (2, 12, 12): the 288 x 288 GEMM with the non-prime chain in its epilogue
@@ -135,7 +139,8 @@ def _full4d_reference():
     return Ts, Us, oracle_next_storage(LY.to_paper(Ts), Us, only=FULL4D_PICKS)
 
 
-@pytest.mark.parametrize("form", [P.HOTRG_SPLIT_FP16, P.HOTRG_FP32, P.HOTRG_SPLIT_BF16, P.HOTRG_FP16, P.HOTRG_BF16])
+@pytest.mark.parametrize("form", [P.HOTRG_SPLIT_FP16, P.HOTRG_FP64, P.HOTRG_FP32, P.HOTRG_SPLIT_BF16, P.HOTRG_FP16,
+                                  P.HOTRG_BF16])
 def test_contract_4d_full_size_sampled(form):
     """4D chi = 8 (M = K = 4096, the three-leg prime and non-prime chains, the 256 x 256 GEMM):
     8 spread (n'_1, n'_2, n'_3) slices of the new tensor against the oracle, element by element."""
@@ -144,6 +149,28 @@ def test_contract_4d_full_size_sampled(form):
     worst, errs = PT.worst_slice_error(got, ref, FULL4D_PICKS)
     print(f"{FORM_NAME[form]} 4D chi=8 full size, 8 slices: max slice error {worst:.2e} "
           f"(bound {SLICE_BOUND[form]:.0e}); per slice " + " ".join(f"{e:.1e}" for e in errs))
+    assert worst < SLICE_BOUND[form]
+
+
+CHI10_4D_DIMS, CHI10_4D_K, CHI10_4D_SEED = (10, 10, 10, 10), (10, 10, 10), 21
+CHI10_4D_PICKS = PT.spread_picks(CHI10_4D_K, 3)
+
+
+@functools.lru_cache(maxsize=None)
+def _chi10_4d_reference():
+    Ts, Us = _random_case(CHI10_4D_DIMS, CHI10_4D_K, CHI10_4D_SEED)
+    return Ts, Us, oracle_next_storage(LY.to_paper(Ts), Us, only=CHI10_4D_PICKS)
+
+
+@pytest.mark.parametrize("form", [P.HOTRG_SPLIT_FP16, P.HOTRG_FP64, P.HOTRG_FP32])
+def test_contract_4d_chi10_sampled(form):
+    """4D chi = 10 (M = K = 10^4, ragged 256 x 256 tiles; the chain kernels at register width 12
+    with chi3 not a multiple of 4): 3 spread (n'_1, n'_2, n'_3) slices against the oracle."""
+    Ts, Us, ref = _chi10_4d_reference()
+    got = gu.contract(Ts, Us, list(CHI10_4D_K), form)
+    worst, errs = PT.worst_slice_error(got, ref, CHI10_4D_PICKS)
+    print(f"{FORM_NAME[form]} 4D chi=10, 3 slices: max slice error {worst:.2e} (bound {SLICE_BOUND[form]:.0e}); "
+          "per slice " + " ".join(f"{e:.1e}" for e in errs))
     assert worst < SLICE_BOUND[form]
 
 
