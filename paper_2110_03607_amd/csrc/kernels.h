@@ -2903,9 +2903,10 @@ __global__ __launch_bounds__(256) void k_pstage4(const MT* __restrict__ T, const
                                                  int pr0, int pr1, typename Store<F>::T* __restrict__ B, long ldb,
                                                  long bplane, const DevState* __restrict__ st) {
   constexpr int BM = CN * CN * CN;                                   // b <= BM
-  __shared__ __attribute__((aligned(16))) MT X[BM], Z1[BM], Z2[BM], O[BM];
-  __shared__ __attribute__((aligned(16))) MT u1s[CN * CN], u2s[CN * CN];   // [m][nh]
-  __shared__ __attribute__((aligned(16))) MT u3s[CN * CN * CN];            // [n3][m][nh3]
+  constexpr int OCAP = CN == 8 ? 4 * BM : BM;                        // staged B rows (4 pairs at chi = 8)
+  __shared__ __attribute__((aligned(16))) MT X[BM], Z1[BM], Z2[BM], O[OCAP];
+  // U_j for every n_j as rows of CN (zero-padded): u_j[(n_j chi_j + m) CN + nh] = U_j[nh + chi_j m][n_j]
+  __shared__ __attribute__((aligned(16))) MT u1s[CN * CN * CN], u2s[CN * CN * CN], u3s[CN * CN * CN];
   const int tid = threadIdx.x;
   const int h = blockIdx.x / dm.chic, cp = blockIdx.x % dm.chic;
   const int b = dm.b, c1 = dm.chi1, c2 = dm.chi2, c3 = dm.chi3, k1 = dm.k1, k2 = dm.k2, k3 = dm.k3;
@@ -2913,35 +2914,30 @@ __global__ __launch_bounds__(256) void k_pstage4(const MT* __restrict__ T, const
   const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * sqrt((double)b)) : 1.0;
   const int rho = h / b, nc = h % b;
   for (int i = tid; i < b; i += 256) X[i] = T[(long)h * dm.H + (long)cp * b + i];
-  for (int i = tid; i < k3 * c3 * CN; i += 256) {
-    const int nh3 = i % CN, m = (i / CN) % c3, n3 = i / (CN * c3);
-    u3s[i] = nh3 < c3 ? (MT)U3[(nh3 + c3 * m) * k3 + n3] : (MT)0;
-  }
-  const int PB = max(1, min(256 / c12, BM / b));                    // pairs per batch of B rows
+  auto stage_u = [&](MT* us, const UT* U, int cj, int kj) {
+    for (int i = tid; i < kj * cj * CN; i += 256) {
+      const int nh = i % CN, m = (i / CN) % cj, n = i / (CN * cj);
+      us[i] = nh < cj ? (MT)U[(nh + cj * m) * kj + n] : (MT)0;
+    }
+  };
+  stage_u(u1s, U1, c1, k1);
+  stage_u(u2s, U2, c2, k2);
+  stage_u(u3s, U3, c3, k3);
+  __syncthreads();
+  const int PB = max(1, min(256 / c12, OCAP / b));                  // pairs per batch of B rows
   int n1cur = -1;
   for (int pr = pr0; pr < pr1;) {
     const int n1 = pr / (k2 * k3), n2 = (pr / k3) % k2;
     const int pe = min(pr1, (n1 * k2 + n2 + 1) * k3);                // end of this (n1, n2) group
-    const bool new1 = n1 != n1cur;
-    __syncthreads();                                                 // the last group's LDS consumed
-    if (new1)
-      for (int i = tid; i < c1 * CN; i += 256) {
-        const int nh = i % CN, m = i / CN;
-        u1s[i] = nh < c1 ? (MT)U1[(nh + c1 * m) * k1 + n1] : (MT)0;
-      }
-    for (int i = tid; i < c2 * CN; i += 256) {
-      const int nh = i % CN, m = i / CN;
-      u2s[i] = nh < c2 ? (MT)U2[(nh + c2 * m) * k2 + n2] : (MT)0;
-    }
-    __syncthreads();
-    if (new1) {
+    // the last group's reads of Z1 and Z2 ended before the barriers of its B batches
+    if (n1 != n1cur) {
       if (tid < c23) {                                               // column (nc2, nc3): all nh1
         MT acc[CN];
 #pragma unroll
         for (int e = 0; e < CN; ++e) acc[e] = 0;
         for (int m = 0; m < c1; ++m) {
           const MT x = X[m * c23 + tid];
-          const MT* u = &u1s[m * CN];
+          const MT* u = &u1s[(n1 * c1 + m) * CN];
 #pragma unroll
           for (int e = 0; e < CN; ++e) acc[e] += u[e] * x;
         }
@@ -2959,7 +2955,7 @@ __global__ __launch_bounds__(256) void k_pstage4(const MT* __restrict__ T, const
       for (int e = 0; e < CN; ++e) acc[e] = 0;
       for (int m = 0; m < c2; ++m) {
         const MT z = Z1[(nh1 * c2 + m) * c3 + nc3];
-        const MT* u = &u2s[m * CN];
+        const MT* u = &u2s[(n2 * c2 + m) * CN];
 #pragma unroll
         for (int e = 0; e < CN; ++e) acc[e] += u[e] * z;
       }
