@@ -33,7 +33,7 @@ def test_antiferromagnet_is_rejected():
         H.bond_factor(W)
 
 
-@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("d", [2, 3, 4])
 @pytest.mark.parametrize("kind,q", [("ising", 2), ("potts", 3)])
 def test_initial_trace_closed_form(d, kind, q):
     # Tr T0 = sum_s V_s W_ss^d: a single site with d self-bonds.  h = 0: q e^{d beta J}
@@ -93,9 +93,26 @@ def test_3d_ising_tori_up_to_2x2x2(beta):
     _check_tori(H.Model("ising", 3), beta, chi=16, steps=3)
 
 
+@pytest.mark.parametrize("beta", [0.1, 0.1497, 0.3])
+def test_4d_ising_2x1x1x1_torus(beta):
+    # one untruncated 4D step (every leg of dimension <= 4): the 2-site torus, by enumeration
+    _check_tori(H.Model("ising", 4), beta, chi=4, steps=1)
+
+
+def test_4d_ising_2x1x1x1_closed_form():
+    # 2x1x1x1 torus: the two sites share two bonds along axis 0 (e^{2b s s'}) and each has a
+    # self-bond along each other axis (e^{3b} per site for either spin), so
+    # Z = sum_{s,s'} e^{6b} e^{2b s s'} = 2 e^{8b} + 2 e^{4b}.
+    beta = 0.2
+    _, recs = H.run(H.Model("ising", 4), beta, chi=4, steps=1)
+    z = math.log(2 * math.exp(8 * beta) + 2 * math.exp(4 * beta))
+    assert recs[0].lnz_per_site == pytest.approx(z / 2, rel=1e-15)
+
+
 def test_ising_with_field_tori():
     _check_tori(H.Model("ising", 2, h=0.3), 0.5, chi=16, steps=4)
     _check_tori(H.Model("ising", 3, h=-0.2), 0.25, chi=16, steps=2)
+    _check_tori(H.Model("ising", 4, h=0.1), 0.2, chi=4, steps=1)
 
 
 def test_potts_tori():
@@ -125,14 +142,17 @@ def _explicit_m(T):
         # M[(n^ n~), (n'^ n'~), c, c'] = sum_rho T[n^, n'^, c, rho] T[n~, n'~, rho, c']
         M = np.einsum("aAcr,bBrC->abABcC", T, T)
         return M
-    # d = 3: T[n2, n1, n2', n1', c, c']
-    return np.einsum("xyXYcr,uvUVrC->xuyvXUYVcC", T, T)
+    if d == 3:
+        # T[n2, n1, n2', n1', c, c']
+        return np.einsum("xyXYcr,uvUVrC->xuyvXUYVcC", T, T)
+    # d = 4: T[n3, n2, n1, n3', n2', n1', c, c']
+    return np.einsum("xyzXYZcr,uvwUVWrC->xuyvzwXUYVZWcC", T, T)
 
 
-@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("d", [2, 3, 4])
 def test_gram_three_steps_equals_explicit_mmt(d):
     rng = np.random.default_rng(5)
-    dims = {2: (3, 3, 2, 2), 3: (2, 3, 2, 3, 2, 2)}[d]
+    dims = {2: (3, 3, 2, 2), 3: (2, 3, 2, 3, 2, 2), 4: (2, 3, 2, 2, 3, 2, 2, 2)}[d]
     T = rng.standard_normal(dims)
     M = _explicit_m(T)
     for j in range(1, d):
@@ -143,9 +163,12 @@ def test_gram_three_steps_equals_explicit_mmt(d):
             # position of the (hat, check) pair of the side leg in M
             if d == 2:
                 pair = (2, 3) if prime else (0, 1)
-            else:
+            elif d == 3:
                 pair = {(2, False): (0, 1), (1, False): (2, 3),
                         (2, True): (4, 5), (1, True): (6, 7)}[(j, prime)]
+            else:
+                pair = {(3, False): (0, 1), (2, False): (2, 3), (1, False): (4, 5),
+                        (3, True): (6, 7), (2, True): (8, 9), (1, True): (10, 11)}[(j, prime)]
             Mm = np.moveaxis(M, pair, (0, 1))            # [hat, check, rest...]
             # merged row index hat + chi*check -> check is the slow index
             Mm = np.swapaxes(Mm, 0, 1).reshape(chi * chi, -1)
@@ -160,12 +183,20 @@ def _naive_3d_einsum(T, W1, W2):
         T, T, W2, W1, W2, W1, optimize=True)
 
 
+def _naive_4d_einsum(T, W1, W2, W3):
+    # hat copy T[h3, h2, h1, h3p, h2p, h1p, c, r]; check copy T[k3, k2, k1, k3p, k2p, k1p, r, C]
+    # U_j[(h + chi k), n] = W_j[k, h, n]
+    return np.einsum(
+        "abgefhcr,ABGEFHrC,AaN,BbM,GgO,EeP,FfQ,HhS->NMOPQScC",
+        T, T, W3, W2, W1, W3, W2, W1, optimize=True)
+
+
 def _naive_2d_einsum(T, W1):
     # hat T[h1, h1p, c, r]; check T[k1, k1p, r, C]
     return np.einsum("aecr,AErC,AaN,EeP->NPcC", T, T, W1, W1, optimize=True)
 
 
-@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("d", [2, 3, 4])
 def test_three_stage_order_equals_single_expression(d):
     rng = np.random.default_rng(11)
     if d == 2:
@@ -174,12 +205,19 @@ def test_three_stage_order_equals_single_expression(d):
         W1 = U1.reshape(3, 3, 5)
         ref = _naive_2d_einsum(T, W1)
         got = H.new_tensor(T, {1: U1})
-    else:
+    elif d == 3:
         T = rng.standard_normal((3, 2, 3, 2, 2, 2))  # n2=3, n1=2, c=2
         U1 = SI.random_isometry(4, 3, seed=1)
         U2 = SI.random_isometry(9, 4, seed=2)
         ref = _naive_3d_einsum(T, U1.reshape(2, 2, 3), U2.reshape(3, 3, 4))
         got = H.new_tensor(T, {1: U1, 2: U2})
+    else:
+        T = rng.standard_normal((2, 3, 2, 2, 3, 2, 2, 2))  # n3=2, n2=3, n1=2, c=2
+        U1 = SI.random_isometry(4, 3, seed=1)
+        U2 = SI.random_isometry(9, 5, seed=2)
+        U3 = SI.random_isometry(4, 2, seed=3)
+        ref = _naive_4d_einsum(T, U1.reshape(2, 2, 3), U2.reshape(3, 3, 5), U3.reshape(2, 2, 2))
+        got = H.new_tensor(T, {1: U1, 2: U2, 3: U3})
     np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
 
 
@@ -272,7 +310,7 @@ def test_2d_ising_hotrg_converges_to_onsager(T):
     assert errs[16] < 2e-5
 
 
-@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("d", [2, 3, 4])
 def test_infinite_temperature_is_exact(d):
     # beta = 0: W has rank 1, Z = q^N exactly for any chi and any lattice
     _, recs = H.run(H.Model("ising", d), 0.0, 4, 8)
