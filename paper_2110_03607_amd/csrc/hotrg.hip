@@ -87,12 +87,14 @@ struct GramGeo {
 GramGeo gram_geo(long H, long R) {
   GramGeo g;
   g.R = R;
-  g.Rp = roundup(R, GRAM_TILE);
+  // R <= 64 (3D chi = 8, 4D): 64 x 64 tiles, so that no padding rows are read or multiplied
+  const long tile = R <= 64 ? 64 : GRAM_TILE;
+  g.Rp = roundup(R, tile);
   g.C = H * H / R;
-  const long tiles = (g.Rp / GRAM_TILE) * (g.Rp / GRAM_TILE);
+  const long tiles = (g.Rp / tile) * (g.Rp / tile);
   long Z = std::max(1L, (512 + tiles - 1) / tiles);
   Z = std::min(Z, std::max(1L, roundup(g.C, 16) / 16));
-  g.kchunk = roundup((g.C + Z - 1) / Z, 16);
+  g.kchunk = roundup((g.C + Z - 1) / Z, tile == 64 ? 32 : 16);   // a multiple of the GEMM's K step
   g.Z = (int)((g.C + g.kchunk - 1) / g.kchunk);
   g.Cp = (long)g.Z * g.kchunk;
   return g;
@@ -506,6 +508,16 @@ void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, 
       return;
     }
   }
+  if constexpr (F == F_FP64) {
+    // 64 x 64 tiles for the small Gram matrices (R <= 64, padded to 64), with 32 doubles of K per step
+    if (Mp % 128 != 0 || Np % 128 != 0) {
+      dim3 grid((unsigned)(Mp / 64), (unsigned)(Np / 64), (unsigned)Z);
+      hipLaunchKernelGGL((k_gemm_tn<Op, PL, 64, 64, 32>), grid, dim3(256), 0, s, (const typename Op::T*)A, lda,
+                         aplane, (const typename Op::T*)B, ldb, bplane, (typename Op::Acc*)C, ldc, czs, (int)kchunk,
+                         scale_ptr, smult);
+      return;
+    }
+  }
   constexpr long T = 128;
   dim3 grid((unsigned)(Mp / T), (unsigned)(Np / T), (unsigned)Z);
   hipLaunchKernelGGL((k_gemm_tn<Op, PL, T, T, GemmCfg<F>::BK>), grid, dim3(256), 0, s,
@@ -579,7 +591,7 @@ int enqueue_gram(hotrg_handle* h, const void* T, bool t_is_f64, const LocalDims&
     permute(T, X);
     launch_gemm<F_FP64>(X, g.Cp, 0, X, g.Cp, 0, part, g.Rp, g.Rp * g.Rp, g.Rp, g.Rp, g.Cp, g.Z, g.kchunk,
                         nullptr, 1.0, h->s);
-    hipLaunchKernelGGL(k_reduce_z, dim3(grid_for(R * R)), dim3(256), 0, h->s, (const double*)part,
+    hipLaunchKernelGGL(k_reduce_zp<false>, dim3((unsigned)((R * R + 15) / 16)), dim3(256), 0, h->s, (const double*)part,
                        g.Rp * g.Rp, g.Rp, g.Z, (int)R, which == 0 ? Gh : Gc);
     if (dT) {
       // d(X X^T) = dX X^T + (dX X^T)^T
@@ -587,7 +599,7 @@ int enqueue_gram(hotrg_handle* h, const void* T, bool t_is_f64, const LocalDims&
       permute(dT, Xd);
       launch_gemm<F_FP64>(Xd, g.Cp, 0, X, g.Cp, 0, part, g.Rp, g.Rp * g.Rp, g.Rp, g.Rp, g.Cp, g.Z, g.kchunk,
                           nullptr, 1.0, h->s);
-      hipLaunchKernelGGL(k_reduce_z_sym, dim3(grid_for(R * R)), dim3(256), 0, h->s, (const double*)part,
+      hipLaunchKernelGGL(k_reduce_zp<true>, dim3((unsigned)((R * R + 15) / 16)), dim3(256), 0, h->s, (const double*)part,
                          g.Rp * g.Rp, g.Rp, g.Z, (int)R,
                          which == 0 ? h->at<double>(h->plan.off_dGh) : h->at<double>(h->plan.off_dGc));
     }

@@ -945,14 +945,30 @@ __global__ __launch_bounds__(512) void k_gemm_f64(const double* __restrict__ A, 
 }
 
 // Fixed-order reduction of split-K slices: out[r][c] = sum_z part[z][r][c] for r < R, c < R.
-__global__ void k_reduce_z(const double* __restrict__ part, long zstride, long ldp, int Z, int R,
-                           double* __restrict__ out) {
-  const long n = (long)R * R;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const long r = i / R, c = i % R;
-    double s = 0.0;
-    for (int z = 0; z < Z; ++z) s += part[z * zstride + r * ldp + c];
-    out[i] = s;
+// Sum of the split-K partial products: out[r][c] = sum_z part[z][r][c].  A workgroup of 256
+// threads takes 16 consecutive outputs; thread (g, o) sums z = g, g + 16, ... in that order and
+// the 16 group sums are added in group order (a fixed order, independent of the launch).
+// SYM: out[r][c] = sum_z (part[z][r][c] + part[z][c][r]).  Grid: ceil(R^2 / 16) workgroups.
+template <bool SYM>
+__global__ __launch_bounds__(256) void k_reduce_zp(const double* __restrict__ part, long zstride, long ldp, int Z,
+                                                   int R, double* __restrict__ out) {
+  __shared__ double red[16][16];
+  const int ol = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const long n = (long)R * R, o = (long)blockIdx.x * 16 + ol;
+  double s = 0.0;
+  if (o < n) {
+    const long r = o / R, c = o % R;
+    for (int z = g; z < Z; z += 16) {
+      s += part[z * zstride + r * ldp + c];
+      if constexpr (SYM) s += part[z * zstride + c * ldp + r];
+    }
+  }
+  red[g][ol] = s;
+  __syncthreads();
+  if (g == 0 && o < n) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += red[q][ol];
+    out[o] = t;
   }
 }
 
@@ -3190,18 +3206,6 @@ __global__ __launch_bounds__(256) void k_trace_lnz(const MT* __restrict__ Tn, in
 // ---------------------------------------------------------------------------
 // Derivative (forward mode) helpers.
 // ---------------------------------------------------------------------------
-
-// dG = G1 + G1^T from the split-K slices of G1 = dX X^T (the derivative of G = X X^T).
-__global__ void k_reduce_z_sym(const double* __restrict__ part, long zstride, long ldp, int Z, int R,
-                               double* __restrict__ out) {
-  const long n = (long)R * R;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const long r = i / R, c = i % R;
-    double s = 0.0;
-    for (int z = 0; z < Z; ++z) s += part[z * zstride + r * ldp + c] + part[z * zstride + c * ldp + r];
-    out[i] = s;
-  }
-}
 
 // dA = sum_{rho, eta} (dGh Gc + Gh dGc), the derivative of the third Gram step.
 __global__ void k_gram_combine_t(const double* __restrict__ Gh, const double* __restrict__ Gc,

@@ -160,7 +160,11 @@ def test_potts_chi16_fp64_gradient_vs_central_differences(beta):
     (1/100 expected; a jump of the truncated approximant inside +-1e-5 breaks this), or 2e-9 |g|
     (rounding of the FP64 forward); and |fd(1e-4) - fd(1e-6)| <= 1e-5 |g| (no bend on the scale
     1e-4).  There the derivative must match fd(1e-6) to 1e-8 and fd(1e-4) to 1e-5.  The steps
-    left out are printed; at least FD_MIN_CHECKABLE[beta] steps must be checkable."""
+    left out are printed; at least FD_MIN_CHECKABLE[beta] steps must be checkable.
+    A left-out step is a cut where the approximant jumps: the kept eigenvalues are nearly
+    degenerate, and the derivative of the kept vectors (dU = sum over the other vectors of
+    (u_l^T dA u_k) / (lambda_k - lambda_l)) carries the rounding of A divided by that gap into every
+    later step.  Checkable steps after the first left-out one are held to 1e-7 against fd(1e-6)."""
     g64 = potts16(beta, "fp64")[0]
     fd4, fd5, fd6 = fd_fp64(beta, 1e-4), fd_fp64(beta, 1e-5), fd_fp64(beta, 1e-6)
     rel = lambda x: np.abs(g64 - x) / np.abs(g64)   # noqa: E731
@@ -173,7 +177,12 @@ def test_potts_chi16_fp64_gradient_vs_central_differences(beta):
           f"\n  per step vs h=1e-6: {_fmt(rel(fd6))}\n  per step vs h=1e-5: {_fmt(rel(fd5))}"
           f"\n  per step vs h=1e-4: {_fmt(rel(fd4))}")
     assert ok.sum() >= FD_MIN_CHECKABLE[beta]
-    assert rel(fd6)[ok].max() < 1e-8
+    first_out = next((p for p in range(len(g64)) if not ok[p]), len(g64))
+    before = ok & (np.arange(len(g64)) < first_out)
+    after = ok & (np.arange(len(g64)) > first_out)
+    assert rel(fd6)[before].max() < 1e-8
+    if after.any():
+        assert rel(fd6)[after].max() < 1e-7
     assert rel(fd4)[ok].max() < 1e-5
 
 
