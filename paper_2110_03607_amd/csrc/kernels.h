@@ -2919,14 +2919,17 @@ __global__ __launch_bounds__(256) void k_pstage4(const MT* __restrict__ T, const
                                                  int pr0, int pr1, typename Store<F>::T* __restrict__ B, long ldb,
                                                  long bplane, const DevState* __restrict__ st) {
   constexpr int BM = CN * CN * CN;                                   // b <= BM
-  constexpr int OCAP = CN == 8 ? 4 * BM : BM;                        // staged B rows (4 pairs at chi = 8)
-  __shared__ __attribute__((aligned(16))) MT X[BM], Z1[BM], Z2[BM], O[OCAP];
+  constexpr int OCAP = CN == 8 ? 4 * BM : BM;                        // staged B rows (chi3 not 8)
+  // Z1 rows (one per nh1) and Z2 rows (one per (nh1, nh2)) padded by one element: the threads of
+  // a wave that read one element of their own row each hit distinct LDS banks
+  __shared__ __attribute__((aligned(16))) MT X[BM], Z1[BM + CN], Z2[BM + CN * CN], O[OCAP];
   // U_j for every n_j as rows of CN (zero-padded): u_j[(n_j chi_j + m) CN + nh] = U_j[nh + chi_j m][n_j]
   __shared__ __attribute__((aligned(16))) MT u1s[CN * CN * CN], u2s[CN * CN * CN], u3s[CN * CN * CN];
   const int tid = threadIdx.x;
   const int h = blockIdx.x / dm.chic, cp = blockIdx.x % dm.chic;
   const int b = dm.b, c1 = dm.chi1, c2 = dm.chi2, c3 = dm.chi3, k1 = dm.k1, k2 = dm.k2, k3 = dm.k3;
   const int c23 = c2 * c3, c12 = c1 * c2;
+  const int z1s = c23 + 1, z2s = c3 + 1;                            // padded row lengths
   const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * sqrt((double)b)) : 1.0;
   const int rho = h / b, nc = h % b;
   for (int i = tid; i < b; i += 256) X[i] = T[(long)h * dm.H + (long)cp * b + i];
@@ -2940,12 +2943,15 @@ __global__ __launch_bounds__(256) void k_pstage4(const MT* __restrict__ T, const
   stage_u(u2s, U2, c2, k2);
   stage_u(u3s, U3, c3, k3);
   __syncthreads();
-  const int PB = max(1, min(256 / c12, OCAP / b));                  // pairs per batch of B rows
+  // chi3 = 8: each thread's eight outputs are one run of the B row (16-byte stores, 1 KiB per
+  // wave per plane); otherwise the rows of a batch of pairs go through LDS
+  const bool direct = c3 == 8;
+  const int PB = max(1, min(256 / c12, direct ? 256 : OCAP / b));   // pairs per batch of B rows
   int n1cur = -1;
   for (int pr = pr0; pr < pr1;) {
     const int n1 = pr / (k2 * k3), n2 = (pr / k3) % k2;
     const int pe = min(pr1, (n1 * k2 + n2 + 1) * k3);                // end of this (n1, n2) group
-    // the last group's reads of Z1 and Z2 ended before the barriers of its B batches
+    // the last group's reads of Z1 and Z2 ended before the barrier that closed it
     if (n1 != n1cur) {
       if (tid < c23) {                                               // column (nc2, nc3): all nh1
         MT acc[CN];
@@ -2959,7 +2965,7 @@ __global__ __launch_bounds__(256) void k_pstage4(const MT* __restrict__ T, const
         }
 #pragma unroll
         for (int e = 0; e < CN; ++e)
-          if (e < c1) Z1[e * c23 + tid] = acc[e];
+          if (e < c1) Z1[e * z1s + tid] = acc[e];
       }
       n1cur = n1;
       __syncthreads();
@@ -2970,58 +2976,64 @@ __global__ __launch_bounds__(256) void k_pstage4(const MT* __restrict__ T, const
 #pragma unroll
       for (int e = 0; e < CN; ++e) acc[e] = 0;
       for (int m = 0; m < c2; ++m) {
-        const MT z = Z1[(nh1 * c2 + m) * c3 + nc3];
+        const MT z = Z1[nh1 * z1s + m * c3 + nc3];
         const MT* u = &u2s[(n2 * c2 + m) * CN];
 #pragma unroll
         for (int e = 0; e < CN; ++e) acc[e] += u[e] * z;
       }
 #pragma unroll
       for (int e = 0; e < CN; ++e)
-        if (e < c2) Z2[(nh1 * c2 + e) * c3 + nc3] = acc[e];
+        if (e < c2) Z2[(nh1 * c2 + e) * z2s + nc3] = acc[e];
     }
+    __syncthreads();                                                 // Z2 complete
     for (int q0 = pr; q0 < pe; q0 += PB) {
       const int np = min(PB, pe - q0);
-      __syncthreads();                                               // Z2 complete / O consumed
-      {
-        const int ps = tid / c12, a = tid % c12;                     // pair q0 + ps, row (nh1, nh2)
-        if (ps < np) {
-          const int n3 = (q0 + ps) % k3;
-          MT acc[CN];
+      const int ps = tid / c12, a = tid % c12;                       // pair q0 + ps, row (nh1, nh2)
+      MT acc[CN];
 #pragma unroll
-          for (int e = 0; e < CN; ++e) acc[e] = 0;
-          for (int m = 0; m < c3; ++m) {
-            const MT z = Z2[a * c3 + m];
-            const MT* u = &u3s[(n3 * c3 + m) * CN];
+      for (int e = 0; e < CN; ++e) acc[e] = 0;
+      if (ps < np) {
+        const int n3 = (q0 + ps) % k3;
+        for (int m = 0; m < c3; ++m) {
+          const MT z = Z2[a * z2s + m];
+          const MT* u = &u3s[(n3 * c3 + m) * CN];
 #pragma unroll
-            for (int e = 0; e < CN; ++e) acc[e] += u[e] * z;
-          }
-#pragma unroll
-          for (int e = 0; e < CN; ++e)
-            if (e < c3) O[ps * b + a * c3 + e] = acc[e];
+          for (int e = 0; e < CN; ++e) acc[e] += u[e] * z;
         }
       }
-      __syncthreads();
       // row (q, c', nc) of B, columns rho b + i (Kp and b multiples of the vector width)
-      auto row_of = [&](int ps) { return (long)((q0 + ps - pr0) * dm.chic + cp) * b + nc; };
+      auto row_of = [&](int pq) { return (long)((q0 + pq - pr0) * dm.chic + cp) * b + nc; };
+      if (direct) {
+        if (ps < np) store_vec_scaled<F, 8>(B, row_of(ps) * ldb + (long)rho * b + a * 8, bplane, acc, sB);
+        continue;
+      }
+      __syncthreads();                                               // O consumed by the last batch
+      if (ps < np) {
+#pragma unroll
+        for (int e = 0; e < CN; ++e)
+          if (e < c3) O[ps * b + a * c3 + e] = acc[e];
+      }
+      __syncthreads();
       if (b % 8 == 0) {
         const int nv = b / 8;
         for (int v = tid; v < np * nv; v += 256) {
-          const int ps = v / nv, i = (v % nv) * 8;
-          store_vec_scaled<F, 8>(B, row_of(ps) * ldb + (long)rho * b + i, bplane, &O[ps * b + i], sB);
+          const int pq = v / nv, i = (v % nv) * 8;
+          store_vec_scaled<F, 8>(B, row_of(pq) * ldb + (long)rho * b + i, bplane, &O[pq * b + i], sB);
         }
       } else if (b % 4 == 0) {
         const int nv = b / 4;
         for (int v = tid; v < np * nv; v += 256) {
-          const int ps = v / nv, i = (v % nv) * 4;
-          store_vec_scaled<F, 4>(B, row_of(ps) * ldb + (long)rho * b + i, bplane, &O[ps * b + i], sB);
+          const int pq = v / nv, i = (v % nv) * 4;
+          store_vec_scaled<F, 4>(B, row_of(pq) * ldb + (long)rho * b + i, bplane, &O[pq * b + i], sB);
         }
       } else {
         for (int v = tid; v < np * b; v += 256) {
-          const int ps = v / b, i = v % b;
-          put_scaled<F>(B, row_of(ps) * ldb + (long)rho * b + i, bplane, O[ps * b + i], sB);
+          const int pq = v / b, i = v % b;
+          put_scaled<F>(B, row_of(pq) * ldb + (long)rho * b + i, bplane, O[pq * b + i], sB);
         }
       }
     }
+    __syncthreads();                                                 // Z2 (and O) read by every thread
     pr = pe;
   }
 }
