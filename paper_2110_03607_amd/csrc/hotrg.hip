@@ -487,12 +487,16 @@ void launch_gemm(const void* A, long lda, long aplane, const void* B, long ldb, 
     if (!small_tiles && Z == 1 && smult == 1.0 && Mp % GB_BM == 0 && Np % GB_BN == 0 && Kp % 64 == 0) {
       const int mt = (int)(Mp / GB_BM), nt = (int)(Np / GB_BN);
       constexpr int WAVES = 8;   // 2 waves per SIMD: one wave's LDS/barrier phase hides under the other's MFMAs
-      if (fuse)
-        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, true, gemm_sched<F>()>), dim3((unsigned)(mt * nt)),
+      if (fuse && fuse->mode == 2)
+        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, 2, gemm_sched<F>()>), dim3((unsigned)(mt * nt)),
+                           dim3(64 * WAVES), 0, s, (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B,
+                           ldb, bplane, (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, *fuse);
+      else if (fuse)
+        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, 1, gemm_sched<F>()>), dim3((unsigned)(mt * nt)),
                            dim3(64 * WAVES), 0, s, (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B,
                            ldb, bplane, (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, *fuse);
       else
-        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, false, gemm_sched<F>()>), dim3((unsigned)(mt * nt)),
+        hipLaunchKernelGGL((k_gemm_big<OpB, PL, WAVES, 0, gemm_sched<F>()>), dim3((unsigned)(mt * nt)),
                            dim3(64 * WAVES), 0, s, (const typename OpB::T*)A, lda, aplane, (const typename OpB::T*)B,
                            ldb, bplane, (float*)C, ldc, (int)Kp, mt, nt, scale_ptr, FuseArgs{});
       return;
@@ -763,6 +767,10 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     const bool fused12 = FormInfo<F>::fused_ok && ld.d == 3 && dm.chi1 == 12 && dm.chi2 == 12 && dm.k1 == 12 &&
                          dm.k2 == 12 && H % F12_T == 0 && ncols % F12_T == 0 && Kp % 64 == 0 &&
                          h->opts.chunk >= 0 && !h->no_fuse && !h->tune_small_tiles && !h->tune_no_f12;
+    // 4D chi = 8: the W3 and W2 contractions in the GEMM epilogue (a (c, g) block is 2 x 2 tiles)
+    const bool fused4 = FormInfo<F>::fused_ok && ld.d == 4 && dm.chi1 == 8 && dm.chi2 == 8 && dm.chi3 == 8 &&
+                        dm.k1 == 8 && dm.k2 == 8 && dm.k3 == 8 && H % GB_BM == 0 && ncols % GB_BN == 0 &&
+                        Kp % 64 == 0 && h->opts.chunk >= 0 && !h->no_fuse && !h->tune_small_tiles;
     FuseArgs fa{};
     if (fused || fused12) {
       fa.U1 = (const float*)U1;
@@ -771,13 +779,21 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
       fa.Hn = (long)dm.k1 * dm.k2 * dm.chic;
       fa.chic = dm.chic;
       fa.g0 = (int)(pr0 * dm.chic);
+      fa.mode = 1;
+    }
+    if (fused4) {
+      fa.U2 = (const float*)U2;
+      fa.U3 = (const float*)U3;
+      fa.W2 = h->at<float>(h->plan.off_W2);
+      fa.gcount = (int)((pr1 - pr0) * dm.chic);
+      fa.mode = 2;
     }
     hipEvent_t t1 = tmark(h);
     if (fused12)
       launch_gemm_f12<F>(Aop, Kp, aplane, Bop, Kp, bplane, H, ncols, Kp, sp, fa, h->s);
     else
       launch_gemm<F>(Aop, Kp, aplane, Bop, Kp, bplane, Cc, Np, 0, Mp, Np, Kp, 1, Kp, sp, 1.0, h->s,
-                     fused ? &fa : nullptr, h->tune_small_tiles);
+                     (fused || fused4) ? &fa : nullptr, h->tune_small_tiles);
     tclose(h, HOTRG_T_BOTTLENECK, t1);
     if (h->profiling) h->acc.flops_bottleneck += 2.0 * (double)H * (double)ncols * (double)H;
     if (fused || fused12) continue;
@@ -785,7 +801,10 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     const long ncell = (long)dm.chic * (pr1 - pr0) * dm.chic;   // (c, g) blocks
     const int g0 = (int)(pr0 * dm.chic), gcount = (int)((pr1 - pr0) * dm.chic);
     const dim3 gnc((unsigned)(dm.chic * gcount));
-    if (ld.d == 4) {
+    if (ld.d == 4 && fused4) {
+      hipLaunchKernelGGL((k_nstage4n<AT, MT, UT, 8>), gnc, dim3(256), 0, h->s, (const AT*)h->at<AT>(h->plan.off_W2),
+                         (const UT*)U1, dm, g0, gcount, Tn);
+    } else if (ld.d == 4) {
       AT* W2 = h->at<AT>(h->plan.off_W2);
       if (cn4_for(dm) == 8) {
         hipLaunchKernelGGL((k_nstage4w<AT, UT, 8>), gnc, dim3(256), 0, h->s, (const AT*)Cc, Np, (const UT*)U2,

@@ -471,10 +471,14 @@ __device__ inline void tile_of(int b, int mt, int nt, int& tm, int& tn) {
 // not written.
 struct FuseArgs {
   const float* U1;     // [(nh1 + 16 nc1) * 16 + n1]
-  const float* U2;     // [(nh2 + 16 nc2) * 16 + n2]
+  const float* U2;     // [(nh2 + 16 nc2) * 16 + n2]  (4D: [(nh2 + 8 nc2) * 8 + n2])
   float* Tn;           // renamed new tensor, row length Hn
   long Hn;
   int chic, g0;
+  int mode;            // 1: 3D chi = 16 (T^next written); 2: 4D chi = 8 (W2 written)
+  const float* U3;     // 4D: [(nh3 + 8 nc3) * 8 + n3]
+  float* W2;           // 4D: W2[(c, g)][(nh1, nc1)][(n2, n3)], g counted within the chunk
+  int gcount;          // 4D: g values in the chunk
 };
 
 // SCHED 0: register staging, one barrier per k-step.
@@ -482,7 +486,15 @@ struct FuseArgs {
 // each lane's 16 bytes land at the wave's LDS base + 16 lane), with no staging registers and no
 // LDS store instructions.  Lane l of a load fetches the global chunk that belongs at its LDS slot
 // (the XOR swizzle is applied to the global address instead of the LDS address).
-template <class Op, int PLANES, int WAVES, bool FUSE, int SCHED = 0>
+// FUSE 2: 4D with chi_1 = chi_2 = chi_3 = k_1 = k_2 = k_3 = 8.  A (c, g) block of C is 512 x 512
+// (rows (nh1, nh2, nh3), columns (nc1, nc2, nc3)), so a tile holds four nh1 and four nc1 values of
+// one block.  The epilogue stages each half of the tile (two nh1 values) in LDS and forms
+//   W3[(nh1, nh2, nc1, nc2)][n3] = sum_{nh3, nc3} C[..][..] U3[nh3 + 8 nc3][n3]   (a thread per item)
+//   W2[(nh1, nc1)][(n2, n3)] = sum_{nh2, nc2} U2[nh2 + 8 nc2][n2] W3[..][n3]      (a thread per output)
+// and writes W2; C is not written, and the U1 contraction follows in k_nstage4n.
+constexpr int F4_CTS = 260;                                             // padded LDS row of the half tile
+constexpr int F4_LDS = (128 * F4_CTS + 512 + 512 + 4096) * 4;           // epilogue bytes
+template <class Op, int PLANES, int WAVES, int FUSE, int SCHED = 0>
 __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
     const typename Op::T* __restrict__ A, long lda, long a_plane,
     const typename Op::T* __restrict__ B, long ldb, long b_plane,
@@ -494,7 +506,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
   constexpr int ES = sizeof(typename Op::T), CE = 16 / ES, BKE = 64 / ES;   // bytes, per chunk, per row
   constexpr int CH = 1024 / THREADS;                        // 16-byte chunks per thread, plane, operand
   constexpr int STAGE = PLANES * (GB_BM + GB_BN) * 64;     // bytes per stage
-  __shared__ __attribute__((aligned(16))) char lds[2 * STAGE];
+  constexpr int LDS_BYTES = (FUSE == 2 && F4_LDS > 2 * STAGE) ? F4_LDS : 2 * STAGE;
+  __shared__ __attribute__((aligned(16))) char lds[LDS_BYTES];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WNC, wn = wave % WNC;
   int tm, tn;
@@ -634,7 +647,64 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_big(
 #undef GB_LD1
 #undef GB_ST1
   const float sc = (float)(scale_ptr ? *scale_ptr : 1.0);
-  if constexpr (FUSE) {
+  if constexpr (FUSE == 2) {
+    static_assert(WAVES == 8 && WTN == 64, "4D epilogue written for 8 waves of 128 x 64");
+    float* Ct = (float*)lds;                 // half tile [(nh1 of the half, nh2, nh3)][(nc1, nc2, nc3)]
+    float* u3s = Ct + 128 * F4_CTS;          // [(nh3 * 8 + nc3) * 8 + n3]
+    float* u2s = u3s + 512;                  // [(nh2 * 8 + nc2) * 8 + n2]
+    float* w3s = u2s + 512;                  // [(nh1 of the half, nh2, nc1 of the tile, nc2)][n3]
+    for (int i = tid; i < 512; i += THREADS) {
+      const int n = i & 7, x = i >> 3, hi = x >> 3, ci = x & 7;
+      u3s[i] = fa.U3[(hi + 8 * ci) * 8 + n];
+      u2s[i] = fa.U2[(hi + 8 * ci) * 8 + n];
+    }
+    const int c = tm >> 1, g = tn >> 1, nh1b = (tm & 1) * 4, nc1b = (tn & 1) * 4;
+    for (int hh = 0; hh < 2; ++hh) {
+      __syncthreads();                       // U staged / the last half's reads of Ct and w3s done
+      if (wm == hh) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              Ct[(i * 16 + 4 * (lane >> 4) + r) * F4_CTS + wn * WTN + j * 16 + fr] = acc[i][j][r] * sc;
+      }
+      __syncthreads();
+      {
+        // item t = (nh1 of the half, nh2, nc1, nc2), nc2 fastest
+        const int nc2 = tid & 7, nc1l = (tid >> 3) & 3, nh2 = (tid >> 5) & 7, nh1l = tid >> 8;
+        float w[8];
+#pragma unroll
+        for (int n = 0; n < 8; ++n) w[n] = 0.f;
+        for (int nh3 = 0; nh3 < 8; ++nh3) {
+          const float* row = Ct + (nh1l * 64 + nh2 * 8 + nh3) * F4_CTS + nc1l * 64 + nc2 * 8;
+          const f4v r0 = *reinterpret_cast<const f4v*>(row), r1 = *reinterpret_cast<const f4v*>(row + 4);
+#pragma unroll
+          for (int nc3 = 0; nc3 < 8; ++nc3) {
+            const float v = nc3 < 4 ? r0[nc3] : r1[nc3 - 4];
+            const float* u = u3s + (nh3 * 8 + nc3) * 8;
+#pragma unroll
+            for (int n = 0; n < 8; ++n) w[n] += v * u[n];
+          }
+        }
+#pragma unroll
+        for (int n = 0; n < 8; ++n) w3s[tid * 8 + n] = w[n];
+      }
+      __syncthreads();
+      {
+        // output t = (nh1 of the half, nc1, n2, n3), n3 fastest
+        const int n3 = tid & 7, n2 = (tid >> 3) & 7, nc1l = (tid >> 6) & 3, nh1l = tid >> 8;
+        float sacc = 0.f;
+        for (int nh2 = 0; nh2 < 8; ++nh2)
+#pragma unroll
+          for (int nc2 = 0; nc2 < 8; ++nc2)
+            sacc += u2s[(nh2 * 8 + nc2) * 8 + n2] * w3s[(((nh1l * 8 + nh2) * 4 + nc1l) * 8 + nc2) * 8 + n3];
+        const int nh1 = nh1b + 2 * hh + nh1l, nc1 = nc1b + nc1l;
+        fa.W2[((long)(c * fa.gcount + g) * 64 + nh1 * 8 + nc1) * 64 + n2 * 8 + n3] = sacc;
+      }
+    }
+  } else if constexpr (FUSE == 1) {
     float* qs = (float*)lds;                 // Q[(nh1 * 16 + nc1) * 16 + n2]
     float* u1s = (float*)(lds + 16384);      // U1
     for (int i = tid; i < 4096; i += THREADS) u1s[i] = fa.U1[i];
