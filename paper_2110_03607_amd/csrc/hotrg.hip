@@ -749,7 +749,12 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     else if (ld.d == 3)
       hipLaunchKernelGGL((k_pstage3<MT, UT, F>), dim3((unsigned)H), dim3(256), 0, h->s, T, (const UT*)U1,
                          (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane, (const DevState*)st);
-    else
+    else if (ld.d == 2 && !h->scalar_prime && dm.chi1 <= 32 && (long)dm.chic * dm.b <= 1024) {
+      const int pbk = std::max(1, 256 / dm.chi1);
+      hipLaunchKernelGGL((k_pstage2r<MT, UT, F>), dim3((unsigned)H, (unsigned)((pr1 - pr0 + pbk - 1) / pbk)),
+                         dim3(256), 0, h->s, T, (const UT*)U1, dm, (int)pr0, (int)pr1, pbk, Bop, Kp, bplane,
+                         (const DevState*)st);
+    } else
       hipLaunchKernelGGL((k_pstage<MT, UT, F>), dim3((unsigned)(H * dm.chic)), dim3(256), 0, h->s, T,
                          (const UT*)U1, (const UT*)U2, dm, (int)pr0, (int)pr1, Bop, Kp, bplane,
                          (const DevState*)st);
@@ -833,6 +838,9 @@ int enqueue_contract_f(hotrg_handle* h, const void* Tv, void* Tnv, const LocalDi
     else if (ld.d == 3)
       hipLaunchKernelGGL((k_nstage3b<AT, MT, UT>), dim3((unsigned)(dm.chic * ((gcount + 7) / 8))), dim3(256), 0,
                          h->s, (const AT*)Cc, Np, (const UT*)U1, (const UT*)U2, dm, g0, gcount, Tn);
+    else if (dm.chi1 <= 32 && dm.k1 <= 32)
+      hipLaunchKernelGGL((k_nstage2g<AT, MT, UT>), dim3((unsigned)(dm.chic * ((gcount + NG2 - 1) / NG2))),
+                         dim3(256), 0, h->s, (const AT*)Cc, Np, (const UT*)U1, dm, g0, gcount, Tn);
     else
       hipLaunchKernelGGL((k_nstage2<AT, MT, UT>), dim3((unsigned)ncell), dim3(64), 0, h->s, (const AT*)Cc, Np,
                          (const UT*)U1, dm, g0, gcount, Tn);

@@ -2968,6 +2968,94 @@ __global__ __launch_bounds__(64) void k_nstage2(const AT* __restrict__ C, long l
 }
 
 // ---------------------------------------------------------------------------
+// 2D chains with the isometry held in registers (chi_c, chi_1, k_1 <= 32).
+//
+// Prime chain: workgroup (row h = (rho, nc) of the check copy, block of PBK pairs); the whole
+// row T[h][(c', nc1')] is staged in LDS.  Thread item (pair pr, nh1') holds the column
+// U1[nh1' + chi1 nc1'][pr] in registers and forms, for every c',
+//   B[(pr, c', nc)][rho b + nh1'] = sum_{nc1'} U1[nh1' + chi1 nc1'][pr] T[h][c' b + nc1']
+// (the T values are read at one LDS address across the wave; consecutive threads write
+// consecutive nh1').
+// ---------------------------------------------------------------------------
+template <class MT, class UT, int F>
+__global__ __launch_bounds__(256) void k_pstage2r(const MT* __restrict__ T, const UT* __restrict__ U1, Dims dm,
+                                                  int pr0, int pr1, int pbk, typename Store<F>::T* __restrict__ B,
+                                                  long ldb, long bplane, const DevState* __restrict__ st) {
+  __shared__ MT X[32 * 32];                                   // chi_c * chi_1 <= 1024
+  const int tid = threadIdx.x, h = blockIdx.x;
+  const int b = dm.b, chi1 = dm.chi1, chic = dm.chic, k1 = dm.k1;
+  const double sB = FormInfo<F>::fp16 ? fp16_scale_for(st->maxabs * sqrt((double)b)) : 1.0;
+  const int rho = h / b, nc = h % b;
+  for (int i = tid; i < chic * b; i += 256) X[i] = T[(long)h * dm.H + i];
+  __syncthreads();
+  const int q0 = pr0 + (int)blockIdx.y * pbk, q1 = min(pr1, q0 + pbk);
+  for (int it = tid; it < (q1 - q0) * chi1; it += 256) {
+    const int pr = q0 + it / chi1, nh1 = it % chi1;
+    MT u[32];
+#pragma unroll
+    for (int m = 0; m < 32; ++m) u[m] = m < chi1 ? (MT)U1[(nh1 + chi1 * m) * k1 + pr] : (MT)0;
+    for (int cp = 0; cp < chic; ++cp) {
+      const MT* x = &X[cp * b];
+      MT s = 0;
+#pragma unroll
+      for (int m = 0; m < 32; ++m)
+        if (m < chi1) s += u[m] * x[m];
+      const long row = (long)((pr - pr0) * chic + cp) * b + nc;
+      put_scaled<F>(B, row * ldb + (long)rho * b + nh1, bplane, s, sB);
+    }
+  }
+}
+
+// Non-prime chain (2D): workgroup (c, block of NG2 consecutive g); the chi1 x chi1 blocks of C
+// for those g are staged in LDS as [x = nh1 chi1 + nc1][g] (rows read straight from memory).
+// Thread (part p, n1) sums x in [p X/P, (p + 1) X/P) for all NG2 values of g at once (one U1
+// load per NG2 multiply-adds); the P partial sums are then added in part order:
+//   T^next[(n1, c)][g] = sum_{nh1, nc1} U1[nh1 + chi1 nc1][n1] C[(c, nh1)][(g, nc1)].
+// ---------------------------------------------------------------------------
+constexpr int NG2 = 8;
+template <class AT, class MT, class UT>
+__global__ __launch_bounds__(256) void k_nstage2g(const AT* __restrict__ C, long ldc, const UT* __restrict__ U1,
+                                                  Dims dm, int g0, int gcount, MT* __restrict__ Tn) {
+  __shared__ AT tiles[32 * 32 * NG2];                          // [x][g within the block]
+  __shared__ AT part[8 * 32 * NG2];                            // [p][n1][g]
+  const int tid = threadIdx.x;
+  const int ngb = (gcount + NG2 - 1) / NG2;
+  const int c = blockIdx.x / ngb, gb = (blockIdx.x % ngb) * NG2;
+  const int chi1 = dm.chi1, k1 = dm.k1, X = chi1 * chi1;
+  const int ng = min(NG2, gcount - gb);
+  const long Hn = (long)k1 * dm.chic;
+  for (int i = tid; i < X * NG2; i += 256) {
+    const int gi = i / X, x = i % X, nh1 = x / chi1, nc1 = x % chi1;   // consecutive threads: consecutive nc1
+    tiles[x * NG2 + gi] = gi < ng ? C[(long)(c * chi1 + nh1) * ldc + (long)(gb + gi) * chi1 + nc1] : (AT)0;
+  }
+  __syncthreads();
+  const int P = 256 / k1 < 8 ? 256 / k1 : 8;                  // parts of the x range
+  const int p = tid / k1, n1 = tid % k1;
+  if (p < P) {
+    const int xa = p * X / P, xb = (p + 1) * X / P;
+    AT acc[NG2];
+#pragma unroll
+    for (int gi = 0; gi < NG2; ++gi) acc[gi] = 0;
+    for (int x = xa; x < xb; ++x) {
+      const int nh1 = x / chi1, nc1 = x % chi1;
+      const AT u = (AT)U1[(nh1 + chi1 * nc1) * k1 + n1];
+      const AT* t = &tiles[x * NG2];
+#pragma unroll
+      for (int gi = 0; gi < NG2; ++gi) acc[gi] += u * t[gi];
+    }
+#pragma unroll
+    for (int gi = 0; gi < NG2; ++gi) part[(p * 32 + n1) * NG2 + gi] = acc[gi];
+  }
+  __syncthreads();
+  for (int o = tid; o < k1 * ng; o += 256) {
+    const int on1 = o / ng, gi = o % ng;
+    AT s = 0;
+    for (int q = 0; q < P; ++q) s += part[(q * 32 + on1) * NG2 + gi];
+    Tn[(long)(on1 * dm.chic + c) * Hn + g0 + gb + gi] = (MT)s;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // 4D contraction stages (Section 4.2.9 with three Next directions, eqs. TU1..TUNCD and
 // AfterBNNCD..AfterBN1).  CN is the register width of the kernels: every chi_j and k_j is at
 // most CN (8 or 12; chosen by the host from the dims).
