@@ -265,7 +265,9 @@ int hotrg_probe_mfma_rate(int precision, double* tflops, void* hip_stream);
  * batch * 2 * n^2 * 8 <= 16 MiB (n = 1024: batch 1; n <= 724: batch 2; n <= 512: batch 4).
  * Larger requests return HOTRG_E_ARG with nothing enqueued.  The call only enqueues work on
  * `hip_stream` (no allocation, no synchronisation): *status_dev (a device int) is set to 0 and
- * then to 1 if the decomposition failed (as hotrg_debug_eigh's HOTRG_E_NUMERIC).  All calls on
+ * then, if the decomposition failed (as hotrg_debug_eigh's HOTRG_E_NUMERIC), to the first cause
+ * found: 1 a non-finite entry, 2 an eigenvalue interval still open at the bisection's iteration
+ * cap, 3 an eigenpair residual above its bound.  All calls on
  * one device share the static array: calls that overlap on one device (different streams or
  * host threads without ordering between them) race and give undefined results.
  * Errors: HOTRG_E_ARG, HOTRG_E_DEVICE. */

@@ -1238,8 +1238,14 @@ int sync_state(hotrg_handle* h, DevState* out) {
   HIPCHK(h, hipMemcpy(out, h->st(), sizeof(DevState), hipMemcpyDeviceToHost));
   if (out->err) {
     h->failed = true;
-    return fail(h, HOTRG_E_NUMERIC, "numeric failure on the device (non-positive or non-finite trace, "
-                                    "or eigensolver without convergence)");
+    if (out->eig_fail == EIG_FAIL_NONFINITE)
+      return fail(h, HOTRG_E_NUMERIC, "numeric failure on the device: non-finite entry of a tridiagonal matrix");
+    if (out->eig_fail == EIG_FAIL_BISECT)
+      return fail(h, HOTRG_E_NUMERIC, "numeric failure on the device: eigenvalue interval still open at the "
+                                      "bisection's iteration cap");
+    if (out->eig_fail)
+      return fail(h, HOTRG_E_NUMERIC, "numeric failure on the device: eigenpair residual above its bound");
+    return fail(h, HOTRG_E_NUMERIC, "numeric failure on the device: non-positive or non-finite trace");
   }
   return HOTRG_OK;
 }

@@ -1163,7 +1163,7 @@ struct EigBatch {
   double* V[EIG_BATCH];
   double* scratch[EIG_BATCH];
   double* tail[EIG_BATCH];   // may be null: where the sum of the eigenvalues not resolved one by one goes
-  int* fail[EIG_BATCH];      // set to 1 when the decomposition failed (see eigh_tri_body); never cleared here
+  int* fail[EIG_BATCH];      // set to a failure code (EIG_FAIL_*, see eigh_tri_body); never cleared here
 };
 
 // zs -= sum_{j0 <= j < j1} (Z_j . zs) Z_j: all coefficients first (a wave per vector,
@@ -1197,7 +1197,7 @@ struct EigDesc {
   double* V;
   double* scratch;
   double* tail;   // may be null
-  int* fail;      // set to 1 on failure
+  int* fail;      // set to a failure code (EIG_FAIL_*) on failure
 };
 
 // LU with partial pivoting of the tridiagonal T - lam I (diagonal d, subdiagonal e), one
@@ -1281,10 +1281,12 @@ __host__ __device__ inline int eig_nev(int n, int kvec) {
 
 // tridiag_done: the tridiagonal form was built by k_tri_step (multi-workgroup, large n):
 // reflectors in R, diagonal and subdiagonal at Z[0, n) and Z[n, 2n).
-// *fail is set to 1 (and never cleared) when the tridiagonal matrix has a non-finite entry, when
-// an eigenvalue interval is still open after the bisection's iteration cap, or when a computed
-// eigenpair has a residual ||T z - lambda z||_2 above EIG_RES_TOL |T| (|z| = 1).
+// *fail is set once (the first cause wins; never cleared) to EIG_FAIL_NONFINITE when the tridiagonal matrix has a
+// non-finite entry, EIG_FAIL_BISECT when an eigenvalue interval is still open after the
+// bisection's iteration cap, EIG_FAIL_RESIDUAL when a computed eigenpair has a residual
+// ||T z - lambda z||_2 above EIG_RES_TOL |T| (|z| = 1).
 constexpr double EIG_RES_TOL = 1e-9;
+constexpr int EIG_FAIL_NONFINITE = 1, EIG_FAIL_BISECT = 2, EIG_FAIL_RESIDUAL = 3;
 __device__ __forceinline__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ A, double* __restrict__ w,
                               double* __restrict__ V, double* __restrict__ R, const bool tridiag_done,
                               double* __restrict__ tail_out, int* __restrict__ fail) {
@@ -1364,7 +1366,7 @@ __device__ __forceinline__ void eigh_tri_body(const int n, const int kvec, doubl
   {
     int bad = 0;
     for (int i = tid; i < n; i += nt) bad |= !isfinite(d[i]) || !isfinite(e[i]);
-    if (__syncthreads_or(bad) && tid == 0) *fail = 1;
+    if (__syncthreads_or(bad) && tid == 0) atomicCAS(fail, 0, EIG_FAIL_NONFINITE);
   }
 
   // ---- 2. eigenvalues by bisection (descending) -------------------------------
@@ -1436,7 +1438,7 @@ __device__ __forceinline__ void eigh_tri_body(const int n, const int kvec, doubl
         b = nb;
       }
     }
-    if (act && jl == 0 && !done) *fail = 1;   // interval still open at the iteration cap
+    if (act && jl == 0 && !done) atomicCAS(fail, 0, EIG_FAIL_BISECT);   // interval still open at the iteration cap
     if (act && jl == 0) w[idx] = 0.5 * (a + b);
   }
   __syncthreads();
@@ -1559,7 +1561,7 @@ __device__ __forceinline__ void eigh_tri_body(const int n, const int kvec, doubl
       rr += r * r;
     }
     for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
-    if (lane == 0 && !(sqrt(rr) <= EIG_RES_TOL * tnorm)) *fail = 1;
+    if (lane == 0 && !(sqrt(rr) <= EIG_RES_TOL * tnorm)) atomicCAS(fail, 0, EIG_FAIL_RESIDUAL);
   }
 
   // ---- 4. back-transformation: V[:, iv] = H_0 H_1 ... H_{n-3} z_iv -------------
@@ -1943,7 +1945,7 @@ __device__ __forceinline__ void eig_bisect_body(const int n, const int kvec, con
     e2[i] = e[i] * e[i];
     bad |= !isfinite(d[i]) || !isfinite(e[i]);
   }
-  if (__syncthreads_or(bad) && tid == 0 && blockIdx.x == 0) *fail = 1;
+  if (__syncthreads_or(bad) && tid == 0 && blockIdx.x == 0) atomicCAS(fail, 0, EIG_FAIL_NONFINITE);
   double lo, hi, tnorm;
   tri_bounds(d, e, n, red, lo, hi, tnorm);
   const double pivmin = fmax(1e-290, 2.2e-16 * 2.2e-16 * tnorm * tnorm);
@@ -1999,7 +2001,7 @@ __device__ __forceinline__ void eig_bisect_body(const int n, const int kvec, con
       b = nb;
     }
   }
-  if (act && jl == 0 && !done) *fail = 1;   // interval still open at the iteration cap
+  if (act && jl == 0 && !done) atomicCAS(fail, 0, EIG_FAIL_BISECT);   // interval still open at the iteration cap
   if (act && jl == 0) w[idx] = 0.5 * (a + b);
 }
 
@@ -2249,7 +2251,7 @@ __device__ __forceinline__ void eig_invit_body(const int n, const int kvec, doub
       rr += r * r;
     }
     for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
-    if (lane == 0 && !(sqrt(rr) <= EIG_RES_TOL * tnorm)) *fail = 1;
+    if (lane == 0 && !(sqrt(rr) <= EIG_RES_TOL * tnorm)) atomicCAS(fail, 0, EIG_FAIL_RESIDUAL);
   }
 }
 
