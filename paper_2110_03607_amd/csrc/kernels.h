@@ -1287,12 +1287,89 @@ __host__ __device__ inline int eig_nev(int n, int kvec) {
 // ||T z - lambda z||_2 above EIG_RES_TOL |T| (|z| = 1).
 constexpr double EIG_RES_TOL = 1e-9;
 constexpr int EIG_FAIL_NONFINITE = 1, EIG_FAIL_BISECT = 2, EIG_FAIL_RESIDUAL = 3;
+
+// Entry i of the deterministic zero-mean start vector of eigenvector iv.
+__device__ inline double eig_start_entry(int i, int iv) {
+  const unsigned hsh = (unsigned)(i + 1) * 2654435761u ^ (unsigned)(iv + 7) * 40503u;
+  return (double)(hsh & 0xFFFFu) / 32768.0 - 1.0;
+}
+
+// Repair of tridiagonal eigenvectors (rows of Z, unit length) whose residual exceeds the bound,
+// run after inverse iteration and before the final residual check.  Inverse iteration can miss
+// inside a cluster of eigenvalues at rounding level when the matrix has fewer non-negligible
+// eigenvalues than kept vectors: the shifts lie far below the pivot floor, the factorisation's
+// growth compounds over runs of tiny pivots in one block, every solve of the cluster grows the
+// same few directions (already held by earlier members), and Gram-Schmidt leaves rounding noise
+// with O(1e-4) weight on the leading eigenvectors.  Eigenvalues come in descending order, so when
+// w[iv] is at rounding level every later eigenvalue is too (for a positive semidefinite matrix
+// such as a Gram matrix): the orthogonal complement of vectors 0 .. iv-1 is then an invariant
+// subspace of near-zero eigenvalues, and any unit vector in it is an eigenvector to within
+// rounding.  A vector above the bound restarts from its start vector orthogonalised against
+// every earlier vector; the later members of its cluster are orthogonalised against the cluster
+// again.  Vectors are left untouched until the first one above the bound (no change at all when
+// none is), and the final check still decides.  zs: LDS vector of n; coef: kvec - 1 entries;
+// first_bad: an LDS int.
+__device__ inline void eig_repair(const double* d, const double* e, const int n, const int kvec,
+                                  const double* __restrict__ w, const double ortol, const double tnorm,
+                                  double* __restrict__ Z, double* zs, double* coef, double* red, int* first_bad) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+  const double bound = EIG_RES_TOL * tnorm;
+  if (tid == 0) *first_bad = kvec;
+  __syncthreads();
+  for (int iv = wv; iv < kvec; iv += nw) {             // a wave per vector
+    const double* z = Z + (long)iv * n;
+    const double lam = w[iv];
+    double rr = 0.0;
+    for (int i = lane; i < n; i += 64) {
+      double r = (d[i] - lam) * z[i];
+      if (i > 0) r += e[i - 1] * z[i - 1];
+      if (i + 1 < n) r += e[i] * z[i + 1];
+      rr += r * r;
+    }
+    for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o);
+    if (lane == 0 && !(sqrt(rr) <= bound)) atomicMin(first_bad, iv);
+  }
+  __syncthreads();
+  const int first = *first_bad;
+  int rc = -1;                                         // first member of the last repaired cluster
+  for (int iv = first; iv < kvec; ++iv) {              // uniform over the block
+    int j0 = iv;
+    while (j0 > 0 && fabs(w[j0 - 1] - w[iv]) <= ortol) --j0;
+    double* z = Z + (long)iv * n;
+    const double lam = w[iv];
+    double rr = 0.0;
+    for (int i = tid; i < n; i += nt) {
+      double r = (d[i] - lam) * z[i];
+      if (i > 0) r += e[i - 1] * z[i - 1];
+      if (i + 1 < n) r += e[i] * z[i + 1];
+      rr += r * r;
+    }
+    const bool bad = !(sqrt(block_sum(rr, red)) <= bound);
+    if (bad) {
+      rc = j0;
+      for (int i = tid; i < n; i += nt) zs[i] = eig_start_entry(i, iv);
+    } else if (j0 == rc) {
+      for (int i = tid; i < n; i += nt) zs[i] = z[i];
+    } else {
+      continue;
+    }
+    const int lo = bad ? 0 : j0;
+    cgs_cluster(zs, Z, n, lo, iv, coef, tid, nt, lane, wv, nw);
+    cgs_cluster(zs, Z, n, lo, iv, coef, tid, nt, lane, wv, nw);
+    double np = 0.0;
+    for (int i = tid; i < n; i += nt) np += zs[i] * zs[i];
+    const double inv = 1.0 / sqrt(block_sum(np, red));
+    for (int i = tid; i < n; i += nt) z[i] = zs[i] * inv;
+    __syncthreads();
+  }
+}
 __device__ __forceinline__ void eigh_tri_body(const int n, const int kvec, double* __restrict__ A, double* __restrict__ w,
                               double* __restrict__ V, double* __restrict__ R, const bool tridiag_done,
                               double* __restrict__ tail_out, int* __restrict__ fail) {
   __shared__ double d[EIG_MAXN], e[EIG_MAXN], vv[EIG_MAXN], qv[EIG_MAXN];
   __shared__ double red[EIG_THREADS / 64];
-  if (eig_split(n, kvec)) return;                       // k_eig_bisect, k_eig_invit and k_eig_backtr
+  __shared__ int first_bad;
+  if (eig_split(n, kvec)) return;                      // k_eig_bisect, k_eig_invit and k_eig_backtr
   double* Z = R + (long)n * n;                          // reflector k at R[k n ..]; tridiagonal eigenvector i at Z[i n ..)
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
 
@@ -1548,6 +1625,7 @@ __device__ __forceinline__ void eigh_tri_body(const int n, const int kvec, doubl
     __syncthreads();
   }
   __syncthreads();
+  eig_repair(d, e, n, kvec, w, ortol, tnorm, Z, zs, coef, red, &first_bad);
   // residual of every computed eigenpair of the tridiagonal matrix (a wave per vector); the
   // negated comparison also flags NaN
   for (int iv = wv; iv < kvec; iv += nw) {
@@ -2143,7 +2221,7 @@ __device__ __forceinline__ void eig_invit_body(const int n, const int kvec, doub
   __shared__ double d[EIG_MAXN], e[EIG_MAXN];
   __shared__ double ys[EI_LDS];
   __shared__ double red[2 * EI_THREADS / 64], coef[64];
-  __shared__ int j0s[64];
+  __shared__ int j0s[64], first_bad;
   double* Z = R + (long)n * n;                 // tridiagonal eigenvector iv at Z[iv n ..) at the end
   const int S = kvec;
   double* Y = (long)n * kvec <= EI_LDS ? ys : Z + (long)kvec * n;
@@ -2238,6 +2316,7 @@ __device__ __forceinline__ void eig_invit_body(const int n, const int kvec, doub
     Z[idx] = Y[(long)r * S + iv];
   }
   __syncthreads();
+  eig_repair(d, e, n, kvec, w, ortol, tnorm, Z, ys, coef, red, &first_bad);   // ys is free now
   // residual of every eigenpair of the tridiagonal matrix (a wave per vector); the negated
   // comparison also flags NaN
   for (int iv = wv; iv < kvec; iv += nw) {

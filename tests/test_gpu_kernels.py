@@ -276,6 +276,54 @@ def test_eigh_leading_vectors_match_library(n, kvec):
         assert sub < 100 * n * u * abs(ref[0]) / gap
 
 
+def _rank_deficient_gram(n, m, sectors, seed):
+    # Gram matrix of an ordered phase: `sectors` blocks of m indices (scattered over n), each a
+    # rank-one term of weight 1/sectors plus a tail of order 1e-20; every other entry exactly
+    # zero, so fewer eigenvalues than kept vectors are non-negligible
+    rng = np.random.default_rng(seed)
+    A = np.zeros((n, n))
+    idx = rng.permutation(n)
+    for s in range(sectors):
+        sec = idx[s * m:(s + 1) * m]
+        v = rng.standard_normal(m)
+        v /= np.linalg.norm(v)
+        tail = rng.standard_normal((m, m)) * 1e-10
+        A[np.ix_(sec, sec)] = np.outer(v, v) / sectors + tail @ tail.T
+    return 0.5 * (A + A.T)
+
+
+@pytest.mark.parametrize("n,kvec", [(256, 16), (576, 24), (120, 16)])
+def test_eigh_rank_deficient_gram(n, kvec):
+    """Fewer non-negligible eigenvalues than kept vectors (the Gram matrices of an ordered phase):
+    the kept vectors past the rank lie in the near-null space, where inverse iteration alone can
+    leave O(1e-4) weight on the leading eigenvectors; the solver must still return orthonormal
+    eigenvectors within the residual bound that span the non-negligible part.  (256, 16) and
+    (576, 24): the solver spread over many workgroups; (120, 16): the one-workgroup solver."""
+    u = 2.0 ** -52
+    cases = [(3, 1, 11), (4, 1, 12), (5, 1, 13), (4, 1, 14), (3, 2, 15), (5, 3, 16)]
+    for start in range(0, len(cases), 3):
+        part = cases[start:start + 3]
+        A = np.stack([_rank_deficient_gram(n, m, s, seed) for m, s, seed in part])
+        print(f"n={n} kvec={kvec} (m, sectors, seed) = {part}", flush=True)
+        w, tail, V = gu.eigh_lead(A.copy(), kvec)
+        nev = n if n <= 256 else max(kvec + 1, 24)
+        for b, (m, s, seed) in enumerate(part):
+            ref, Vr = np.linalg.eigh(A[b])
+            ref, Vr = ref[::-1], Vr[:, ::-1]
+            np.testing.assert_allclose(w[b, :nev], ref[:nev], rtol=0, atol=2 * n * u * abs(ref[0]))
+            rank = int(np.sum(ref > 1e-12 * ref[0]))
+            assert rank == s < kvec
+            res = np.linalg.norm(A[b] @ V[b] - V[b] * w[b, :kvec][None, :])
+            orth = np.linalg.norm(V[b].T @ V[b] - np.eye(kvec))
+            lead = Vr[:, :rank]
+            miss = np.linalg.norm(lead - V[b] @ (V[b].T @ lead))
+            print(f"  m={m} sectors={s} seed={seed}: residual {res:.1e}, orthogonality {orth:.1e}, "
+                  f"leading span missed {miss:.1e}")
+            assert res < 1e-13 * abs(ref[0]) * n
+            assert orth < 1e-13 * n
+            assert miss < 100 * n * u
+
+
 def _near_tridiagonal(n, eps, seed):
     rng = np.random.default_rng(seed)
     B = np.diag(2 + rng.random(n)) + np.diag(0.5 * rng.random(n - 1), 1)
