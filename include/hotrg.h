@@ -235,7 +235,11 @@ size_t hotrg_debug_eigh_workspace_bytes(int n, int batch);
  * A_dev is overwritten.  Errors: HOTRG_E_ARG, HOTRG_E_OOM, HOTRG_E_DEVICE, and
  * HOTRG_E_NUMERIC when the tridiagonal form has a non-finite entry, an eigenvalue is not
  * resolved within the bisection's iteration cap, or an eigenpair's residual
- * ||T z - lambda z|| exceeds 1e-9 |T| (the same failure makes hotrg_step's run fail). */
+ * ||T z - lambda z|| exceeds 1e-9 |T| (the same failure makes hotrg_step's run fail).  A vector
+ * that inverse iteration leaves above that bound is first rebuilt in the orthogonal complement of
+ * the earlier vectors, which is a near-null space when its eigenvalue lies at rounding level in a
+ * positive semidefinite matrix (a Gram matrix of lower rank than the kept count); the bound is
+ * then checked again. */
 int hotrg_debug_eigh(int n, int batch, double* A_dev, double* w_dev, double* V_dev,
                      void* workspace_dev, size_t workspace_bytes, void* hip_stream);
 
