@@ -1288,10 +1288,20 @@ __host__ __device__ inline int eig_nev(int n, int kvec) {
 constexpr double EIG_RES_TOL = 1e-9;
 constexpr int EIG_FAIL_NONFINITE = 1, EIG_FAIL_BISECT = 2, EIG_FAIL_RESIDUAL = 3;
 
-// Entry i of the deterministic zero-mean start vector of eigenvector iv.
+// Entry i of the restart vector of eigenvector iv in the repair below: the top 16 bits of the
+// MurmurHash3 32-bit finaliser of a key linear in (i, iv), mapped to [-1, 1).  The vectors of
+// different iv are independent: 256 of them at n = 256 have full rank.  (The start vectors of
+// inverse iteration take the low 16 bits of hash(i) XOR c(iv); XOR with a constant is affine in
+// the bits of hash(i), so all of them lie in one space of dimension 17, too few to restart the
+// members of a large near-null cluster.)
 __device__ inline double eig_start_entry(int i, int iv) {
-  const unsigned hsh = (unsigned)(i + 1) * 2654435761u ^ (unsigned)(iv + 7) * 40503u;
-  return (double)(hsh & 0xFFFFu) / 32768.0 - 1.0;
+  unsigned h = (unsigned)i * 0x9E3779B1u + (unsigned)(iv + 1) * 0x85EBCA77u;
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return (double)(h >> 16) / 32768.0 - 1.0;
 }
 
 // Repair of tridiagonal eigenvectors (rows of Z, unit length) whose residual exceeds the bound,
@@ -1304,9 +1314,9 @@ __device__ inline double eig_start_entry(int i, int iv) {
 // w[iv] is at rounding level every later eigenvalue is too (for a positive semidefinite matrix
 // such as a Gram matrix): the orthogonal complement of vectors 0 .. iv-1 is then an invariant
 // subspace of near-zero eigenvalues, and any unit vector in it is an eigenvector to within
-// rounding.  A vector above the bound restarts from its start vector orthogonalised against
-// every earlier vector; the later members of its cluster are orthogonalised against the cluster
-// again.  Vectors are left untouched until the first one above the bound (no change at all when
+// rounding.  A vector above the bound restarts from its restart vector (eig_start_entry)
+// orthogonalised against every earlier vector; the later members of its cluster are
+// orthogonalised against the cluster again.  Vectors are left untouched until the first one above the bound (no change at all when
 // none is), and the final check still decides.  zs: LDS vector of n; coef: kvec - 1 entries;
 // first_bad: an LDS int.
 __device__ inline void eig_repair(const double* d, const double* e, const int n, const int kvec,

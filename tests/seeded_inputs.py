@@ -38,6 +38,23 @@ CONFIG6 = dict(kind="ising", d=4, q=2, temps=(6.0, 6.68, 7.5), chi=4, steps=12)
 CONFIG7 = dict(kind="ising", d=4, q=2, temps=(6.68,), chi=5, steps=8)
 
 
+def rank_deficient_gram(n, m, sectors, seed):
+    """Symmetric positive semidefinite n x n matrix shaped like the Gram matrix of an ordered
+    phase: `sectors` blocks of m indices (scattered over n), each a rank-one term of weight
+    1/sectors plus a tail of order 1e-20; every other entry exactly zero, so only `sectors`
+    eigenvalues are non-negligible."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((n, n))
+    idx = rng.permutation(n)
+    for s in range(sectors):
+        sec = idx[s * m:(s + 1) * m]
+        v = rng.standard_normal(m)
+        v /= np.linalg.norm(v)
+        tail = rng.standard_normal((m, m)) * 1e-10
+        A[np.ix_(sec, sec)] = np.outer(v, v) / sectors + tail @ tail.T
+    return 0.5 * (A + A.T)
+
+
 def random_positive_tensor(shape, seed=0, spread=0.5):
     """Dense FP64 tensor with i.i.d. entries exp(spread * N(0, 1)) (all positive, so every
     trace of a network of copies is positive)."""

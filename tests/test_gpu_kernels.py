@@ -277,22 +277,6 @@ def test_eigh_leading_vectors_match_library(n, kvec):
         assert sub < 100 * n * u * abs(ref[0]) / gap
 
 
-def _rank_deficient_gram(n, m, sectors, seed):
-    # Gram matrix of an ordered phase: `sectors` blocks of m indices (scattered over n), each a
-    # rank-one term of weight 1/sectors plus a tail of order 1e-20; every other entry exactly
-    # zero, so fewer eigenvalues than kept vectors are non-negligible
-    rng = np.random.default_rng(seed)
-    A = np.zeros((n, n))
-    idx = rng.permutation(n)
-    for s in range(sectors):
-        sec = idx[s * m:(s + 1) * m]
-        v = rng.standard_normal(m)
-        v /= np.linalg.norm(v)
-        tail = rng.standard_normal((m, m)) * 1e-10
-        A[np.ix_(sec, sec)] = np.outer(v, v) / sectors + tail @ tail.T
-    return 0.5 * (A + A.T)
-
-
 @pytest.mark.parametrize("form", ["dense", "tridiagonal"])
 @pytest.mark.parametrize("n,kvec", [(256, 16), (576, 24), (120, 16)])
 def test_eigh_rank_deficient_gram(n, kvec, form):
@@ -311,7 +295,7 @@ def test_eigh_rank_deficient_gram(n, kvec, form):
     cases = [(3, 1, 11), (4, 1, 12), (5, 1, 13), (4, 1, 14), (3, 2, 15), (5, 3, 16), (4, 2, 17), (3, 1, 18)]
     for start in range(0, len(cases), 4):
         part = cases[start:start + 4]
-        A = np.stack([_rank_deficient_gram(n, m, s, seed) for m, s, seed in part])
+        A = np.stack([SI.rank_deficient_gram(n, m, s, seed) for m, s, seed in part])
         if form == "tridiagonal":
             for b in range(len(part)):
                 H = scipy.linalg.hessenberg(A[b])

@@ -5,6 +5,7 @@ contents still in the static array), a rejected oversize request, and the failur
 
 import numpy as np
 import pytest
+import scipy.linalg
 
 from tests import seeded_inputs as SI
 
@@ -75,3 +76,36 @@ def test_noalloc_reports_failure_in_status():
     w, _, status = _noalloc(A.copy())
     assert status == 0
     np.testing.assert_allclose(w[0], np.sort(np.linalg.eigvalsh(A[0]))[::-1], atol=1e-14)
+
+
+def _tridiagonal_form(A):
+    H = scipy.linalg.hessenberg(A)
+    d, e = np.diag(H), np.diag(H, -1)
+    return np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+
+
+def test_noalloc_rank_deficient_gram():
+    """Every eigenvector of matrices of rank 1 and 2 at n = 256 (tridiagonal forms of ordered-phase
+    Gram matrices, with near-null clusters of 254 and 255 vectors): status 0, the same bits as the
+    workspace entry point, and the solver's own bounds: every residual within 1e-9 |T|, and so
+    every overlap with the non-negligible eigenvectors within 1e-9 |T| / gap per residual.  The
+    first matrix is one on which the full solver reported a numeric failure before vectors above
+    the residual bound were rebuilt."""
+    n, u = 256, 2.0 ** -52
+    A = np.stack([_tridiagonal_form(SI.rank_deficient_gram(n, m, s, seed)) for m, s, seed in ((5, 1, 13), (4, 2, 17))])
+    w_ref, V_ref = gu.eigh(A.copy())
+    w, V, status = _noalloc(A.copy())
+    assert status == 0
+    np.testing.assert_array_equal(w, w_ref)
+    np.testing.assert_array_equal(V, V_ref)
+    for b, rank in enumerate((1, 2)):
+        ref = np.sort(np.linalg.eigvalsh(A[b]))[::-1]
+        np.testing.assert_allclose(w[b], ref, rtol=0, atol=2 * n * u * abs(ref[0]))
+        tnorm = np.abs(np.diag(A[b])).max() + 2 * np.abs(np.diag(A[b], -1)).max()
+        res = np.linalg.norm(A[b] @ V[b] - V[b] * w[b][None, :], axis=0)
+        orth = np.abs(V[b].T @ V[b] - np.eye(n))
+        gap = ref[rank - 1]
+        print(f"matrix {b}: max residual {res.max():.1e} (bound {1e-9 * tnorm:.1e}), max overlap {orth.max():.1e} "
+              f"(bound {2e-9 * tnorm / gap:.1e})")
+        assert res.max() <= 1e-9 * tnorm
+        assert orth.max() <= 2e-9 * tnorm / gap + 1e-12
